@@ -1,0 +1,210 @@
+"""FP64 CPU oracle for periodic cubic-spline particle tracking.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers.  The GPU product path never
+imports this package.  The arithmetic lives in ``pt_oracle.c`` (plain C, FP64,
+OpenMP over lines and particles); this module only marshals numpy arrays.
+
+Parity with the paper itself is unpinned: the paper prints no interpolated
+values, coefficients or trajectories.  Every function here is instead pinned by
+the tests against closed forms, dense linear algebra, brute-force sums over all
+basis functions and convergence rates (see tests/test_oracle_*.py).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "_pt_oracle.so")
+_lib = None
+
+OK = 0
+ERR_SIZE = -2
+ERR_NONFINITE = -5
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(_SO)
+        i32, i64, dbl, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        lib.oracle_num_threads.restype = i32
+        lib.oracle_solve_line.argtypes = [i32, vp, vp]
+        lib.oracle_spline_coeffs.argtypes = [i32, i32, i32, vp, vp]
+        lib.oracle_cell_keys.argtypes = [i32, i32, i32, dbl, dbl, dbl, i32, i32, i64,
+                                         vp, vp, vp, vp]
+        lib.oracle_stable_sort.argtypes = [i64, vp, vp]
+        lib.oracle_stable_sort.restype = None
+        lib.oracle_interp.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, vp, i32, vp]
+        lib.oracle_rk2_step.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, dbl, vp]
+        lib.oracle_interp_bwd.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, vp, vp,
+                                          vp, vp]
+        lib.oracle_spline_coeffs_bwd.argtypes = [i32, i32, i32, vp, vp]
+        lib.oracle_rk2_step_bwd.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, dbl,
+                                            vp, vp, vp]
+        for name in ("oracle_solve_line", "oracle_spline_coeffs", "oracle_cell_keys",
+                     "oracle_interp", "oracle_rk2_step", "oracle_interp_bwd",
+                     "oracle_spline_coeffs_bwd", "oracle_rk2_step_bwd"):
+            getattr(lib, name).restype = i32
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _chk(rc):
+    if rc != OK:
+        raise OracleError(f"oracle status {rc}")
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+class Grid:
+    """Periodic box: n = (nx, ny, nz) points, lengths L = (lx, ly, lz)."""
+
+    def __init__(self, nx, ny=None, nz=None, lx=2 * np.pi, ly=None, lz=None):
+        self.nx, self.ny, self.nz = nx, ny or nx, nz or nx
+        self.lx, self.ly, self.lz = lx, ly or lx, lz or lx
+
+    @property
+    def args(self):
+        return (self.nx, self.ny, self.nz, self.lx, self.ly, self.lz)
+
+    @property
+    def padded_shape(self):
+        return (3, self.nz + 3, self.ny + 3, self.nx + 3)
+
+
+def solve_line(g):
+    """Periodic (S[m-1] + 4 S[m] + S[m+1]) / 6 = g[m] along one line."""
+    g = _f64(g)
+    s = np.empty_like(g)
+    _chk(_load().oracle_solve_line(g.size, _ptr(g), _ptr(s)))
+    return s
+
+
+def spline_coeffs(field):
+    """field [3][nz][ny][nx] -> padded coefficients [3][nz+3][ny+3][nx+3]."""
+    field = _f64(field)
+    _, nz, ny, nx = field.shape
+    out = np.empty((3, nz + 3, ny + 3, nx + 3), dtype=np.float64)
+    _chk(_load().oracle_spline_coeffs(nx, ny, nz, _ptr(field), _ptr(out)))
+    return out
+
+
+def cell_keys(grid, pos, tile_x, tile_y):
+    """Return (cells int32 [3][np], t float64 [3][np], key uint64 [np])."""
+    pos = _f64(pos)
+    np_ = pos.shape[1]
+    cells = np.empty((3, np_), dtype=np.int32)
+    t = np.empty((3, np_), dtype=np.float64)
+    key = np.empty(np_, dtype=np.uint64)
+    _chk(_load().oracle_cell_keys(*grid.args, tile_x, tile_y, np_, _ptr(pos), _ptr(cells),
+                                  _ptr(t), _ptr(key)))
+    return cells, t, key
+
+
+def stable_sort(key):
+    """perm such that key[perm] is non-decreasing, ties in input order."""
+    key = np.ascontiguousarray(key, dtype=np.uint64)
+    perm = np.empty(key.size, dtype=np.int32)
+    _load().oracle_stable_sort(key.size, _ptr(key), _ptr(perm))
+    return perm
+
+
+def sort_particles(grid, pos, tile_x, tile_y):
+    """Stable sort of particles by cell key: (pos_sorted, perm, key_sorted)."""
+    _, _, key = cell_keys(grid, pos, tile_x, tile_y)
+    perm = stable_sort(key)
+    return np.ascontiguousarray(pos[:, perm]), perm, key[perm]
+
+
+def interp(grid, coeff, pos, n_out=3):
+    """(u,v,w) [3][np] or (u,v,w, du_i/dx_j) [12][np] at the positions."""
+    coeff, pos = _f64(coeff), _f64(pos)
+    np_ = pos.shape[1]
+    out = np.empty((n_out, np_), dtype=np.float64)
+    _chk(_load().oracle_interp(*grid.args, _ptr(coeff), np_, _ptr(pos), n_out, _ptr(out)))
+    return out
+
+
+def rk2_step(grid, coeff, pos, dt):
+    """One Heun step of dx/dt = u(x); returns new positions (unwrapped)."""
+    coeff = _f64(coeff)
+    p = _f64(pos).copy()
+    _chk(_load().oracle_rk2_step(*grid.args, _ptr(coeff), p.shape[1], dt, _ptr(p)))
+    return p
+
+
+def interp_bwd(grid, coeff, pos, gout, want_pos=True, want_coeff=True):
+    coeff, pos, gout = _f64(coeff), _f64(pos), _f64(gout)
+    gpos = np.zeros_like(pos) if want_pos else None
+    gcoeff = np.zeros_like(coeff) if want_coeff else None
+    _chk(_load().oracle_interp_bwd(*grid.args, _ptr(coeff), pos.shape[1], _ptr(pos),
+                                   _ptr(gout), _ptr(gpos), _ptr(gcoeff)))
+    return gpos, gcoeff
+
+
+def spline_coeffs_bwd(gcoeff):
+    """Adjoint of spline_coeffs: padded gradient -> field gradient."""
+    gcoeff = _f64(gcoeff)
+    _, pz, py, px = gcoeff.shape
+    out = np.empty((3, pz - 3, py - 3, px - 3), dtype=np.float64)
+    _chk(_load().oracle_spline_coeffs_bwd(px - 3, py - 3, pz - 3, _ptr(gcoeff), _ptr(out)))
+    return out
+
+
+def rk2_step_bwd(grid, coeff, pos_n, dt, lam, gcoeff=None):
+    """Adjoint of one Heun step: returns (dL/dx^n, gcoeff accumulated)."""
+    coeff, pos_n = _f64(coeff), _f64(pos_n)
+    g = _f64(lam).copy()
+    _chk(_load().oracle_rk2_step_bwd(*grid.args, _ptr(coeff), pos_n.shape[1], dt,
+                                     _ptr(pos_n), _ptr(g), _ptr(gcoeff)))
+    return g, gcoeff
+
+
+def advect(grid, coeff, pos, dt, steps, tile_x=None, tile_y=None):
+    """K Heun steps.  With tile sizes given, the particles are re-sorted by
+    cell key before every step (as the GPU path does); returns
+    (final positions, ids) where ids[i] is the input index of particle i."""
+    p = _f64(pos).copy()
+    ids = np.arange(p.shape[1], dtype=np.int64)
+    for _ in range(steps):
+        if tile_x is not None:
+            p, perm, _ = sort_particles(grid, p, tile_x, tile_y)
+            ids = ids[perm]
+        p = rk2_step(grid, coeff, p, dt)
+    return p, ids
+
+
+def loss_and_grads(grid, field, pos0, dt, steps):
+    """L = sum |x(K)|^2 after K Heun steps (no sort: the loss is
+    order-independent); returns (L, dL/dpos0, dL/dfield) by the hand adjoint."""
+    coeff = spline_coeffs(field)
+    traj = [_f64(pos0).copy()]
+    for _ in range(steps):
+        traj.append(rk2_step(grid, coeff, traj[-1], dt))
+    xk = traj[-1]
+    loss = float(np.sum(xk * xk))
+    lam = 2.0 * xk
+    gcoeff = np.zeros_like(coeff)
+    for k in range(steps - 1, -1, -1):
+        lam, gcoeff = rk2_step_bwd(grid, coeff, traj[k], dt, lam, gcoeff)
+    gfield = spline_coeffs_bwd(gcoeff)
+    return loss, lam, gfield
