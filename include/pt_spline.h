@@ -1,0 +1,198 @@
+/*
+ * pt_spline.h - C ABI of the MI355X (gfx950) periodic cubic-spline particle
+ * tracking library.
+ *
+ * The library implements, on one GPU, the per-step path of the particle
+ * tracking method of Buaria & Yeung (Comput. Phys. Commun., "A highly scalable
+ * particle tracking algorithm using partitioned global address space (PGAS)
+ * programming for extreme-scale turbulence simulations"):
+ *   Operation 1 of Sec. 2.2  - cubic-spline coefficients of a periodic field,
+ *                              one periodic tridiagonal solve per axis;
+ *   Sec. 3                   - particles ordered by the spline cell that
+ *                              holds them (the one-device counterpart of the
+ *                              paper's position-based particle-to-process
+ *                              mapping), as a stable radix sort;
+ *   Operations 2 and 3       - basis functions and the 64-term sum of
+ *     of Sec. 2.2              eq. (spline), for (u,v,w) and for the nine
+ *                              velocity gradients;
+ *   eq. (dxdt), Sec. 4.3     - explicit second-order Runge-Kutta advance of
+ *                              the particle positions;
+ * plus hand-written adjoints of each of these (not in the paper).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers owned by the caller.  No entry
+ *    point allocates device memory; scratch space is passed in as a workspace
+ *    whose size is given by pt_workspace_bytes().  The library keeps, per
+ *    device, one 4-byte error flag in its own static device memory.
+ *  - Arrays are dense, C order, x the fastest index:
+ *      field   float [3][nz][ny][nx]           grid values of (u, v, w)
+ *      coeff   [3][nz+3][ny+3][nx+3]           padded spline coefficients,
+ *              float (PT_F32) or bfloat16 bits (PT_BF16); along every axis the
+ *              padded index P holds the coefficient of grid line (P-1) mod n,
+ *              i.e. the index range 1..N+3 of eq. (spline) shifted to 0-based
+ *      pos     double [3][np]                  positions x, y, z, unwrapped
+ *  - Every call validates its arguments on the host before launching anything
+ *    and returns a pt_status; no exception crosses the ABI.  Work is enqueued
+ *    asynchronously on `stream` (0 = the null stream).  HIP launch failures
+ *    return PT_ERR_HIP.  A kernel that meets a non-finite position treats it
+ *    as the origin, finishes, and raises the device error flag that
+ *    pt_last_device_error() reports.
+ *  - Gradient outputs named g_* ACCUMULATE (+=) into caller-initialised
+ *    buffers, except pt_spline_coeffs_bwd, which overwrites g_field.
+ *  - Grid sizes: 4 <= n <= 8192 per axis; np < 2^31.
+ */
+#ifndef PT_SPLINE_H
+#define PT_SPLINE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PT_OK = 0,
+  PT_ERR_NULL = -1,        /* a required pointer is NULL */
+  PT_ERR_SIZE = -2,        /* grid size, particle count or box length invalid */
+  PT_ERR_DTYPE = -3,       /* unknown coefficient dtype */
+  PT_ERR_WORKSPACE = -4,   /* workspace NULL or smaller than required */
+  PT_ERR_NONFINITE = -5,   /* a kernel met a NaN or infinite position */
+  PT_ERR_HIP = -6,         /* a HIP runtime call or launch failed */
+  PT_ERR_UNSUPPORTED = -7, /* valid but not supported (e.g. n > 8192) */
+  PT_ERR_ARG = -8          /* other invalid argument (bad op code, dt) */
+} pt_status;
+
+/* Storage type of the spline coefficients.  Arithmetic is FP32 for both. */
+typedef enum { PT_F32 = 0, PT_BF16 = 1 } pt_dtype;
+
+/* Periodic box [0,lx) x [0,ly) x [0,lz) sampled at nx*ny*nz points with
+ * uniform spacing lx/nx, ly/ny, lz/nz (Sec. 2.2). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double lx, ly, lz;
+} pt_grid;
+
+/* Operation codes for pt_workspace_bytes. */
+enum {
+  PT_OP_SPLINE = 0,     /* pt_spline_coeffs */
+  PT_OP_SORT = 1,       /* pt_sort_particles */
+  PT_OP_RK2 = 2,        /* pt_rk2_step (with or without sort) */
+  PT_OP_SPLINE_BWD = 3, /* pt_spline_coeffs_bwd */
+  PT_OP_RK2_BWD = 4     /* pt_rk2_step_bwd (with or without sort) */
+};
+
+/* Bytes of workspace the operation needs for this grid, coefficient dtype
+ * and particle count (np ignored for the spline operations).  The result is a
+ * multiple of 256.  Returns PT_ERR_ARG for an unknown op. */
+pt_status pt_workspace_bytes(int op, const pt_grid *grid, pt_dtype dtype, int64_t np,
+                             size_t *bytes);
+
+/* Layout of the particle sort key (see pt_sort_particles): cells are grouped
+ * in columns of tile_x * tile_y cells in the (x, y) plane, running the full
+ * height in z; key_bits is the number of significant key bits for this grid.
+ * With a = alpha, b = beta, g = gamma (0-based cell indices):
+ *   key = (((b/ty * ceil(nx/tx) + a/tx) * nz + g) * ty + b%ty) * tx + a%tx. */
+pt_status pt_key_layout(const pt_grid *grid, int32_t *tile_x, int32_t *tile_y,
+                        int32_t *key_bits);
+
+/* Operation 1 (Sec. 2.2): spline coefficients of the three components.
+ * Along every grid line of every axis the coefficients S solve the periodic
+ * tridiagonal system (S[m-1] + 4 S[m] + S[m+1]) / 6 = g[m], m = 0..n-1
+ * (indices mod n), so that the tensor-product cubic B-spline with
+ * coefficients S interpolates the grid values exactly.  Axes are solved in
+ * the paper's order x, z, y; the last pass writes the padded layout (rounded
+ * to nearest-even for PT_BF16).
+ *   field  in   float [3][nz][ny][nx]
+ *   coeff  out  [3][nz+3][ny+3][nx+3] of `dtype`; must not overlap field
+ *   ws          >= pt_workspace_bytes(PT_OP_SPLINE, ...) bytes */
+pt_status pt_spline_coeffs(const pt_grid *grid, const float *field, void *coeff,
+                           pt_dtype dtype, void *ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* Sec. 2.2 and Sec. 3: map each position to its cell and order particles by
+ * cell.  Per axis, in double precision with no fused operations,
+ *   s = x * (n / L);  s_w = s - n floor(s / n), then +n if s_w < 0 and -n if
+ *   s_w >= n;  alpha = floor(s_w),  t = s_w - alpha in [0, 1)
+ * (the shadow position inside the primary domain).  The key is the one given
+ * at pt_key_layout; the sort is a stable LSD radix sort, so particles with
+ * equal keys keep their input order.
+ *   pos         in   double [3][np]
+ *   pos_sorted  out  double [3][np], pos_sorted[d][i] = pos[d][perm[i]]
+ *                    (may be NULL); must not overlap pos
+ *   perm        out  int32 [np], original index of sorted particle i
+ *   keys_out    out  uint64 [np] sorted keys (may be NULL)
+ *   ws               >= pt_workspace_bytes(PT_OP_SORT, ...) bytes */
+pt_status pt_sort_particles(const pt_grid *grid, int64_t np, const double *pos,
+                            double *pos_sorted, int32_t *perm, uint64_t *keys_out,
+                            void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Operations 2 and 3 of Sec. 2.2, eq. (spline): at every particle
+ *   g+ = sum_{k,j,i=1..4} b_i(x') c_j(y') d_k(z') S[gamma+k-2][beta+j-2][alpha+i-2]
+ * with the cubic B-spline pieces as basis functions, in FP32.
+ *   coeff  in   padded coefficients of `dtype`
+ *   pos    in   double [3][np] (any order; sorted order is fastest)
+ *   out    out  float [3][np] = (u, v, w) */
+pt_status pt_interp_uvw(const pt_grid *grid, const void *coeff, pt_dtype dtype,
+                        int64_t np, const double *pos, float *out, hipStream_t stream);
+
+/* As pt_interp_uvw, plus the nine velocity gradients from the derivatives of
+ * the basis functions (Sec. 2.2: the splines are twice differentiable):
+ *   out  float [12][np]: u, v, w, then du_i/dx_j at row 3 + 3 i + j. */
+pt_status pt_interp_grad(const pt_grid *grid, const void *coeff, pt_dtype dtype,
+                         int64_t np, const double *pos, float *out, hipStream_t stream);
+
+/* One RK2 step of dx/dt = u(x) (eq. (dxdt)), Heun's form:
+ *   u0 = u(x);  x* = x + dt u0;  u1 = u(x*);  x <- x + dt/2 (u0 + u1),
+ * velocities from the spline (FP32), positions in FP64, stored unwrapped.
+ * If sort != 0 the particles are first re-ordered as by pt_sort_particles and
+ * pos (and ids, if not NULL) come back in the new order.
+ *   pos  in/out double [3][np];  ids  in/out int32 [np] or NULL
+ *   ws          >= pt_workspace_bytes(PT_OP_RK2, ...) bytes */
+pt_status pt_rk2_step(const pt_grid *grid, const void *coeff, pt_dtype dtype,
+                      int64_t np, double dt, double *pos, int32_t *ids, int sort,
+                      void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of pt_interp_uvw (not in the paper).  With gu = dL/d(u,v,w):
+ *   g_pos[d][p]  += sum_c gu[c][p] du_c/dx_d (p)          (may be NULL)
+ *   g_coeff[c][.] += b_i c_j d_k gu[c][p] over each stencil (may be NULL),
+ * g_coeff is FP32 in the padded layout whatever the coefficient dtype (a
+ * BF16 coefficient is treated as its FP32 value: straight-through).  The
+ * scatter uses FP32 atomics, so its summation order is not fixed. */
+pt_status pt_interp_uvw_bwd(const pt_grid *grid, const void *coeff, pt_dtype dtype,
+                            int64_t np, const double *pos, const float *g_out,
+                            double *g_pos, float *g_coeff, hipStream_t stream);
+
+/* Adjoint of pt_spline_coeffs.  Each padded coefficient gradient is folded
+ * onto the grid line it copies, then the transposed line solves are applied
+ * (the 1-4-1 periodic matrix is symmetric, so they are the same solves) in the
+ * order y, z, x.  g_coeff float [3][nz+3][ny+3][nx+3] in (not modified);
+ * g_field float [3][nz][ny][nx] out (overwritten). */
+pt_status pt_spline_coeffs_bwd(const pt_grid *grid, const float *g_coeff, float *g_field,
+                               void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of one pt_rk2_step.  pos_n: the positions the step started from
+ * (in the step's input order); sort: as given to the forward step.
+ * g_pos: on entry dL/d(output positions) in the step's output order, on exit
+ * dL/d(pos_n) in the input order.  g_coeff (may be NULL) accumulates dL/dS.
+ *   x*b = J(x*)^T (dt/2) lam;  u0b = dt/2 lam + dt x*b;
+ *   x^n b = lam + x*b + J(x^n)^T u0b;  g_coeff += W(x*)^T (dt/2) lam + W(x^n)^T u0b. */
+pt_status pt_rk2_step_bwd(const pt_grid *grid, const void *coeff, pt_dtype dtype,
+                          int64_t np, double dt, const double *pos_n, int sort,
+                          double *g_pos, float *g_coeff, void *ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Synchronises `stream`, then returns PT_ERR_NONFINITE if any kernel on the
+ * current device met a non-finite position since the previous call (and
+ * clears the flag), PT_ERR_HIP on a runtime error, else PT_OK. */
+pt_status pt_last_device_error(hipStream_t stream);
+
+/* Static description of a status code. */
+const char *pt_status_string(pt_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PT_SPLINE_H */

@@ -1,0 +1,237 @@
+"""ctypes binding of libpt_spline.so (argument marshalling only).
+
+Every function named pt_* here calls the C entry point of the same name in
+include/pt_spline.h with the device pointers of the given torch tensors and
+the current HIP stream; all arithmetic runs in the library's kernels.  A
+missing library raises at import time: there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpt_spline.so")
+
+PT_OK = 0
+PT_ERR_NULL = -1
+PT_ERR_SIZE = -2
+PT_ERR_DTYPE = -3
+PT_ERR_WORKSPACE = -4
+PT_ERR_NONFINITE = -5
+PT_ERR_HIP = -6
+PT_ERR_UNSUPPORTED = -7
+PT_ERR_ARG = -8
+
+PT_F32 = 0
+PT_BF16 = 1
+
+PT_OP_SPLINE = 0
+PT_OP_SORT = 1
+PT_OP_RK2 = 2
+PT_OP_SPLINE_BWD = 3
+PT_OP_RK2_BWD = 4
+
+EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_sort_particles",
+           "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_interp_uvw_bwd",
+           "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
+           "pt_status_string")
+
+
+class PtGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double)]
+
+
+class PtError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2005_13193_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                             ctypes.c_size_t)
+    g = ctypes.POINTER(PtGrid)
+    sig = {
+        "pt_workspace_bytes": [ctypes.c_int, g, ctypes.c_int, i64, ctypes.POINTER(sz)],
+        "pt_key_layout": [g, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "pt_spline_coeffs": [g, vp, vp, ctypes.c_int, vp, sz, vp],
+        "pt_sort_particles": [g, i64, vp, vp, vp, vp, vp, sz, vp],
+        "pt_interp_uvw": [g, vp, ctypes.c_int, i64, vp, vp, vp],
+        "pt_interp_grad": [g, vp, ctypes.c_int, i64, vp, vp, vp],
+        "pt_rk2_step": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
+        "pt_interp_uvw_bwd": [g, vp, ctypes.c_int, i64, vp, vp, vp, vp, vp],
+        "pt_spline_coeffs_bwd": [g, vp, vp, vp, sz, vp],
+        "pt_rk2_step_bwd": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp, vp, vp, sz,
+                            vp],
+        "pt_last_device_error": [vp],
+        "pt_status_string": [ctypes.c_int],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.pt_status_string.restype = ctypes.c_char_p
+    return lib
+
+
+LIB = _load()
+
+
+def status_string(status):
+    return LIB.pt_status_string(status).decode()
+
+
+def _check(fn, status):
+    if status != PT_OK:
+        raise PtError(fn, status, status_string(status))
+
+
+def _grid(grid):
+    if isinstance(grid, PtGrid):
+        return grid
+    return PtGrid(*grid.nxyz, *grid.lxyz)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(coeff):
+    if coeff.dtype == torch.float32:
+        return PT_F32
+    if coeff.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return PT_BF16
+    raise TypeError(f"coefficients must be float32 or bfloat16, got {coeff.dtype}")
+
+
+def _need(t, dtype, shape=None, name="tensor"):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+# ----------------------------------------------------------- raw entries ---
+
+def pt_workspace_bytes(op, grid, dtype_code, np_):
+    out = ctypes.c_size_t(0)
+    _check("pt_workspace_bytes",
+           LIB.pt_workspace_bytes(op, ctypes.byref(_grid(grid)), dtype_code, np_,
+                                  ctypes.byref(out)))
+    return out.value
+
+
+def pt_key_layout(grid):
+    tx, ty, bits = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check("pt_key_layout", LIB.pt_key_layout(ctypes.byref(_grid(grid)), ctypes.byref(tx),
+                                              ctypes.byref(ty), ctypes.byref(bits)))
+    return tx.value, ty.value, bits.value
+
+
+def pt_spline_coeffs(grid, field, coeff, ws, stream=None):
+    _need(field, torch.float32, (3, grid.nz, grid.ny, grid.nx), "field")
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _check("pt_spline_coeffs",
+           LIB.pt_spline_coeffs(ctypes.byref(_grid(grid)), _ptr(field), _ptr(coeff),
+                                _dtype_code(coeff), _ptr(ws), ws.numel() * ws.element_size(),
+                                _stream(stream)))
+
+
+def pt_spline_coeffs_bwd(grid, g_coeff, g_field, ws, stream=None):
+    _need(g_coeff, torch.float32, grid.padded_shape, "g_coeff")
+    _need(g_field, torch.float32, (3, grid.nz, grid.ny, grid.nx), "g_field")
+    _check("pt_spline_coeffs_bwd",
+           LIB.pt_spline_coeffs_bwd(ctypes.byref(_grid(grid)), _ptr(g_coeff), _ptr(g_field),
+                                    _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pt_sort_particles(grid, pos, pos_sorted, perm, keys_out, ws, stream=None):
+    np_ = pos.shape[1]
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(pos_sorted, torch.float64, (3, np_), "pos_sorted")
+    _need(perm, torch.int32, (np_,), "perm")
+    _need(keys_out, torch.int64, (np_,), "keys_out")
+    _check("pt_sort_particles",
+           LIB.pt_sort_particles(ctypes.byref(_grid(grid)), np_, _ptr(pos), _ptr(pos_sorted),
+                                 _ptr(perm), _ptr(keys_out), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pt_interp_uvw(grid, coeff, pos, out, stream=None):
+    np_ = pos.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(out, torch.float32, (3, np_), "out")
+    _check("pt_interp_uvw",
+           LIB.pt_interp_uvw(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                             _ptr(pos), _ptr(out), _stream(stream)))
+
+
+def pt_interp_grad(grid, coeff, pos, out, stream=None):
+    np_ = pos.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(out, torch.float32, (12, np_), "out")
+    _check("pt_interp_grad",
+           LIB.pt_interp_grad(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                              _ptr(pos), _ptr(out), _stream(stream)))
+
+
+def pt_rk2_step(grid, coeff, dt, pos, ids, sort, ws, stream=None):
+    np_ = pos.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(ids, torch.int32, (np_,), "ids")
+    _check("pt_rk2_step",
+           LIB.pt_rk2_step(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                           float(dt), _ptr(pos), _ptr(ids), int(bool(sort)), _ptr(ws),
+                           ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pt_interp_uvw_bwd(grid, coeff, pos, g_out, g_pos, g_coeff, stream=None):
+    np_ = pos.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(g_out, torch.float32, (3, np_), "g_out")
+    _need(g_pos, torch.float64, (3, np_), "g_pos")
+    _need(g_coeff, torch.float32, grid.padded_shape, "g_coeff")
+    _check("pt_interp_uvw_bwd",
+           LIB.pt_interp_uvw_bwd(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff),
+                                 np_, _ptr(pos), _ptr(g_out), _ptr(g_pos), _ptr(g_coeff),
+                                 _stream(stream)))
+
+
+def pt_rk2_step_bwd(grid, coeff, dt, pos_n, sort, g_pos, g_coeff, ws, stream=None):
+    np_ = pos_n.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos_n, torch.float64, (3, np_), "pos_n")
+    _need(g_pos, torch.float64, (3, np_), "g_pos")
+    _need(g_coeff, torch.float32, grid.padded_shape, "g_coeff")
+    _check("pt_rk2_step_bwd",
+           LIB.pt_rk2_step_bwd(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                               float(dt), _ptr(pos_n), int(bool(sort)), _ptr(g_pos),
+                               _ptr(g_coeff), _ptr(ws), ws.numel() * ws.element_size(),
+                               _stream(stream)))
+
+
+def pt_last_device_error(stream=None):
+    return LIB.pt_last_device_error(_stream(stream))

@@ -1,0 +1,322 @@
+// C ABI entry points: host-side argument validation, workspace carving and
+// dispatch to the kernels of solve.hip, sort.hip and gather.hip.
+#include <math.h>
+#include <mutex>
+
+#include "pt_common.h"
+
+namespace pt {
+
+// solve.hip
+size_t spline_ws_floats(const pt_grid* g, pt_dtype dtype);
+pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype dtype, float* ws,
+                     hipStream_t s);
+pt_status spline_bwd(const pt_grid* g, const float* gcoeff, float* gfield, float* ws,
+                     hipStream_t s);
+// sort.hip
+int key_bits(const pt_grid* g);
+size_t sort_ws_bytes(const pt_grid* g, int64_t np);
+pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double* pos_sorted,
+                         int32_t* perm, uint64_t* keys_out, void* ws, hipStream_t s);
+pt_status permute_ids(int64_t np, const int32_t* in, const int32_t* perm, int32_t* out,
+                      hipStream_t s);
+// gather.hip
+pt_status interp_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,
+                     const double* pos, float* out, int nout, hipStream_t s);
+pt_status rk2_advance(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
+                      const double* x, double* x_out, float* u0, hipStream_t s);
+pt_status interp_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,
+                     const double* pos, const float* gout, double* gpos, float* gcoeff,
+                     hipStream_t s);
+pt_status rk2_backward(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
+                       const double* x, const double* lam, double* out, float* gcoeff, float* u0,
+                       double* xbs, hipStream_t s);
+pt_status scatter_back(int64_t np, const double* in, const int32_t* perm, double* out,
+                       hipStream_t s);
+
+// One non-finite-position flag per device, in the library's static device
+// memory; kernels receive its device address.
+static __device__ int g_error_flag;
+
+constexpr int kMaxDevices = 64;
+static int* g_flag_ptr[kMaxDevices];
+static std::mutex g_flag_mu;
+
+int* device_error_flag() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_flag_mu);
+  if (!g_flag_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_error_flag)) != hipSuccess) return nullptr;
+    g_flag_ptr[dev] = (int*)p;
+  }
+  return g_flag_ptr[dev];
+}
+
+static inline size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static pt_status check_grid(const pt_grid* g) {
+  if (!g) return PT_ERR_NULL;
+  const int n[3] = {g->nx, g->ny, g->nz};
+  const double L[3] = {g->lx, g->ly, g->lz};
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 4) return PT_ERR_SIZE;
+    if (!(L[d] > 0.0) || !isfinite(L[d])) return PT_ERR_SIZE;
+  }
+  for (int d = 0; d < 3; ++d)
+    if (n[d] > 8192) return PT_ERR_UNSUPPORTED;
+  return PT_OK;
+}
+
+static pt_status check_np(int64_t np) {
+  if (np < 0 || np > (int64_t)0x7fffffff) return PT_ERR_SIZE;
+  return PT_OK;
+}
+
+static pt_status check_dtype(pt_dtype d) {
+  return (d == PT_F32 || d == PT_BF16) ? PT_OK : PT_ERR_DTYPE;
+}
+
+static pt_status ready() { return device_error_flag() ? PT_OK : PT_ERR_HIP; }
+
+#define PT_TRY(expr)                  \
+  do {                                \
+    pt_status st_ = (expr);           \
+    if (st_ != PT_OK) return st_;     \
+  } while (0)
+
+// ------------------------------------------------------ workspace sizes ---
+struct Rk2Ws {
+  void* sort;
+  double* pos_sorted;
+  int32_t* perm;
+  int32_t* ids_tmp;
+  float* u0;
+};
+
+static size_t rk2_ws_bytes(const pt_grid* g, int64_t np) {
+  return a256(sort_ws_bytes(g, np)) + a256(24 * (size_t)np) + 2 * a256(4 * (size_t)np) +
+         a256(12 * (size_t)np);
+}
+
+static Rk2Ws carve_rk2(const pt_grid* g, int64_t np, void* ws) {
+  char* p = (char*)ws;
+  Rk2Ws w;
+  w.sort = p; p += a256(sort_ws_bytes(g, np));
+  w.pos_sorted = (double*)p; p += a256(24 * (size_t)np);
+  w.perm = (int32_t*)p; p += a256(4 * (size_t)np);
+  w.ids_tmp = (int32_t*)p; p += a256(4 * (size_t)np);
+  w.u0 = (float*)p;
+  return w;
+}
+
+struct Rk2BwdWs {
+  void* sort;
+  double* pos_sorted;
+  int32_t* perm;
+  double* xbn;
+  double* xbs;
+  float* u0;
+};
+
+static size_t rk2_bwd_ws_bytes(const pt_grid* g, int64_t np) {
+  return a256(sort_ws_bytes(g, np)) + 3 * a256(24 * (size_t)np) + a256(4 * (size_t)np) +
+         a256(12 * (size_t)np);
+}
+
+static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, void* ws) {
+  char* p = (char*)ws;
+  Rk2BwdWs w;
+  w.sort = p; p += a256(sort_ws_bytes(g, np));
+  w.pos_sorted = (double*)p; p += a256(24 * (size_t)np);
+  w.xbn = (double*)p; p += a256(24 * (size_t)np);
+  w.xbs = (double*)p; p += a256(24 * (size_t)np);
+  w.perm = (int32_t*)p; p += a256(4 * (size_t)np);
+  w.u0 = (float*)p;
+  return w;
+}
+
+}  // namespace pt
+
+using namespace pt;
+
+extern "C" {
+
+pt_status pt_workspace_bytes(int op, const pt_grid* grid, pt_dtype dtype, int64_t np,
+                             size_t* bytes) {
+  if (!bytes) return PT_ERR_NULL;
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  if (op != PT_OP_SPLINE && op != PT_OP_SPLINE_BWD) PT_TRY(check_np(np));
+  const size_t n3 = (size_t)grid->nx * grid->ny * grid->nz;
+  switch (op) {
+    case PT_OP_SPLINE: *bytes = a256(4 * spline_ws_floats(grid, dtype)); break;
+    case PT_OP_SPLINE_BWD: *bytes = a256(4 * n3); break;
+    case PT_OP_SORT: *bytes = a256(sort_ws_bytes(grid, np)); break;
+    case PT_OP_RK2: *bytes = a256(rk2_ws_bytes(grid, np)); break;
+    case PT_OP_RK2_BWD: *bytes = a256(rk2_bwd_ws_bytes(grid, np)); break;
+    default: return PT_ERR_ARG;
+  }
+  return PT_OK;
+}
+
+pt_status pt_key_layout(const pt_grid* grid, int32_t* tile_x, int32_t* tile_y, int32_t* bits) {
+  PT_TRY(check_grid(grid));
+  if (!tile_x || !tile_y || !bits) return PT_ERR_NULL;
+  *tile_x = kTileX;
+  *tile_y = kTileY;
+  *bits = key_bits(grid);
+  return PT_OK;
+}
+
+pt_status pt_spline_coeffs(const pt_grid* grid, const float* field, void* coeff, pt_dtype dtype,
+                           void* ws, size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  if (!field || !coeff) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_SPLINE, grid, dtype, 0, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  return spline_fwd(grid, field, coeff, dtype, (float*)ws, stream);
+}
+
+pt_status pt_spline_coeffs_bwd(const pt_grid* grid, const float* g_coeff, float* g_field, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  if (!g_coeff || !g_field) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_SPLINE_BWD, grid, PT_F32, 0, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  return spline_bwd(grid, g_coeff, g_field, (float*)ws, stream);
+}
+
+pt_status pt_sort_particles(const pt_grid* grid, int64_t np, const double* pos, double* pos_sorted,
+                            int32_t* perm, uint64_t* keys_out, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_np(np));
+  if (np == 0) return PT_OK;
+  if (!pos || !perm) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_SORT, grid, PT_F32, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  return sort_particles(grid, np, pos, pos_sorted, perm, keys_out, ws, stream);
+}
+
+pt_status pt_interp_uvw(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                        const double* pos, float* out, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos || !out) return PT_ERR_NULL;
+  PT_TRY(ready());
+  return interp_fwd(grid, coeff, dtype, np, pos, out, 3, stream);
+}
+
+pt_status pt_interp_grad(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                         const double* pos, float* out, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos || !out) return PT_ERR_NULL;
+  PT_TRY(ready());
+  return interp_fwd(grid, coeff, dtype, np, pos, out, 12, stream);
+}
+
+pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                      double dt, double* pos, int32_t* ids, int sort, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (!isfinite(dt)) return PT_ERR_ARG;
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_RK2, grid, dtype, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  Rk2Ws w = carve_rk2(grid, np, ws);
+  if (sort) {
+    PT_TRY(sort_particles(grid, np, pos, w.pos_sorted, w.perm, nullptr, w.sort, stream));
+    if (ids) {
+      PT_TRY(permute_ids(np, ids, w.perm, w.ids_tmp, stream));
+      PT_HIP_CHECK(hipMemcpyAsync(ids, w.ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
+    }
+    return rk2_advance(grid, coeff, dtype, np, dt, w.pos_sorted, pos, w.u0, stream);
+  }
+  return rk2_advance(grid, coeff, dtype, np, dt, pos, pos, w.u0, stream);
+}
+
+pt_status pt_interp_uvw_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                            const double* pos, const float* g_out, double* g_pos, float* g_coeff,
+                            hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (np == 0 || (!g_pos && !g_coeff)) return PT_OK;
+  if (!coeff || !pos || !g_out) return PT_ERR_NULL;
+  PT_TRY(ready());
+  return interp_bwd(grid, coeff, dtype, np, pos, g_out, g_pos, g_coeff, stream);
+}
+
+pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                          double dt, const double* pos_n, int sort, double* g_pos, float* g_coeff,
+                          void* ws, size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (!isfinite(dt)) return PT_ERR_ARG;
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos_n || !g_pos) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_RK2_BWD, grid, dtype, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  Rk2BwdWs w = carve_rk2_bwd(grid, np, ws);
+  if (sort) {
+    PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.sort, stream));
+    PT_TRY(rk2_backward(grid, coeff, dtype, np, dt, w.pos_sorted, g_pos, w.xbn, g_coeff, w.u0,
+                        w.xbs, stream));
+    return scatter_back(np, w.xbn, w.perm, g_pos, stream);
+  }
+  return rk2_backward(grid, coeff, dtype, np, dt, pos_n, g_pos, g_pos, g_coeff, w.u0, w.xbs,
+                      stream);
+}
+
+pt_status pt_last_device_error(hipStream_t stream) {
+  int* flag = device_error_flag();
+  if (!flag) return PT_ERR_HIP;
+  PT_HIP_CHECK(hipStreamSynchronize(stream));
+  int v = 0;
+  PT_HIP_CHECK(hipMemcpy(&v, flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (v) {
+    const int zero = 0;
+    PT_HIP_CHECK(hipMemcpy(flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+    return PT_ERR_NONFINITE;
+  }
+  return PT_OK;
+}
+
+const char* pt_status_string(pt_status s) {
+  switch (s) {
+    case PT_OK: return "ok";
+    case PT_ERR_NULL: return "required pointer is NULL";
+    case PT_ERR_SIZE: return "invalid grid size, box length or particle count";
+    case PT_ERR_DTYPE: return "unknown coefficient dtype";
+    case PT_ERR_WORKSPACE: return "workspace missing or too small";
+    case PT_ERR_NONFINITE: return "non-finite particle position";
+    case PT_ERR_HIP: return "HIP runtime error";
+    case PT_ERR_UNSUPPORTED: return "unsupported size";
+    case PT_ERR_ARG: return "invalid argument";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

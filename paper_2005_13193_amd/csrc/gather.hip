@@ -1,0 +1,322 @@
+// Operations 2 and 3 of Sec. 2.2 (basis functions and the 64-term sum of
+// eq. (spline)) at every particle, the Heun RK2 stages built on them, and
+// their adjoints.  One thread per particle; the 16 x-runs of 4 coefficients
+// per component are read straight from the padded array.  Particles that are
+// ordered by cell (pt_sort_particles) make neighbouring lanes read
+// neighbouring coefficients, so the reads coalesce and hit in L2.
+#include "pt_common.h"
+
+namespace pt {
+
+struct Cell {
+  int a, b, c;
+  float t[3];
+};
+
+__device__ __forceinline__ Cell locate(const GridDev& g, double x, double y, double z, int* err) {
+  Cell cl;
+  bool bad = false;
+  double t0, t1, t2;
+  cl.a = cell_1d(x, g.cs[0], g.nx, &t0, &bad);
+  cl.b = cell_1d(y, g.cs[1], g.ny, &t1, &bad);
+  cl.c = cell_1d(z, g.cs[2], g.nz, &t2, &bad);
+  if (bad) *err = 1;
+  cl.t[0] = (float)t0;
+  cl.t[1] = (float)t1;
+  cl.t[2] = (float)t2;
+  return cl;
+}
+
+// Value (and, with GRAD, the three physical derivatives) of each component:
+// out[c] = u_c, out[3 + 3c + d] = du_c/dx_d.
+template <typename CT, bool GRAD>
+__device__ __forceinline__ void spline_eval(const GridDev& g, const CT* __restrict__ coeff,
+                                            const Cell& cl, float out[12]) {
+  float wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
+  bspline_w(cl.t[0], wx);
+  bspline_w(cl.t[1], wy);
+  bspline_w(cl.t[2], wz);
+  if (GRAD) {
+    bspline_dw(cl.t[0], dx);
+    bspline_dw(cl.t[1], dy);
+    bspline_dw(cl.t[2], dz);
+  }
+  const int64_t off = ((int64_t)cl.c * g.py + cl.b) * g.px + cl.a;
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    const CT* base = coeff + comp * g.comp + off;
+    float v = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float ty = 0.f, tdy = 0.f, tdx = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const CT* row = base + k * g.plane + j * g.px;
+        const float r0 = load_coeff(row), r1 = load_coeff(row + 1);
+        const float r2 = load_coeff(row + 2), r3 = load_coeff(row + 3);
+        const float sx = wx[0] * r0 + wx[1] * r1 + wx[2] * r2 + wx[3] * r3;
+        ty += wy[j] * sx;
+        if (GRAD) {
+          tdy += dy[j] * sx;
+          tdx += wy[j] * (dx[0] * r0 + dx[1] * r1 + dx[2] * r2 + dx[3] * r3);
+        }
+      }
+      v += wz[k] * ty;
+      if (GRAD) {
+        gx += wz[k] * tdx;
+        gy += wz[k] * tdy;
+        gz += dz[k] * ty;
+      }
+    }
+    out[comp] = v;
+    if (GRAD) {
+      out[3 + 3 * comp + 0] = gx * g.inv_h[0];
+      out[3 + 3 * comp + 1] = gy * g.inv_h[1];
+      out[3 + 3 * comp + 2] = gz * g.inv_h[2];
+    }
+  }
+}
+
+// Transposed 64-term sum: g_coeff[comp][stencil] += w_ijk gu[comp].
+__device__ __forceinline__ void spline_scatter(const GridDev& g, float* __restrict__ gc,
+                                               const Cell& cl, const float gu[3]) {
+  float wx[4], wy[4], wz[4];
+  bspline_w(cl.t[0], wx);
+  bspline_w(cl.t[1], wy);
+  bspline_w(cl.t[2], wz);
+  const int64_t off = ((int64_t)cl.c * g.py + cl.b) * g.px + cl.a;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float wjk = wz[k] * wy[j];
+      float* row = gc + off + k * g.plane + j * g.px;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float w = wjk * wx[i];
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) unsafeAtomicAdd(row + comp * g.comp + i, w * gu[comp]);
+      }
+    }
+}
+
+template <typename CT, int NOUT>
+__global__ __launch_bounds__(256) void interp_kernel(GridDev g, const CT* __restrict__ coeff,
+                                                     int64_t np, const double* __restrict__ pos,
+                                                     float* __restrict__ out, int* err) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= np) return;
+  const Cell cl = locate(g, pos[p], pos[np + p], pos[2 * np + p], err);
+  float o[12];
+  spline_eval<CT, NOUT == 12>(g, coeff, cl, o);
+#pragma unroll
+  for (int q = 0; q < NOUT; ++q) out[q * np + p] = o[q];
+}
+
+// Second Heun stage: x* = x + dt u0, u1 = u(x*), x_out = x + dt/2 (u0 + u1).
+// x_out may alias x (each thread reads its own particle before writing).
+template <typename CT>
+__global__ __launch_bounds__(256) void rk2_stage2(GridDev g, const CT* __restrict__ coeff,
+                                                  int64_t np, double dt, const double* x,
+                                                  const float* __restrict__ u0, double* x_out,
+                                                  int* err) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= np) return;
+  double xn[3], xs[3];
+  float ua[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    xn[d] = x[d * np + p];
+    ua[d] = u0[d * np + p];
+    xs[d] = xn[d] + dt * (double)ua[d];
+  }
+  const Cell cl = locate(g, xs[0], xs[1], xs[2], err);
+  float ub[12];
+  spline_eval<CT, false>(g, coeff, cl, ub);
+  const double h = 0.5 * dt;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) x_out[d * np + p] = xn[d] + h * ((double)ua[d] + (double)ub[d]);
+}
+
+template <typename CT>
+__global__ __launch_bounds__(256) void interp_bwd_kernel(GridDev g, const CT* __restrict__ coeff,
+                                                         int64_t np, const double* __restrict__ pos,
+                                                         const float* __restrict__ gout,
+                                                         double* __restrict__ gpos,
+                                                         float* __restrict__ gcoeff, int* err) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= np) return;
+  const Cell cl = locate(g, pos[p], pos[np + p], pos[2 * np + p], err);
+  const float gu[3] = {gout[p], gout[np + p], gout[2 * np + p]};
+  if (gpos) {
+    float o[12];
+    spline_eval<CT, true>(g, coeff, cl, o);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      gpos[d * np + p] += (double)(gu[0] * o[3 + d] + gu[1] * o[6 + d] + gu[2] * o[9 + d]);
+  }
+  if (gcoeff) spline_scatter(g, gcoeff, cl, gu);
+}
+
+// Adjoint of a Heun step, part 1 (at x*): ub1 = dt/2 lam, xbs = J(x*)^T ub1,
+// g_coeff += W(x*)^T ub1.  u0 is the stage-1 velocity at x^n.
+template <typename CT>
+__global__ __launch_bounds__(256) void rk2_bwd_star(GridDev g, const CT* __restrict__ coeff,
+                                                    int64_t np, double dt,
+                                                    const double* __restrict__ x,
+                                                    const float* __restrict__ u0,
+                                                    const double* __restrict__ lam,
+                                                    double* __restrict__ xbs,
+                                                    float* __restrict__ gcoeff, int* err) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= np) return;
+  double xs[3];
+  float ub[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    xs[d] = x[d * np + p] + dt * (double)u0[d * np + p];
+    ub[d] = (float)(0.5 * dt * lam[d * np + p]);
+  }
+  const Cell cl = locate(g, xs[0], xs[1], xs[2], err);
+  float o[12];
+  spline_eval<CT, true>(g, coeff, cl, o);
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    xbs[d * np + p] = (double)(ub[0] * o[3 + d] + ub[1] * o[6 + d] + ub[2] * o[9 + d]);
+  if (gcoeff) spline_scatter(g, gcoeff, cl, ub);
+}
+
+// Part 2 (at x^n): ub0 = dt/2 lam + dt xbs, out = lam + xbs + J(x^n)^T ub0,
+// g_coeff += W(x^n)^T ub0.  out may alias lam.
+template <typename CT>
+__global__ __launch_bounds__(256) void rk2_bwd_n(GridDev g, const CT* __restrict__ coeff,
+                                                 int64_t np, double dt,
+                                                 const double* __restrict__ x, const double* lam,
+                                                 const double* __restrict__ xbs, double* out,
+                                                 float* __restrict__ gcoeff, int* err) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= np) return;
+  double l[3], s[3];
+  float ub[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    l[d] = lam[d * np + p];
+    s[d] = xbs[d * np + p];
+    ub[d] = (float)(0.5 * dt * l[d] + dt * s[d]);
+  }
+  const Cell cl = locate(g, x[p], x[np + p], x[2 * np + p], err);
+  float o[12];
+  spline_eval<CT, true>(g, coeff, cl, o);
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    out[d * np + p] = l[d] + s[d] + (double)(ub[0] * o[3 + d] + ub[1] * o[6 + d] + ub[2] * o[9 + d]);
+  if (gcoeff) spline_scatter(g, gcoeff, cl, ub);
+}
+
+__global__ __launch_bounds__(256) void scatter_rows_f64(int64_t np, const double* __restrict__ in,
+                                                        const int32_t* __restrict__ perm,
+                                                        double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  const int64_t q = perm[i];
+  out[q] = in[i];
+  out[np + q] = in[np + i];
+  out[2 * np + q] = in[2 * np + i];
+}
+
+// ------------------------------------------------------------ launchers ---
+#define PT_DISPATCH_CT(dtype, KERNEL, ...)                                  \
+  do {                                                                      \
+    if ((dtype) == PT_F32) {                                                \
+      hipLaunchKernelGGL(KERNEL<float>, __VA_ARGS__);                       \
+    } else {                                                                \
+      hipLaunchKernelGGL(KERNEL<uint16_t>, __VA_ARGS__);                    \
+    }                                                                       \
+  } while (0)
+
+pt_status interp_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,
+                     const double* pos, float* out, int nout, hipStream_t s) {
+  const GridDev gd = make_grid_dev(g);
+  const dim3 grid(grid_1d(np, 256)), block(256);
+  int* err = device_error_flag();
+  if (nout == 3) {
+    if (dtype == PT_F32)
+      hipLaunchKernelGGL((interp_kernel<float, 3>), grid, block, 0, s, gd, (const float*)coeff, np,
+                         pos, out, err);
+    else
+      hipLaunchKernelGGL((interp_kernel<uint16_t, 3>), grid, block, 0, s, gd,
+                         (const uint16_t*)coeff, np, pos, out, err);
+  } else {
+    if (dtype == PT_F32)
+      hipLaunchKernelGGL((interp_kernel<float, 12>), grid, block, 0, s, gd, (const float*)coeff,
+                         np, pos, out, err);
+    else
+      hipLaunchKernelGGL((interp_kernel<uint16_t, 12>), grid, block, 0, s, gd,
+                         (const uint16_t*)coeff, np, pos, out, err);
+  }
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
+pt_status rk2_advance(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
+                      const double* x, double* x_out, float* u0, hipStream_t s) {
+  pt_status st = interp_fwd(g, coeff, dtype, np, x, u0, 3, s);
+  if (st != PT_OK) return st;
+  const GridDev gd = make_grid_dev(g);
+  if (dtype == PT_F32)
+    hipLaunchKernelGGL(rk2_stage2<float>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd,
+                       (const float*)coeff, np, dt, x, u0, x_out, device_error_flag());
+  else
+    hipLaunchKernelGGL(rk2_stage2<uint16_t>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd,
+                       (const uint16_t*)coeff, np, dt, x, u0, x_out, device_error_flag());
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
+pt_status interp_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,
+                     const double* pos, const float* gout, double* gpos, float* gcoeff,
+                     hipStream_t s) {
+  const GridDev gd = make_grid_dev(g);
+  if (dtype == PT_F32)
+    hipLaunchKernelGGL(interp_bwd_kernel<float>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd,
+                       (const float*)coeff, np, pos, gout, gpos, gcoeff, device_error_flag());
+  else
+    hipLaunchKernelGGL(interp_bwd_kernel<uint16_t>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd,
+                       (const uint16_t*)coeff, np, pos, gout, gpos, gcoeff, device_error_flag());
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
+// Adjoint of one Heun step on particles in the order x is given; lam is
+// dL/dx_out in that order; out receives dL/dx (out may alias lam).
+pt_status rk2_backward(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
+                       const double* x, const double* lam, double* out, float* gcoeff, float* u0,
+                       double* xbs, hipStream_t s) {
+  pt_status st = interp_fwd(g, coeff, dtype, np, x, u0, 3, s);
+  if (st != PT_OK) return st;
+  const GridDev gd = make_grid_dev(g);
+  const dim3 grid(grid_1d(np, 256)), block(256);
+  int* err = device_error_flag();
+  if (dtype == PT_F32) {
+    hipLaunchKernelGGL(rk2_bwd_star<float>, grid, block, 0, s, gd, (const float*)coeff, np, dt, x,
+                       u0, lam, xbs, gcoeff, err);
+    hipLaunchKernelGGL(rk2_bwd_n<float>, grid, block, 0, s, gd, (const float*)coeff, np, dt, x,
+                       lam, xbs, out, gcoeff, err);
+  } else {
+    hipLaunchKernelGGL(rk2_bwd_star<uint16_t>, grid, block, 0, s, gd, (const uint16_t*)coeff, np,
+                       dt, x, u0, lam, xbs, gcoeff, err);
+    hipLaunchKernelGGL(rk2_bwd_n<uint16_t>, grid, block, 0, s, gd, (const uint16_t*)coeff, np, dt,
+                       x, lam, xbs, out, gcoeff, err);
+  }
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
+pt_status scatter_back(int64_t np, const double* in, const int32_t* perm, double* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(scatter_rows_f64, dim3(grid_1d(np, 256)), dim3(256), 0, s, np, in, perm, out);
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
+}  // namespace pt

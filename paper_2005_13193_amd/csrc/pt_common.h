@@ -1,0 +1,119 @@
+// Internal definitions shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pt_spline.h"
+
+namespace pt {
+
+// Particles are ordered in columns of kTileX x kTileY cells (full height in
+// z); see pt_key_layout.
+constexpr int kTileX = 32;
+constexpr int kTileY = 32;
+
+// Launch-time description of the grid and of the padded coefficient array.
+struct GridDev {
+  int nx, ny, nz;      // grid points per axis
+  int px, py, pz;      // padded extents n + 3
+  int64_t plane;       // px * py
+  int64_t comp;        // px * py * pz (elements per component)
+  double cs[3];        // n / L per axis (grid units per length), host-rounded
+  float inv_h[3];      // n / L in FP32 (for physical derivatives)
+};
+
+inline GridDev make_grid_dev(const pt_grid* g) {
+  GridDev d;
+  d.nx = g->nx; d.ny = g->ny; d.nz = g->nz;
+  d.px = g->nx + 3; d.py = g->ny + 3; d.pz = g->nz + 3;
+  d.plane = (int64_t)d.px * d.py;
+  d.comp = d.plane * d.pz;
+  d.cs[0] = (double)g->nx / g->lx;
+  d.cs[1] = (double)g->ny / g->ly;
+  d.cs[2] = (double)g->nz / g->lz;
+  for (int i = 0; i < 3; ++i) d.inv_h[i] = (float)d.cs[i];
+  return d;
+}
+
+// ---------------------------------------------------------------- cells ---
+// Shadow position and cell along one axis (Sec. 2.2 / Sec. 3): every step is
+// one IEEE double operation, none fused, so the cell index is identical to
+// any other implementation of the same sequence.  A non-finite coordinate
+// yields cell 0, t = 0 and sets *bad.
+__device__ __forceinline__ int cell_1d(double x, double cs, int n, double* t, bool* bad) {
+#pragma clang fp contract(off)
+  if (!(fabs(x) <= 1.7976931348623157e308)) {  // NaN or +-inf
+    *bad = true;
+    *t = 0.0;
+    return 0;
+  }
+  const double dn = (double)n;
+  double s = x * cs;
+  double k = floor(s / dn);
+  double kn = k * dn;
+  double sw = s - kn;
+  if (sw < 0.0) sw = sw + dn;
+  if (sw >= dn) sw = sw - dn;
+  double fa = floor(sw);
+  *t = sw - fa;
+  int a = (int)fa;
+  // sw is in [0, n) by construction; the clamp only guards the memory access.
+  a = a < 0 ? 0 : (a > n - 1 ? n - 1 : a);
+  return a;
+}
+
+// ------------------------------------------------------------- weights ---
+// Uniform cubic B-spline pieces on the cell, i = 1..4 <-> coefficient
+// offsets -1..+2 (eq. (spline): p = alpha + i - 2), and their t-derivatives.
+__device__ __forceinline__ void bspline_w(float t, float w[4]) {
+  const float s = 1.0f - t;
+  const float t2 = t * t, t3 = t2 * t;
+  const float r6 = 1.0f / 6.0f;
+  w[0] = s * s * s * r6;
+  w[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * r6;
+  w[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * r6;
+  w[3] = t3 * r6;
+}
+
+__device__ __forceinline__ void bspline_dw(float t, float w[4]) {
+  const float s = 1.0f - t;
+  w[0] = -0.5f * s * s;
+  w[1] = t * (1.5f * t - 2.0f);
+  w[2] = 0.5f + t * (1.0f - 1.5f * t);
+  w[3] = 0.5f * t * t;
+}
+
+// ------------------------------------------------------------ bfloat16 ---
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  return __uint_as_float((uint32_t)b << 16);
+}
+
+// Round to nearest, ties to even; NaN stays a (quiet) NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float load_coeff(const float* p) { return *p; }
+__device__ __forceinline__ float load_coeff(const uint16_t* p) { return bf16_to_f32(*p); }
+
+// ---------------------------------------------------------- host glue ---
+// Per-device pointer to the library's non-finite-position flag.
+int* device_error_flag();
+
+inline unsigned grid_1d(int64_t n, int block) {
+  return (unsigned)((n + block - 1) / block);
+}
+
+}  // namespace pt
+
+#define PT_HIP_CHECK(expr)                    \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return PT_ERR_HIP;  \
+  } while (0)
+
+#define PT_LAUNCH_CHECK() PT_HIP_CHECK(hipGetLastError())

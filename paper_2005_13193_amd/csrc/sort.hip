@@ -1,0 +1,307 @@
+// Particle ordering by spline cell (the one-device counterpart of the
+// position-based particle-to-process mapping of Sec. 3): cell keys in FP64,
+// a stable least-significant-digit radix sort of (key, index) with 8-bit
+// digits, and the permutation of the particle arrays.
+//
+// Radix pass structure: the input is cut into wave tiles of kWaveItems
+// consecutive elements.  A histogram kernel counts the digits of every tile,
+// an exclusive scan over the digit-major count table gives every (digit,
+// tile) its output offset, and a scatter kernel re-reads each tile in order
+// and ranks equal digits with wave ballots, which keeps the sort stable.
+#include "pt_common.h"
+
+namespace pt {
+
+constexpr int kRounds = 16;
+constexpr int kWaveItems = 64 * kRounds;  // elements per wave tile
+constexpr int kScanItems = 8;             // per thread in the scan kernels
+constexpr int kScanBlock = 256 * kScanItems;
+
+template <typename K>
+__global__ __launch_bounds__(256) void cell_key_kernel(GridDev g, int64_t np,
+                                                       const double* __restrict__ pos,
+                                                       K* __restrict__ keys,
+                                                       uint32_t* __restrict__ vals, int* err) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  bool bad = false;
+  double t;
+  const int a = cell_1d(pos[i], g.cs[0], g.nx, &t, &bad);
+  const int b = cell_1d(pos[np + i], g.cs[1], g.ny, &t, &bad);
+  const int c = cell_1d(pos[2 * np + i], g.cs[2], g.nz, &t, &bad);
+  if (bad) *err = 1;
+  const K ncx = (K)((g.nx + kTileX - 1) / kTileX);
+  const K key = ((((K)(b / kTileY) * ncx + (K)(a / kTileX)) * (K)g.nz + (K)c) * (K)kTileY +
+                 (K)(b % kTileY)) * (K)kTileX + (K)(a % kTileX);
+  keys[i] = key;
+  vals[i] = (uint32_t)i;
+}
+
+// Lanes holding the same 8-bit digit: AND of the ballots of each bit (or of
+// their complements), restricted to the valid lanes.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
+  uint64_t peers = valid;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int bit = (d >> b) & 1;
+    const uint64_t bal = __ballot(bit);
+    peers &= bit ? bal : ~bal;
+  }
+  return peers;
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void radix_hist(const K* __restrict__ keys, int64_t n, int shift,
+                                                  uint32_t* __restrict__ counts, int64_t nwt) {
+  __shared__ uint32_t h[4][256];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = lane; i < 256; i += 64) h[wave][i] = 0;
+  __syncthreads();
+  const int64_t wt = (int64_t)blockIdx.x * 4 + wave;
+  const uint64_t lt = (1ull << lane) - 1;
+  if (wt < nwt) {
+    const int64_t base = wt * kWaveItems;
+    for (int r = 0; r < kRounds; ++r) {
+      const int64_t idx = base + r * 64 + lane;
+      const bool ok = idx < n;
+      const uint32_t d = ok ? (uint32_t)((keys[idx] >> shift) & 255) : 0u;
+      const uint64_t peers = match_digit(d, __ballot(ok));
+      if (ok && (peers & lt) == 0) h[wave][d] += (uint32_t)__popcll(peers);
+    }
+  }
+  __syncthreads();
+  if (wt < nwt)
+    for (int i = lane; i < 256; i += 64) counts[(int64_t)i * nwt + wt] = h[wave][i];
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void radix_scatter(const K* __restrict__ kin,
+                                                     const uint32_t* __restrict__ vin,
+                                                     K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                     int64_t n, int shift,
+                                                     const uint32_t* __restrict__ offsets,
+                                                     int64_t nwt) {
+  __shared__ uint32_t h[4][256];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t wt = (int64_t)blockIdx.x * 4 + wave;
+  if (wt < nwt)
+    for (int i = lane; i < 256; i += 64) h[wave][i] = offsets[(int64_t)i * nwt + wt];
+  __syncthreads();
+  if (wt >= nwt) return;
+  const uint64_t lt = (1ull << lane) - 1;
+  const int64_t base = wt * kWaveItems;
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t idx = base + r * 64 + lane;
+    const bool ok = idx < n;
+    K k = 0;
+    uint32_t v = 0;
+    if (ok) { k = kin[idx]; v = vin[idx]; }
+    const uint32_t d = (uint32_t)((k >> shift) & 255);
+    const uint64_t peers = match_digit(d, __ballot(ok));
+    const uint32_t start = ok ? h[wave][d] : 0u;
+    if (ok) {
+      const uint32_t dst = start + (uint32_t)__popcll(peers & lt);
+      kout[dst] = k;
+      vout[dst] = v;
+      // the lowest lane of each digit group advances the running offset; its
+      // new value depends on the value it read, so the read completes first
+      if ((peers & lt) == 0) h[wave][d] = start + (uint32_t)__popcll(peers);
+    }
+  }
+}
+
+// ------------------------------------------------- exclusive scan (u32) ---
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void scan_blocks(uint32_t* __restrict__ data, int64_t n,
+                                                   uint32_t* __restrict__ block_sums) {
+  __shared__ uint32_t wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)tid * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? data[base + i] : 0u;
+    tot += v[i];
+  }
+  const uint32_t incl = wave_incl_scan(tot, lane);
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int w = 0; w < wave; ++w) woff += wsum[w];
+  uint32_t run = woff + incl - tot;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) data[base + i] = run;
+    run += v[i];
+  }
+  if (tid == 255) block_sums[blockIdx.x] = woff + incl;
+}
+
+__global__ __launch_bounds__(256) void scan_add(uint32_t* __restrict__ data, int64_t n,
+                                                const uint32_t* __restrict__ block_offsets) {
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  const uint32_t off = block_offsets[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) data[base + i] += off;
+}
+
+static size_t scan_scratch_words(int64_t n) {
+  size_t w = 0;
+  while (n > 1) {
+    n = (n + kScanBlock - 1) / kScanBlock;
+    w += (size_t)n + 64;
+  }
+  return w + 64;
+}
+
+static pt_status exclusive_scan(uint32_t* data, int64_t n, uint32_t* scratch, hipStream_t s) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(scan_blocks, dim3((unsigned)nb), dim3(256), 0, s, data, n, scratch);
+  PT_LAUNCH_CHECK();
+  if (nb > 1) {
+    pt_status st = exclusive_scan(scratch, nb, scratch + nb + 64, s);
+    if (st != PT_OK) return st;
+    hipLaunchKernelGGL(scan_add, dim3((unsigned)nb), dim3(256), 0, s, data, n, scratch);
+    PT_LAUNCH_CHECK();
+  }
+  return PT_OK;
+}
+
+// -------------------------------------------------------------- permute ---
+__global__ __launch_bounds__(256) void permute_pos(int64_t np, const double* __restrict__ pos,
+                                                   const int32_t* __restrict__ perm,
+                                                   double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  const int64_t p = perm[i];
+  out[i] = pos[p];
+  out[np + i] = pos[np + p];
+  out[2 * np + i] = pos[2 * np + p];
+}
+
+__global__ __launch_bounds__(256) void permute_i32(int64_t np, const int32_t* __restrict__ in,
+                                                   const int32_t* __restrict__ perm,
+                                                   int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  out[i] = in[perm[i]];
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void widen_keys(int64_t np, const K* __restrict__ k,
+                                                  uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < np) out[i] = (uint64_t)k[i];
+}
+
+// ------------------------------------------------------------ host side ---
+
+int key_bits(const pt_grid* g) {
+  const uint64_t ncx = (uint64_t)((g->nx + kTileX - 1) / kTileX);
+  const uint64_t ncy = (uint64_t)((g->ny + kTileY - 1) / kTileY);
+  const uint64_t range = ncx * ncy * (uint64_t)g->nz * kTileX * kTileY;
+  int bits = 0;
+  while (bits < 64 && ((range - 1) >> bits) != 0) ++bits;
+  return bits < 1 ? 1 : bits;
+}
+
+static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct SortWs {
+  void* keys[2];
+  uint32_t* vals0;
+  uint32_t* counts;
+  uint32_t* scan;
+};
+
+size_t sort_ws_bytes(const pt_grid* g, int64_t np) {
+  const size_t kb = key_bits(g) > 32 ? 8 : 4;
+  const int64_t nwt = (np + kWaveItems - 1) / kWaveItems;
+  const size_t ncount = (size_t)nwt * 256;
+  return 2 * align256(kb * (size_t)np) + align256(4 * (size_t)np) + align256(4 * ncount) +
+         align256(4 * scan_scratch_words((int64_t)ncount));
+}
+
+static SortWs carve_sort_ws(const pt_grid* g, int64_t np, void* ws) {
+  const size_t kb = key_bits(g) > 32 ? 8 : 4;
+  const int64_t nwt = (np + kWaveItems - 1) / kWaveItems;
+  char* p = (char*)ws;
+  SortWs w;
+  w.keys[0] = p; p += align256(kb * (size_t)np);
+  w.keys[1] = p; p += align256(kb * (size_t)np);
+  w.vals0 = (uint32_t*)p; p += align256(4 * (size_t)np);
+  w.counts = (uint32_t*)p; p += align256(4 * (size_t)nwt * 256);
+  w.scan = (uint32_t*)p;
+  return w;
+}
+
+template <typename K>
+static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int32_t* perm,
+                           uint64_t* keys_out, void* ws, hipStream_t s) {
+  const GridDev gd = make_grid_dev(g);
+  SortWs w = carve_sort_ws(g, np, ws);
+  const int bits = key_bits(g);
+  const int passes = (bits + 7) / 8;
+  const int64_t nwt = (np + kWaveItems - 1) / kWaveItems;
+  const unsigned tblocks = (unsigned)((nwt + 3) / 4);
+  K* kbuf[2] = {(K*)w.keys[0], (K*)w.keys[1]};
+  // pass i writes value buffer (passes - 1 - i) & 1: 0 = perm, 1 = scratch,
+  // so that the last pass lands in perm.
+  uint32_t* vbuf[2] = {(uint32_t*)perm, w.vals0};
+  const int first_dst = (passes - 1) & 1;
+  const int src0 = first_dst ^ 1;
+  hipLaunchKernelGGL(cell_key_kernel<K>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd, np, pos,
+                     kbuf[src0], vbuf[src0], device_error_flag());
+  PT_LAUNCH_CHECK();
+  int src = src0;
+  for (int p = 0; p < passes; ++p) {
+    const int dst = src ^ 1;
+    hipLaunchKernelGGL(radix_hist<K>, dim3(tblocks), dim3(256), 0, s, kbuf[src], np, 8 * p,
+                       w.counts, nwt);
+    PT_LAUNCH_CHECK();
+    pt_status st = exclusive_scan(w.counts, nwt * 256, w.scan, s);
+    if (st != PT_OK) return st;
+    hipLaunchKernelGGL(radix_scatter<K>, dim3(tblocks), dim3(256), 0, s, kbuf[src], vbuf[src],
+                       kbuf[dst], vbuf[dst], np, 8 * p, w.counts, nwt);
+    PT_LAUNCH_CHECK();
+    src = dst;
+  }
+  if (keys_out) {
+    hipLaunchKernelGGL(widen_keys<K>, dim3(grid_1d(np, 256)), dim3(256), 0, s, np, kbuf[src],
+                       keys_out);
+    PT_LAUNCH_CHECK();
+  }
+  return PT_OK;
+}
+
+pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double* pos_sorted,
+                         int32_t* perm, uint64_t* keys_out, void* ws, hipStream_t s) {
+  pt_status st = key_bits(g) > 32 ? sort_impl<uint64_t>(g, np, pos, perm, keys_out, ws, s)
+                                   : sort_impl<uint32_t>(g, np, pos, perm, keys_out, ws, s);
+  if (st != PT_OK) return st;
+  if (pos_sorted) {
+    hipLaunchKernelGGL(permute_pos, dim3(grid_1d(np, 256)), dim3(256), 0, s, np, pos, perm,
+                       pos_sorted);
+    PT_LAUNCH_CHECK();
+  }
+  return PT_OK;
+}
+
+pt_status permute_ids(int64_t np, const int32_t* in, const int32_t* perm, int32_t* out,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(permute_i32, dim3(grid_1d(np, 256)), dim3(256), 0, s, np, in, perm, out);
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
+}  // namespace pt

@@ -1,0 +1,108 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry point
+the header declares, and rejects invalid arguments on the host, before any
+launch (no kernel runs in this file)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pt_spline.h")
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_2005_13193_amd import _binding
+    return _binding
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_expected_entry_points():
+    names = declared_functions()
+    for n in ("pt_spline_coeffs", "pt_sort_particles", "pt_interp_uvw", "pt_interp_grad",
+              "pt_rk2_step", "pt_interp_uvw_bwd", "pt_spline_coeffs_bwd", "pt_rk2_step_bwd",
+              "pt_workspace_bytes", "pt_key_layout", "pt_last_device_error",
+              "pt_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(b):
+    lib = ctypes.CDLL(b.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(b.EXPORTS) == set(declared_functions())
+
+
+def _g(b, n=(32, 32, 32), L=(6.283185307179586,) * 3):
+    return b.PtGrid(*n, *L)
+
+
+def test_workspace_sizes(b):
+    g = _g(b, (64, 48, 40))
+    n3 = 64 * 48 * 40
+    sp = ctypes.c_size_t()
+    assert b.LIB.pt_workspace_bytes(b.PT_OP_SPLINE, ctypes.byref(g), b.PT_F32, 0, ctypes.byref(sp)) == 0
+    assert sp.value >= 4 * n3 and sp.value % 256 == 0
+    assert b.LIB.pt_workspace_bytes(b.PT_OP_SPLINE, ctypes.byref(g), b.PT_BF16, 0, ctypes.byref(sp)) == 0
+    assert sp.value >= 8 * n3
+    for op in (b.PT_OP_SORT, b.PT_OP_RK2, b.PT_OP_RK2_BWD):
+        assert b.LIB.pt_workspace_bytes(op, ctypes.byref(g), b.PT_F32, 12345, ctypes.byref(sp)) == 0
+        assert sp.value >= 12345 * 8
+    assert b.LIB.pt_workspace_bytes(99, ctypes.byref(g), b.PT_F32, 0, ctypes.byref(sp)) == b.PT_ERR_ARG
+    assert b.LIB.pt_workspace_bytes(0, ctypes.byref(g), 7, 0, ctypes.byref(sp)) == b.PT_ERR_DTYPE
+
+
+def test_key_layout_bits(b):
+    for n, bits in (((1024,) * 3, 30), ((2048,) * 3, 33), ((32,) * 3, 15), ((4,) * 3, 12)):
+        tx, ty, kb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        g = _g(b, n)
+        assert b.LIB.pt_key_layout(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty),
+                                   ctypes.byref(kb)) == 0
+        assert (tx.value, ty.value) == (32, 32)
+        assert kb.value == bits, (n, kb.value)
+
+
+def test_invalid_arguments_rejected_before_launch(b):
+    L = b.LIB
+    g = _g(b)
+    bad = _g(b, (3, 32, 32))
+    huge = _g(b, (16384, 32, 32))
+    badL = _g(b, (32, 32, 32), (0.0, 1.0, 1.0))
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)  # never dereferenced: validation fails first
+    assert L.pt_spline_coeffs(None, fake, fake, 0, fake, 1 << 30, None) == b.PT_ERR_NULL
+    assert L.pt_spline_coeffs(ctypes.byref(bad), fake, fake, 0, fake, 1 << 30, None) == b.PT_ERR_SIZE
+    assert L.pt_spline_coeffs(ctypes.byref(badL), fake, fake, 0, fake, 1 << 30, None) == b.PT_ERR_SIZE
+    assert L.pt_spline_coeffs(ctypes.byref(huge), fake, fake, 0, fake, 1 << 40, None) == b.PT_ERR_UNSUPPORTED
+    assert L.pt_spline_coeffs(ctypes.byref(g), None, fake, 0, fake, 1 << 30, None) == b.PT_ERR_NULL
+    assert L.pt_spline_coeffs(ctypes.byref(g), fake, fake, 5, fake, 1 << 30, None) == b.PT_ERR_DTYPE
+    assert L.pt_spline_coeffs(ctypes.byref(g), fake, fake, 0, fake, 16, None) == b.PT_ERR_WORKSPACE
+    assert L.pt_spline_coeffs(ctypes.byref(g), fake, fake, 0, None, 1 << 30, None) == b.PT_ERR_WORKSPACE
+    assert L.pt_spline_coeffs_bwd(ctypes.byref(g), fake, None, fake, 1 << 30, None) == b.PT_ERR_NULL
+    assert L.pt_sort_particles(ctypes.byref(g), -1, fake, fake, fake, None, fake, 1 << 30, None) == b.PT_ERR_SIZE
+    assert L.pt_sort_particles(ctypes.byref(g), 1 << 31, fake, fake, fake, None, fake, 1 << 40, None) == b.PT_ERR_SIZE
+    assert L.pt_sort_particles(ctypes.byref(g), 10, fake, fake, None, None, fake, 1 << 30, None) == b.PT_ERR_NULL
+    assert L.pt_sort_particles(ctypes.byref(g), 10, fake, fake, fake, None, fake, 8, None) == b.PT_ERR_WORKSPACE
+    assert L.pt_sort_particles(ctypes.byref(g), 0, None, None, None, None, None, 0, None) == b.PT_OK
+    assert L.pt_interp_uvw(ctypes.byref(g), None, 0, 10, fake, fake, None) == b.PT_ERR_NULL
+    assert L.pt_interp_uvw(ctypes.byref(g), fake, 2, 10, fake, fake, None) == b.PT_ERR_DTYPE
+    assert L.pt_interp_uvw(ctypes.byref(g), None, 0, 0, None, None, None) == b.PT_OK
+    assert L.pt_interp_grad(ctypes.byref(g), fake, 0, 10, None, fake, None) == b.PT_ERR_NULL
+    nan = float("nan")
+    assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, nan, fake, None, 1, fake, 1 << 40, None) == b.PT_ERR_ARG
+    assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, 0.1, fake, None, 1, fake, 8, None) == b.PT_ERR_WORKSPACE
+    assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, 10, 0.1, fake, 1, None, None, fake, 1 << 40, None) == b.PT_ERR_NULL
+    assert L.pt_interp_uvw_bwd(ctypes.byref(g), fake, 0, 10, fake, None, fake, None, None) == b.PT_ERR_NULL
+    assert L.pt_interp_uvw_bwd(ctypes.byref(g), fake, 0, 10, fake, fake, None, None, None) == b.PT_OK
+
+
+def test_status_strings(b):
+    for s in range(-8, 1):
+        assert b.status_string(s) != "unknown status"
+    assert b.status_string(-99) == "unknown status"
