@@ -219,6 +219,7 @@ __global__ __launch_bounds__(256) void scatter_rows_f64(int64_t np, const double
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= np) return;
   const int64_t q = perm[i];
+  if ((uint64_t)q >= (uint64_t)np) return;
   out[q] = in[i];
   out[np + q] = in[np + i];
   out[2 * np + q] = in[2 * np + i];

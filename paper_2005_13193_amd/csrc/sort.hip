@@ -101,8 +101,10 @@ __global__ __launch_bounds__(256) void radix_scatter(const K* __restrict__ kin,
     const uint32_t start = ok ? h[wave][d] : 0u;
     if (ok) {
       const uint32_t dst = start + (uint32_t)__popcll(peers & lt);
-      kout[dst] = k;
-      vout[dst] = v;
+      if (dst < (uint64_t)n) {  // always true for consistent counts; guards the store
+        kout[dst] = k;
+        vout[dst] = v;
+      }
       // the lowest lane of each digit group advances the running offset; its
       // new value depends on the value it read, so the read completes first
       if ((peers & lt) == 0) h[wave][d] = start + (uint32_t)__popcll(peers);
@@ -184,6 +186,7 @@ __global__ __launch_bounds__(256) void permute_pos(int64_t np, const double* __r
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= np) return;
   const int64_t p = perm[i];
+  if ((uint64_t)p >= (uint64_t)np) return;
   out[i] = pos[p];
   out[np + i] = pos[np + p];
   out[2 * np + i] = pos[2 * np + p];
@@ -194,7 +197,8 @@ __global__ __launch_bounds__(256) void permute_i32(int64_t np, const int32_t* __
                                                    int32_t* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= np) return;
-  out[i] = in[perm[i]];
+  const int64_t p = perm[i];
+  if ((uint64_t)p < (uint64_t)np) out[i] = in[p];
 }
 
 template <typename K>

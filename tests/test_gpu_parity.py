@@ -16,6 +16,14 @@ pytestmark = pytest.mark.gpu
 
 F32_TOL = 1e-5
 BF16_TOL = 5e-3
+GRAD_BF16_TOL = 2e-2
+
+
+def bf16_round(a):
+    """FP64 -> nearest BF16 value (ties to even), returned as FP64."""
+    b = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
+    return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
 @pytest.fixture(scope="module")
@@ -140,7 +148,15 @@ def test_interp_uvw_and_grad_parity(pt, n, np_, clustered, dtype):
     assert normwise(out, ref) < tol
     out12 = host(pt.interp_grad(g, coeff, ps))
     ref12 = oracle.interp(og, ref_coeff, pos_s, n_out=12)
-    assert normwise(out12, ref12) < tol
+    assert normwise(out12[:3], ref12[:3]) < tol
+    # BF16 storage error is amplified ~1/(k h) in the derivative rows
+    assert normwise(out12[3:], ref12[3:]) < (tol if dtype == "f32" else GRAD_BF16_TOL)
+    if dtype == "bf16":
+        # the gather arithmetic itself: both sides read the same BF16 values
+        import torch
+        q = bf16_round(ref_coeff)
+        out_q = host(pt.interp_grad(g, dev(q, torch.float32).to(torch.bfloat16), ps))
+        assert normwise(out_q, oracle.interp(og, q, pos_s, n_out=12)) < F32_TOL
     # unsorted input gives the same values
     out_u = host(pt.interp_uvw(g, coeff, dev(pos)))
     assert normwise(out_u, oracle.interp(og, ref_coeff, pos)) < tol
