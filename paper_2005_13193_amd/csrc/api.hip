@@ -17,7 +17,8 @@ pt_status spline_bwd(const pt_grid* g, const float* gcoeff, float* gfield, float
 int key_bits(const pt_grid* g);
 size_t sort_ws_bytes(const pt_grid* g, int64_t np);
 pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double* pos_sorted,
-                         int32_t* perm, uint64_t* keys_out, void* ws, hipStream_t s);
+                         int32_t* perm, uint64_t* keys_out, int32_t* lstart, void* ws,
+                         hipStream_t s);
 pt_status permute_ids(int64_t np, const int32_t* in, const int32_t* perm, int32_t* out,
                       hipStream_t s);
 // gather.hip
@@ -33,6 +34,13 @@ pt_status rk2_backward(const pt_grid* g, const void* coeff, pt_dtype dtype, int6
                        double* xbs, hipStream_t s);
 pt_status scatter_back(int64_t np, const double* in, const int32_t* perm, double* out,
                        hipStream_t s);
+// tile.hip
+int64_t tile_nlayers(const pt_grid* g);
+pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
+                       int64_t np, double dt, const double* x, double* x_out, hipStream_t s);
+pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
+                       int64_t np, double dt, const double* x, const double* lam, double* xbn,
+                       float* u0, float* ub0, float* gcoeff, hipStream_t s);
 
 // One non-finite-position flag per device, in the library's static device
 // memory; kernels receive its device address.
@@ -87,17 +95,20 @@ static pt_status ready() { return device_error_flag() ? PT_OK : PT_ERR_HIP; }
   } while (0)
 
 // ------------------------------------------------------ workspace sizes ---
+static size_t lstart_bytes(const pt_grid* g) { return 4 * (size_t)(tile_nlayers(g) + 1); }
+
 struct Rk2Ws {
   void* sort;
   double* pos_sorted;
   int32_t* perm;
   int32_t* ids_tmp;
   float* u0;
+  int32_t* lstart;
 };
 
 static size_t rk2_ws_bytes(const pt_grid* g, int64_t np) {
   return a256(sort_ws_bytes(g, np)) + a256(24 * (size_t)np) + 2 * a256(4 * (size_t)np) +
-         a256(12 * (size_t)np);
+         a256(12 * (size_t)np) + a256(lstart_bytes(g));
 }
 
 static Rk2Ws carve_rk2(const pt_grid* g, int64_t np, void* ws) {
@@ -107,7 +118,8 @@ static Rk2Ws carve_rk2(const pt_grid* g, int64_t np, void* ws) {
   w.pos_sorted = (double*)p; p += a256(24 * (size_t)np);
   w.perm = (int32_t*)p; p += a256(4 * (size_t)np);
   w.ids_tmp = (int32_t*)p; p += a256(4 * (size_t)np);
-  w.u0 = (float*)p;
+  w.u0 = (float*)p; p += a256(12 * (size_t)np);
+  w.lstart = (int32_t*)p;
   return w;
 }
 
@@ -118,11 +130,13 @@ struct Rk2BwdWs {
   double* xbn;
   double* xbs;
   float* u0;
+  float* ub0;
+  int32_t* lstart;
 };
 
 static size_t rk2_bwd_ws_bytes(const pt_grid* g, int64_t np) {
   return a256(sort_ws_bytes(g, np)) + 3 * a256(24 * (size_t)np) + a256(4 * (size_t)np) +
-         a256(12 * (size_t)np);
+         2 * a256(12 * (size_t)np) + a256(lstart_bytes(g));
 }
 
 static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, void* ws) {
@@ -133,7 +147,9 @@ static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, void* ws) {
   w.xbn = (double*)p; p += a256(24 * (size_t)np);
   w.xbs = (double*)p; p += a256(24 * (size_t)np);
   w.perm = (int32_t*)p; p += a256(4 * (size_t)np);
-  w.u0 = (float*)p;
+  w.u0 = (float*)p; p += a256(12 * (size_t)np);
+  w.ub0 = (float*)p; p += a256(12 * (size_t)np);
+  w.lstart = (int32_t*)p;
   return w;
 }
 
@@ -204,7 +220,7 @@ pt_status pt_sort_particles(const pt_grid* grid, int64_t np, const double* pos, 
   PT_TRY(pt_workspace_bytes(PT_OP_SORT, grid, PT_F32, np, &need));
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
   PT_TRY(ready());
-  return sort_particles(grid, np, pos, pos_sorted, perm, keys_out, ws, stream);
+  return sort_particles(grid, np, pos, pos_sorted, perm, keys_out, nullptr, ws, stream);
 }
 
 pt_status pt_interp_uvw(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
@@ -244,12 +260,13 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
   PT_TRY(ready());
   Rk2Ws w = carve_rk2(grid, np, ws);
   if (sort) {
-    PT_TRY(sort_particles(grid, np, pos, w.pos_sorted, w.perm, nullptr, w.sort, stream));
+    PT_TRY(sort_particles(grid, np, pos, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
+                          stream));
     if (ids) {
       PT_TRY(permute_ids(np, ids, w.perm, w.ids_tmp, stream));
       PT_HIP_CHECK(hipMemcpyAsync(ids, w.ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
     }
-    return rk2_advance(grid, coeff, dtype, np, dt, w.pos_sorted, pos, w.u0, stream);
+    return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, pos, stream);
   }
   return rk2_advance(grid, coeff, dtype, np, dt, pos, pos, w.u0, stream);
 }
@@ -281,9 +298,10 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
   PT_TRY(ready());
   Rk2BwdWs w = carve_rk2_bwd(grid, np, ws);
   if (sort) {
-    PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.sort, stream));
-    PT_TRY(rk2_backward(grid, coeff, dtype, np, dt, w.pos_sorted, g_pos, w.xbn, g_coeff, w.u0,
-                        w.xbs, stream));
+    PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
+                          stream));
+    PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, g_pos, w.xbn, w.u0,
+                        w.ub0, g_coeff, stream));
     return scatter_back(np, w.xbn, w.perm, g_pos, stream);
   }
   return rk2_backward(grid, coeff, dtype, np, dt, pos_n, g_pos, g_pos, g_coeff, w.u0, w.xbs,

@@ -249,9 +249,12 @@ static SortWs carve_sort_ws(const pt_grid* g, int64_t np, void* ws) {
   return w;
 }
 
+pt_status build_layer_table(const pt_grid* g, int64_t np, const void* keys, int key_bytes,
+                            int32_t* ls, hipStream_t s);
+
 template <typename K>
 static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int32_t* perm,
-                           uint64_t* keys_out, void* ws, hipStream_t s) {
+                           uint64_t* keys_out, int32_t* lstart, void* ws, hipStream_t s) {
   const GridDev gd = make_grid_dev(g);
   SortWs w = carve_sort_ws(g, np, ws);
   const int bits = key_bits(g);
@@ -285,13 +288,16 @@ static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int3
                        keys_out);
     PT_LAUNCH_CHECK();
   }
+  if (lstart) return build_layer_table(g, np, kbuf[src], (int)sizeof(K), lstart, s);
   return PT_OK;
 }
 
 pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double* pos_sorted,
-                         int32_t* perm, uint64_t* keys_out, void* ws, hipStream_t s) {
-  pt_status st = key_bits(g) > 32 ? sort_impl<uint64_t>(g, np, pos, perm, keys_out, ws, s)
-                                   : sort_impl<uint32_t>(g, np, pos, perm, keys_out, ws, s);
+                         int32_t* perm, uint64_t* keys_out, int32_t* lstart, void* ws,
+                         hipStream_t s) {
+  pt_status st = key_bits(g) > 32
+                     ? sort_impl<uint64_t>(g, np, pos, perm, keys_out, lstart, ws, s)
+                     : sort_impl<uint32_t>(g, np, pos, perm, keys_out, lstart, ws, s);
   if (st != PT_OK) return st;
   if (pos_sorted) {
     hipLaunchKernelGGL(permute_pos, dim3(grid_1d(np, 256)), dim3(256), 0, s, np, pos, perm,

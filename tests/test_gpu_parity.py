@@ -287,3 +287,61 @@ def test_nonfinite_flag(pt):
     assert pt.last_device_error() == -5
     assert pt.last_device_error() == 0
     assert np.isfinite(out).all()
+
+
+# ------------------------------------------------- column-tiled kernels ---
+# pt_rk2_step / pt_rk2_step_bwd with sort=1 run the column-tiled kernels:
+# grids below span several columns (ragged in x and y), several z-segments
+# (ragged), dense layers that need several passes, and steps long enough
+# that predictor points leave the column tile or the LDS ring.
+TILED = [((100, 70, 300), 60000, True, 1.0), ((64, 64, 64), 30000, False, 3.0),
+         ((33, 40, 37), 5000, True, 1.0), ((4, 5, 6), 300, False, 1.0)]
+
+
+def _field_any(nx, ny, nz):
+    return field_for(nx, ny, nz, seed=3)
+
+
+@pytest.mark.parametrize("shape,np_,clustered,cfl", TILED)
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_rk2_tiled_fwd_bwd_parity(pt, shape, np_, clustered, cfl, dtype):
+    import torch
+    nx, ny, nz = shape
+    f = _field_any(nx, ny, nz)
+    g = pt.Grid(nx, ny, nz)
+    og = oracle.Grid(nx, ny, nz)
+    ref_coeff = oracle.spline_coeffs(f)
+    if dtype == "f32":
+        coeff = pt.spline_coeffs(g, dev(f, torch.float32))
+    else:
+        # the kernels' arithmetic on BF16 storage: both sides read the same
+        # BF16 coefficients (the BF16 rounding error itself is checked against
+        # the FP64 oracle on smooth fields in test_rk2_step_parity)
+        ref_coeff = bf16_round(ref_coeff)
+        coeff = dev(ref_coeff, torch.float32).to(torch.bfloat16)
+    tol = F32_TOL
+    pos = (synth.clustered_particles_np(np_, sigma=0.1) if clustered
+           else synth.uniform_particles_np(np_, seed=7))
+    dt = cfl * 0.6 * (2 * np.pi / max(shape)) / np.abs(f).max()
+    # forward: sorted order, ids give the permutation
+    p = dev(pos)
+    ids = torch.arange(np_, dtype=torch.int32, device="cuda")
+    pt.rk2_step(g, coeff, p, dt, ids=ids, sort=True)
+    idh = host(ids)
+    _, perm_ref, _ = oracle.sort_particles(og, pos, 32, 32)
+    assert np.array_equal(idh, perm_ref)
+    ref = oracle.rk2_step(og, ref_coeff, pos, dt)
+    assert normwise(host(p) - pos[:, idh], ref[:, idh] - pos[:, idh]) < tol
+    # adjoint of the same step
+    rng = np.random.default_rng(5)
+    lam = rng.standard_normal((3, np_))
+    gp = dev(lam)
+    gco = torch.zeros(g.padded_shape, dtype=torch.float32, device="cuda")
+    pt.rk2_step_bwd(g, coeff, dev(pos), dt, gp, gco, sort=True)
+    lam_ref, gc_ref = oracle.rk2_step_bwd(og, ref_coeff, pos[:, perm_ref], dt, lam,
+                                          np.zeros_like(ref_coeff))
+    ref_in = np.empty_like(lam_ref)
+    ref_in[:, perm_ref] = lam_ref
+    assert normwise(host(gp), ref_in) < tol
+    assert normwise(host(gco).reshape(3, -1), gc_ref.reshape(3, -1)) < F32_TOL
+    assert pt.last_device_error() == 0
