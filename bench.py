@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--uniform", action="store_true",
+                    help="uniform particles instead of the configuration's distribution")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has "
@@ -103,6 +105,9 @@ def main():
     import synth
 
     n, np_, kmax, clustered, desc = CONFIGS[args.config]
+    if args.uniform and clustered:
+        clustered = False
+        desc = desc.split(" (")[0].replace("particles", "uniform particles")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cdt = torch.float32 if args.dtype == "f32" else torch.bfloat16

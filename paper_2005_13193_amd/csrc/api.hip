@@ -1,5 +1,5 @@
 // C ABI entry points: host-side argument validation, workspace carving and
-// dispatch to the kernels of solve.hip, sort.hip and gather.hip.
+// dispatch to the kernels of solve.hip, sort.hip, gather.hip and tile.hip.
 #include <math.h>
 #include <mutex>
 
@@ -37,10 +37,12 @@ pt_status scatter_back(int64_t np, const double* in, const int32_t* perm, double
 // tile.hip
 int64_t tile_nlayers(const pt_grid* g);
 pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
-                       int64_t np, double dt, const double* x, double* x_out, hipStream_t s);
+                       int64_t np, double dt, const double* x, double* x_out, void* defer,
+                       hipStream_t s);
 pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, const double* lam, double* xbn,
-                       float* u0, float* ub0, float* gcoeff, hipStream_t s);
+                       float* u0, float* ub0, float* gcoeff, void* defer, hipStream_t s);
+size_t tile_defer_bytes(int64_t np);
 
 // One non-finite-position flag per device, in the library's static device
 // memory; kernels receive its device address.
@@ -104,11 +106,12 @@ struct Rk2Ws {
   int32_t* ids_tmp;
   float* u0;
   int32_t* lstart;
+  void* defer;
 };
 
 static size_t rk2_ws_bytes(const pt_grid* g, int64_t np) {
   return a256(sort_ws_bytes(g, np)) + a256(24 * (size_t)np) + 2 * a256(4 * (size_t)np) +
-         a256(12 * (size_t)np) + a256(lstart_bytes(g));
+         a256(12 * (size_t)np) + a256(lstart_bytes(g)) + a256(tile_defer_bytes(np));
 }
 
 static Rk2Ws carve_rk2(const pt_grid* g, int64_t np, void* ws) {
@@ -119,7 +122,8 @@ static Rk2Ws carve_rk2(const pt_grid* g, int64_t np, void* ws) {
   w.perm = (int32_t*)p; p += a256(4 * (size_t)np);
   w.ids_tmp = (int32_t*)p; p += a256(4 * (size_t)np);
   w.u0 = (float*)p; p += a256(12 * (size_t)np);
-  w.lstart = (int32_t*)p;
+  w.lstart = (int32_t*)p; p += a256(lstart_bytes(g));
+  w.defer = p;
   return w;
 }
 
@@ -132,11 +136,12 @@ struct Rk2BwdWs {
   float* u0;
   float* ub0;
   int32_t* lstart;
+  void* defer;
 };
 
 static size_t rk2_bwd_ws_bytes(const pt_grid* g, int64_t np) {
   return a256(sort_ws_bytes(g, np)) + 3 * a256(24 * (size_t)np) + a256(4 * (size_t)np) +
-         2 * a256(12 * (size_t)np) + a256(lstart_bytes(g));
+         2 * a256(12 * (size_t)np) + a256(lstart_bytes(g)) + a256(tile_defer_bytes(np));
 }
 
 static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, void* ws) {
@@ -149,7 +154,8 @@ static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, void* ws) {
   w.perm = (int32_t*)p; p += a256(4 * (size_t)np);
   w.u0 = (float*)p; p += a256(12 * (size_t)np);
   w.ub0 = (float*)p; p += a256(12 * (size_t)np);
-  w.lstart = (int32_t*)p;
+  w.lstart = (int32_t*)p; p += a256(lstart_bytes(g));
+  w.defer = p;
   return w;
 }
 
@@ -266,7 +272,7 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
       PT_TRY(permute_ids(np, ids, w.perm, w.ids_tmp, stream));
       PT_HIP_CHECK(hipMemcpyAsync(ids, w.ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
     }
-    return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, pos, stream);
+    return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, pos, w.defer, stream);
   }
   return rk2_advance(grid, coeff, dtype, np, dt, pos, pos, w.u0, stream);
 }
@@ -301,7 +307,7 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
     PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
                           stream));
     PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, g_pos, w.xbn, w.u0,
-                        w.ub0, g_coeff, stream));
+                        w.ub0, g_coeff, w.defer, stream));
     return scatter_back(np, w.xbn, w.perm, g_pos, stream);
   }
   return rk2_backward(grid, coeff, dtype, np, dt, pos_n, g_pos, g_pos, g_coeff, w.u0, w.xbs,

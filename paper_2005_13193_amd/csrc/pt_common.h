@@ -50,11 +50,17 @@ __device__ __forceinline__ int cell_1d(double x, double cs, int n, double* t, bo
   }
   const double dn = (double)n;
   double s = x * cs;
-  double k = floor(s / dn);
-  double kn = k * dn;
-  double sw = s - kn;
-  if (sw < 0.0) sw = sw + dn;
-  if (sw >= dn) sw = sw - dn;
+  double sw = s;
+  // Inside the primary domain floor(s / n) is 0 (a quotient that rounds up to
+  // 1 is corrected back by the second test), so the division is only needed
+  // outside it; both branches give the same bits.
+  if (!(s >= 0.0 && s < dn)) {
+    double k = floor(s / dn);
+    double kn = k * dn;
+    sw = s - kn;
+    if (sw < 0.0) sw = sw + dn;
+    if (sw >= dn) sw = sw - dn;
+  }
   double fa = floor(sw);
   *t = sw - fa;
   int a = (int)fa;

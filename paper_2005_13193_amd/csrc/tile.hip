@@ -2,42 +2,60 @@
 //
 // After pt_sort_particles the particles of a column of kTileX x kTileY cells
 // are contiguous and ordered by layer z.  One workgroup takes one column over
-// a range of layers and marches up in z with a ring of kRing padded
-// coefficient planes of the column's (kTileX+3) x (kTileY+3) tile staged in
-// LDS, so that every coefficient is read from HBM about once per column
-// (plus the three shared halo rows/columns and the planes at segment
-// boundaries).  Per slab of kSlab layers the ring holds planes z-1 .. z+5:
-// the stencils of the particles of the slab and of points up to one layer
-// away (the RK2 predictor moves a particle by at most ~0.6 cell per step).
-// Points whose stencil is not in the ring (they left the column or moved
-// more than one layer) are evaluated from global memory instead.
+// a segment of layers and marches up in z with a ring of kRing padded
+// coefficient planes of the column's tile staged in LDS, so that every
+// coefficient is read from HBM about once per column (plus the three shared
+// halo rows/columns and the planes at segment ends).  Per slab of kSlab
+// layers the ring holds planes z-1 .. z+5: the stencils of the particles of
+// the slab and of points up to one layer away (the RK2 predictor moves a
+// particle by at most ~0.6 cell per step).  Points whose stencil is not in
+// the ring (they left the column or moved more than one layer) take a slow
+// path from global memory.
+//
+// Latency: the load queue of a wave retires in order, so waiting on one load
+// waits on every older one.  Every iteration therefore issues its prefetch
+// (plane data and first-pass particle data for the next-but-one slab) at its
+// very end, after all loads it waits on itself.
 //
 // Four lanes evaluate one point: lane i holds the x-offset i of the 4x4x4
-// stencil, sums the 16 (y, z) rows for each component, and the four partial
-// sums are combined with quad DPP moves.
+// stencil, sums the 16 (y, z) rows for each component, and the partial sums
+// are combined with quad DPP moves.
 #include "pt_common.h"
 
 namespace pt {
 
-constexpr int kTB = 512;                 // threads per workgroup
-constexpr int kGroups = kTB / 4;         // points in flight per pass
-constexpr int kTW = kTileX + 3;          // tile width in padded points (35)
-constexpr int kTH = kTileY + 3;          // tile height (35)
-constexpr int kRing = 8;                 // LDS plane slots (power of two)
-constexpr int kSlab = 2;                 // layers per iteration
-constexpr int kRowP = 36;                // LDS row pitch (floats)
-constexpr int kCompP = kTH * kRowP + 4;  // LDS component pitch
-constexpr int kSlotP = 3 * kCompP + 4;   // LDS plane-slot pitch
-constexpr int kPlaneElems = 3 * kTW * kTH;
-constexpr int kPerThread = (kPlaneElems + kTB - 1) / kTB;  // 8
-constexpr int kLayerShift = 10;          // log2(kTileX * kTileY)
-static_assert(kTileX * kTileY == (1 << kLayerShift), "layer shift");
+constexpr int kTB = 512;          // threads per workgroup
+constexpr int kGroups = kTB / 4;  // points per pass
+constexpr int kRing = 8;          // LDS plane slots (power of two)
+constexpr int kSlab = 2;          // layers per iteration
+constexpr int kGatherSeg = 128;   // layers per gather work item
+constexpr int kScatterSeg = 256;  // layers per scatter work item
+// The particle table indexes half-layers: the rows 0..15 and 16..31 of a
+// column layer (key >> 9 with 32 x 32 columns).
+constexpr int kHalfShift = 9;     // log2(kTileX * kTileY / 2)
+constexpr int kMaxSlots = 64;     // slots for the largest |ub| (see zero_int)
+constexpr int kDeferHeader = 512; // bytes before the deferred list
+static_assert(kTileX * kTileY == (2 << kHalfShift), "half-layer shift");
+
+// Tile geometry with an M-cell margin around the column in x and y.
+template <int M>
+struct Geo {
+  static constexpr int TW = kTileX + 3 + 2 * M;  // tile width in padded points
+  static constexpr int TH = kTileY + 3 + 2 * M;
+  static constexpr int RowP = TW + 1;
+  static constexpr int CompP = TH * RowP + 4;
+  static constexpr int SlotP = 3 * CompP + 4;
+  static constexpr int Elems = 3 * TW * TH;
+  static constexpr int PerThread = (Elems + kTB - 1) / kTB;
+  static constexpr int RingFloats = kRing * SlotP;
+};
 
 struct TileArgs {
   GridDev g;
   const void* coeff;
   const int32_t* lstart;  // [ncol * nz + 1]: first particle of each (column, layer)
-  int ncx, ncol, nseg, seg_len;
+  int ncx, ncy, ncol, nseg, seg_len;
+  int color;              // scatter: parities (cx, cy, segment) of this launch
   int64_t np;
   double dt;
   const double* x;        // [3][np] positions (sorted)
@@ -47,24 +65,10 @@ struct TileArgs {
   float* u0;              // bwd: stage-1 velocity  [3][np]
   float* ub0;             // bwd: adjoint of stage-1 velocity [3][np]
   float* gcoeff;          // scatter target (padded FP32)
+  uint32_t* defer;        // scatter: deferred stencils (2 p + stage)
+  int* defer_count;
   int* err;
 };
-
-// Work item of a block: column and first/last layer.  Blocks are dealt to the
-// 8 XCDs round-robin; item numbers are remapped so that each XCD walks a
-// contiguous run of neighbouring columns (shared halos stay in its L2).
-__device__ __forceinline__ void work_item(const TileArgs& a, int* col, int* z0, int* z1) {
-  const int nitems = a.ncol * a.nseg;
-  const int b = blockIdx.x;
-  const int per = (nitems + 7) / 8;
-  int item = (b & 7) * per + (b >> 3);
-  if ((b & 7) * per + (b >> 3) >= nitems || (b >> 3) >= per) item = -1;
-  if (item < 0) { *col = -1; return; }
-  const int seg = item / a.ncol;
-  *col = item - seg * a.ncol;
-  *z0 = seg * a.seg_len;
-  *z1 = min(*z0 + a.seg_len, a.g.nz);
-}
 
 __device__ __forceinline__ float quad_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
@@ -72,38 +76,56 @@ __device__ __forceinline__ float quad_sum(float v) {
   return v;
 }
 
+__device__ __forceinline__ float pick4(const float w[4], int i) {
+  return i == 0 ? w[0] : i == 1 ? w[1] : i == 2 ? w[2] : w[3];
+}
+
 // ------------------------------------------------------ plane staging ---
-template <typename CT>
-struct PlaneLoader {
-  const CT* coeff;
-  int64_t comp_stride, plane;
-  int px, py, X0, Y0;
+// Thread-to-element map of one tile plane: element e = tid + q * kTB is
+// component c, row y, column x.  Every load is issued (addresses clamped into
+// the array) so that each iteration issues the same number of loads.
+template <int M>
+__device__ __forceinline__ void plane_elem(int q, int* c, int* y, int* x, bool* in) {
+  using G = Geo<M>;
+  int e = threadIdx.x + q * kTB;
+  *in = e < G::Elems;
+  e = *in ? e : G::Elems - 1;
+  *c = e / (G::TW * G::TH);
+  const int r = e - *c * (G::TW * G::TH);
+  *y = r / G::TW;
+  *x = r - *y * G::TW;
+}
 
-  __device__ __forceinline__ void load(int P, int npad, float v[kPerThread]) const {
+template <typename CT, int M>
+__device__ __forceinline__ void load_plane(const CT* coeff, const GridDev& g, int X0, int Y0,
+                                           int P, float* v) {
+  using G = Geo<M>;
+  const int npad = g.nz + 3;
+  const bool pok = P >= 0 && P < npad;
+  const int Pc = min(max(P, 0), npad - 1);
 #pragma unroll
-    for (int q = 0; q < kPerThread; ++q) {
-      const int e = threadIdx.x + q * kTB;
-      const int c = e / (kTW * kTH);
-      const int r = e - c * (kTW * kTH);
-      const int y = r / kTW, x = r - y * kTW;
-      const bool ok = e < kPlaneElems && P >= 0 && P < npad && X0 + x < px && Y0 + y < py;
-      v[q] = ok ? load_coeff(coeff + c * comp_stride + (int64_t)P * plane +
-                             (int64_t)(Y0 + y) * px + (X0 + x))
-                : 0.0f;
-    }
+  for (int q = 0; q < G::PerThread; ++q) {
+    int c, y, x;
+    bool in;
+    plane_elem<M>(q, &c, &y, &x, &in);
+    const int X = X0 + x, Y = Y0 + y;
+    const bool ok = in && pok && X >= 0 && X < g.px && Y >= 0 && Y < g.py;
+    const int Xc = min(max(X, 0), g.px - 1), Yc = min(max(Y, 0), g.py - 1);
+    const float t =
+        load_coeff(coeff + c * g.comp + (int64_t)Pc * g.plane + (int64_t)Yc * g.px + Xc);
+    v[q] = ok ? t : 0.0f;
   }
-};
+}
 
-__device__ __forceinline__ void store_plane(float* lds, int slot, const float v[kPerThread]) {
+template <int M>
+__device__ __forceinline__ void store_plane(float* lds, int slot, const float* v) {
+  using G = Geo<M>;
 #pragma unroll
-  for (int q = 0; q < kPerThread; ++q) {
-    const int e = threadIdx.x + q * kTB;
-    if (e < kPlaneElems) {
-      const int c = e / (kTW * kTH);
-      const int r = e - c * (kTW * kTH);
-      const int y = r / kTW, x = r - y * kTW;
-      lds[slot * kSlotP + c * kCompP + y * kRowP + x] = v[q];
-    }
+  for (int q = 0; q < G::PerThread; ++q) {
+    int c, y, x;
+    bool in;
+    plane_elem<M>(q, &c, &y, &x, &in);
+    if (in) lds[slot * G::SlotP + c * G::CompP + y * G::RowP + x] = v[q];
   }
 }
 
@@ -114,6 +136,9 @@ struct Pt {
   bool in_ring;    // stencil resident in LDS
 };
 
+// X0, Y0: padded index of LDS column/row 0; cells a with a - X0 in
+// [0, kTileX + 2M) have their 4x4 stencil columns inside the tile.
+template <int M>
 __device__ __forceinline__ Pt locate_pt(const GridDev& g, const double p[3], int X0, int Y0,
                                         int zlo, int zhi, int* err) {
   Pt q;
@@ -127,15 +152,17 @@ __device__ __forceinline__ Pt locate_pt(const GridDev& g, const double p[3], int
   q.t[1] = (float)t1;
   q.t[2] = (float)t2;
   const int lx = q.a - X0, ly = q.b - Y0;
-  q.in_ring = lx >= 0 && lx < kTileX && ly >= 0 && ly < kTileY && q.c >= zlo && q.c <= zhi;
+  q.in_ring = lx >= 0 && lx < kTileX + 2 * M && ly >= 0 && ly < kTileY + 2 * M && q.c >= zlo &&
+              q.c <= zhi;
   return q;
 }
 
 // Value (GRAD: and gradient) of the three components at a resident point;
 // every lane of the quad returns the full result.
-template <bool GRAD>
+template <int M, bool GRAD>
 __device__ __forceinline__ void eval_lds(const float* lds, const GridDev& g, const Pt& q, int X0,
                                          int Y0, int lane, float out[12]) {
+  using G = Geo<M>;
   float wx[4], wy[4], wz[4], dwx[4], dwy[4], dwz[4];
   bspline_w(q.t[0], wx);
   bspline_w(q.t[1], wy);
@@ -145,9 +172,8 @@ __device__ __forceinline__ void eval_lds(const float* lds, const GridDev& g, con
     bspline_dw(q.t[1], dwy);
     bspline_dw(q.t[2], dwz);
   }
-  const float wxi = lane == 0 ? wx[0] : lane == 1 ? wx[1] : lane == 2 ? wx[2] : wx[3];
-  float dwxi = 0.f;
-  if (GRAD) dwxi = lane == 0 ? dwx[0] : lane == 1 ? dwx[1] : lane == 2 ? dwx[2] : dwx[3];
+  const float wxi = pick4(wx, lane);
+  const float dwxi = GRAD ? pick4(dwx, lane) : 0.0f;
   const int col = (q.a - X0) + lane;
   const int row0 = q.b - Y0;
 #pragma unroll
@@ -155,11 +181,11 @@ __device__ __forceinline__ void eval_lds(const float* lds, const GridDev& g, con
     float A = 0.f, B = 0.f, C = 0.f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const float* pl = lds + ((q.c + k) & (kRing - 1)) * kSlotP + comp * kCompP + col;
+      const float* pl = lds + ((q.c + k) & (kRing - 1)) * G::SlotP + comp * G::CompP + col;
       float sy = 0.f, sdy = 0.f;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const float s = pl[(row0 + j) * kRowP];
+        const float s = pl[(row0 + j) * G::RowP];
         sy += wy[j] * s;
         if (GRAD) sdy += dwy[j] * s;
       }
@@ -178,8 +204,7 @@ __device__ __forceinline__ void eval_lds(const float* lds, const GridDev& g, con
   }
 }
 
-// Same quantity from global memory (points outside the ring; rare, so kept
-// out of line).
+// Same quantity from global memory (points outside the ring).
 template <typename CT, bool GRAD>
 __device__ __forceinline__ void eval_global(const CT* __restrict__ coeff, const GridDev& g,
                                             const Pt& q, float out[12]) {
@@ -228,30 +253,144 @@ __device__ __forceinline__ void eval_global(const CT* __restrict__ coeff, const 
 template <typename CT, bool GRAD>
 __device__ __forceinline__ void eval_point(const float* lds, const CT* coeff, const GridDev& g,
                                            const Pt& q, int X0, int Y0, int lane, float out[12]) {
-  if (q.in_ring) eval_lds<GRAD>(lds, g, q, X0, Y0, lane, out);
+  if (q.in_ring) eval_lds<0, GRAD>(lds, g, q, X0, Y0, lane, out);
   else eval_global<CT, GRAD>(coeff, g, q, out);
 }
 
 // ------------------------------------------------------- gather kernels ---
+// The gather ring holds kGRing dense planes [3][kTileY+3][kTileX+3] of 32-bit
+// words (FP32 values, or BF16 bits in the low half).  Two loader waves fill it
+// with direct global-to-LDS loads; eight compute waves only read it.  The
+// load queue of a wave retires in order, so keeping the plane loads in waves
+// of their own means the compute waves never wait on them, and the loaders
+// wait for exactly their own loads before the barrier that publishes them.
+constexpr int kGRing = 10;                     // planes z-1 .. z+7 in use + spare
+constexpr int kGTW = kTileX + 3, kGTH = kTileY + 3;
+constexpr int kGComp = kGTW * kGTH;            // 1225 words per component
+constexpr int kGSlot = 3 * kGComp + 5;         // slot pitch (words)
+constexpr int kCompute = 512;                  // compute threads (8 waves)
+constexpr int kLoaders = 2;                    // loader waves
+constexpr int kGTB = kCompute + 64 * kLoaders;
+constexpr int kGChunks = (kGComp + 63) / 64;   // 64-word chunks per component (20)
+constexpr int kGChunksPerLoader = (kGChunks + kLoaders - 1) / kLoaders;
+constexpr int kGGroups = kCompute / 4;
+
 enum { TILE_RK2_FWD = 0, TILE_RK2_BWD_GRAD = 1 };
 
-template <typename CT, int MODE>
-__device__ __forceinline__ void process_particle(const TileArgs& a, const float* lds, int64_t p,
-                                                 int X0, int Y0, int zz, int lane) {
-  const GridDev& g = a.g;
-  const CT* coeff = (const CT*)a.coeff;
+__device__ __forceinline__ int gslot(int P) { return (P + kGRing) % kGRing; }
+
+template <typename CT>
+__device__ __forceinline__ float ring_val(const uint32_t* w);
+template <>
+__device__ __forceinline__ float ring_val<float>(const uint32_t* w) { return __uint_as_float(*w); }
+template <>
+__device__ __forceinline__ float ring_val<uint16_t>(const uint32_t* w) {
+  return __uint_as_float(*w << 16);
+}
+
+// Value (GRAD: and gradient) at a resident point; every lane of the quad
+// returns the full result.
+template <typename CT, bool GRAD>
+__device__ __forceinline__ void eval_ring(const uint32_t* ring, const GridDev& g, const Pt& q,
+                                          int X0, int Y0, int lane, float out[12]) {
+  float wx[4], wy[4], wz[4], dwx[4], dwy[4], dwz[4];
+  bspline_w(q.t[0], wx);
+  bspline_w(q.t[1], wy);
+  bspline_w(q.t[2], wz);
+  if (GRAD) {
+    bspline_dw(q.t[0], dwx);
+    bspline_dw(q.t[1], dwy);
+    bspline_dw(q.t[2], dwz);
+  }
+  const float wxi = pick4(wx, lane);
+  const float dwxi = GRAD ? pick4(dwx, lane) : 0.0f;
+  const int off = (q.b - Y0) * kGTW + (q.a - X0) + lane;
+  int sl[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sl[k] = gslot(q.c + k) * kGSlot + off;
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    float A = 0.f, B = 0.f, C = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t* pl = ring + sl[k] + comp * kGComp;
+      float sy = 0.f, sdy = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float v = ring_val<CT>(pl + j * kGTW);
+        sy += wy[j] * v;
+        if (GRAD) sdy += dwy[j] * v;
+      }
+      A += wz[k] * sy;
+      if (GRAD) {
+        B += wz[k] * sdy;
+        C += dwz[k] * sy;
+      }
+    }
+    out[comp] = quad_sum(wxi * A);
+    if (GRAD) {
+      out[3 + 3 * comp + 0] = quad_sum(dwxi * A) * g.inv_h[0];
+      out[3 + 3 * comp + 1] = quad_sum(wxi * B) * g.inv_h[1];
+      out[3 + 3 * comp + 2] = quad_sum(wxi * C) * g.inv_h[2];
+    }
+  }
+}
+
+// Per-particle data of one pass.
+struct PData {
+  double x[3];
+  double lam[3];
+  int p;
+  bool ok;
+};
+
+template <int MODE>
+__device__ __forceinline__ void load_pdata(const TileArgs& a, int64_t p, bool ok, PData* d) {
   const int64_t np = a.np;
-  double xn[3] = {a.x[p], a.x[np + p], a.x[2 * np + p]};
-  // resident layers of cells: zz-1 .. zz+2 (planes zz-1 .. zz+5)
-  const Pt qn = locate_pt(g, xn, X0, Y0, zz - 1, zz + kSlab, a.err);
+  const int64_t i = ok ? p : 0;  // always a valid address: the load is always issued
+  d->ok = ok;
+  d->p = (int)p;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) d->x[c] = a.x[c * np + i];
+  if (MODE == TILE_RK2_BWD_GRAD) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d->lam[c] = a.lam[c * np + i];
+  }
+}
+
+__device__ __forceinline__ void defer_particle(int* count, int32_t* list, int64_t np, int p) {
+  const int i = atomicAdd(count, 1);
+  if ((int64_t)i < np) list[i] = p;
+}
+
+// Both Heun stages (forward) or the whole step adjoint (backward) of one
+// particle from the ring.  A particle whose predictor point is not resident is
+// deferred to the cleanup kernel, which redoes it from global memory.
+template <typename CT, int MODE>
+__device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t* ring,
+                                              const PData& d, int X0, int Y0, int zz, int lane,
+                                              float* umax) {
+  const GridDev& g = a.g;
+  const int64_t np = a.np, p = d.p;
+  const double* xn = d.x;
+  // resident cells: layers zz-1 .. zz+kSlab (planes zz-1 .. zz+5)
+  const Pt qn = locate_pt<0>(g, xn, X0, Y0, zz - 1, zz + kSlab, a.err);
+  if (!qn.in_ring) {  // cannot happen for a correctly sorted particle; kept safe
+    if (lane == 0) defer_particle(a.defer_count, (int32_t*)a.defer, np, d.p);
+    return;
+  }
   if (MODE == TILE_RK2_FWD) {
     float u0[12], u1[12];
-    eval_point<CT, false>(lds, coeff, g, qn, X0, Y0, lane, u0);
+    eval_ring<CT, false>(ring, g, qn, X0, Y0, lane, u0);
     double xs[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xs[d] = xn[d] + a.dt * (double)u0[d];
-    const Pt qs = locate_pt(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
-    eval_point<CT, false>(lds, coeff, g, qs, X0, Y0, lane, u1);
+    for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)u0[c];
+    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
+    if (!qs.in_ring) {
+      if (lane == 0) defer_particle(a.defer_count, (int32_t*)a.defer, np, d.p);
+      return;
+    }
+    eval_ring<CT, false>(ring, g, qs, X0, Y0, lane, u1);
     if (lane < 3) {
       const double h = 0.5 * a.dt;
       const double x0 = lane == 0 ? xn[0] : lane == 1 ? xn[1] : xn[2];
@@ -260,204 +399,587 @@ __device__ __forceinline__ void process_particle(const TileArgs& a, const float*
       a.x_out[lane * np + p] = x0 + h * ((double)ua + (double)ub);
     }
   } else {
-    // adjoint of a Heun step: J(x^n) and u0 at x^n, then J(x*) at x*
     float on[12], os[12];
-    eval_point<CT, true>(lds, coeff, g, qn, X0, Y0, lane, on);
-    double xs[3], lam[3];
+    eval_ring<CT, true>(ring, g, qn, X0, Y0, lane, on);
+    double xs[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      xs[d] = xn[d] + a.dt * (double)on[d];
-      lam[d] = a.lam[d * np + p];
+    for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)on[c];
+    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
+    if (!qs.in_ring) {
+      if (lane == 0) defer_particle(a.defer_count, (int32_t*)a.defer, np, d.p);
+      return;
     }
-    const Pt qs = locate_pt(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
-    eval_point<CT, true>(lds, coeff, g, qs, X0, Y0, lane, os);
+    eval_ring<CT, true>(ring, g, qs, X0, Y0, lane, os);
+    const double* lam = d.lam;
     float ub1[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) ub1[d] = (float)(0.5 * a.dt * lam[d]);
-    double xbs[3], ub0d[3];
+    for (int c = 0; c < 3; ++c) ub1[c] = (float)(0.5 * a.dt * lam[c]);
+    double xbs[3], xb[3];
+    float ub0[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      xbs[d] = (double)(ub1[0] * os[3 + d] + ub1[1] * os[6 + d] + ub1[2] * os[9 + d]);
-      ub0d[d] = 0.5 * a.dt * lam[d] + a.dt * xbs[d];
+    for (int c = 0; c < 3; ++c) {
+      xbs[c] = (double)(ub1[0] * os[3 + c] + ub1[1] * os[6 + c] + ub1[2] * os[9 + c]);
+      ub0[c] = (float)(0.5 * a.dt * lam[c] + a.dt * xbs[c]);
     }
-    float ub0[3] = {(float)ub0d[0], (float)ub0d[1], (float)ub0d[2]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xb[c] = lam[c] + xbs[c] +
+              (double)(ub0[0] * on[3 + c] + ub0[1] * on[6 + c] + ub0[2] * on[9 + c]);
+      *umax = fmaxf(*umax, fmaxf(fabsf(ub0[c]), fabsf(ub1[c])));
+    }
+    // lane c < 3 writes component c (selects, not indexing: register arrays
+    // indexed by a lane-dependent value would live in scratch memory)
     if (lane < 3) {
-      const int d = lane;
-      const double xb = lam[d] + xbs[d] +
-                        (double)(ub0[0] * on[3 + d] + ub0[1] * on[6 + d] + ub0[2] * on[9 + d]);
-      a.xbn[d * np + p] = xb;
-      a.u0[d * np + p] = d == 0 ? on[0] : d == 1 ? on[1] : on[2];
-      a.ub0[d * np + p] = ub0[d];
+      const int c = lane;
+      a.xbn[c * np + p] = c == 0 ? xb[0] : c == 1 ? xb[1] : xb[2];
+      a.u0[c * np + p] = c == 0 ? on[0] : c == 1 ? on[1] : on[2];
+      a.ub0[c * np + p] = c == 0 ? ub0[0] : c == 1 ? ub0[1] : ub0[2];
     }
   }
 }
 
+// Work item of a gather block.  Blocks are dealt to the 8 XCDs round-robin;
+// item numbers are remapped so that each XCD walks a contiguous run of
+// neighbouring columns of one segment (their shared halos stay in its L2).
+__device__ __forceinline__ bool gather_item(const TileArgs& a, int* col, int* z0, int* z1) {
+  const int nitems = a.ncol * a.nseg;
+  const int b = blockIdx.x;
+  const int per = (nitems + 7) / 8;
+  const int item = (b & 7) * per + (b >> 3);
+  if ((b >> 3) >= per || item >= nitems) return false;
+  const int seg = item / a.ncol;
+  *col = item - seg * a.ncol;
+  *z0 = seg * a.seg_len;
+  *z1 = min(*z0 + a.seg_len, a.g.nz);
+  return true;
+}
+
+// Loader side: per lane the in-plane offsets of its chunks (same for every
+// plane and component), then one direct-to-LDS load per chunk.
+template <typename CT>
+struct RingLoader {
+  int rel[kGChunksPerLoader];
+  bool act[kGChunksPerLoader];
+  int chunk0;
+
+  __device__ __forceinline__ void init(const GridDev& g, int X0, int Y0, int loader, int lane) {
+    chunk0 = loader;
+#pragma unroll
+    for (int m = 0; m < kGChunksPerLoader; ++m) {
+      const int c = loader + kLoaders * m;
+      const int r = 64 * c + lane;
+      act[m] = c < kGChunks && r < kGComp;
+      const int rr = min(r, kGComp - 1);
+      const int y = rr / kGTW, x = rr - y * kGTW;
+      const int X = min(X0 + x, g.px - 1), Y = min(Y0 + y, g.py - 1);
+      rel[m] = Y * g.px + X;
+    }
+  }
+
+  __device__ __forceinline__ void load(const CT* coeff, const GridDev& g, uint32_t* ring,
+                                       int P) const {
+    const int Pc = min(max(P, 0), g.nz + 2);
+    uint32_t* slot = ring + gslot(P) * kGSlot;
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      const CT* base = coeff + comp * g.comp + (int64_t)Pc * g.plane;
+#pragma unroll
+      for (int m = 0; m < kGChunksPerLoader; ++m) {
+        const int c = chunk0 + kLoaders * m;
+        if (c < kGChunks && act[m]) {
+          const auto* src = (const __attribute__((address_space(1))) void*)(base + rel[m]);
+          auto* dst = (__attribute__((address_space(3))) void*)(slot + comp * kGComp + 64 * c);
+          if constexpr (sizeof(CT) == 4) __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
+          else __builtin_amdgcn_global_load_lds(src, dst, 2, 0, 0);
+        }
+      }
+    }
+  }
+};
+
+// s_waitcnt vmcnt(0) with the other counters left alone
+#define PT_WAIT_VMCNT0() __builtin_amdgcn_s_waitcnt(0x0F70)
+
 template <typename CT, int MODE>
-__global__ __launch_bounds__(kTB) void tile_gather(TileArgs a) {
-  extern __shared__ float lds[];
+__global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
+  extern __shared__ uint32_t gsm[];
+  uint32_t* ring = gsm;
+  int* lst = (int*)(gsm + kGRing * kGSlot);  // layer starts of the segment
   int col, z0, z1;
-  work_item(a, &col, &z0, &z1);
-  if (col < 0) return;
+  if (!gather_item(a, &col, &z0, &z1)) return;
   const GridDev& g = a.g;
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
   const int X0 = cx * kTileX, Y0 = cy * kTileY;
-  const int npad = g.nz + 3;
-  PlaneLoader<CT> ld{(const CT*)a.coeff, g.comp, g.plane, g.px, g.py, X0, Y0};
-  const int lane = threadIdx.x & 3, grp = threadIdx.x >> 2;
-  const int32_t* ls = a.lstart + (int64_t)col * g.nz;
+  const int wave = threadIdx.x >> 6;
+  const bool loader = wave >= kCompute / 64;
+  const int nl = z1 - z0;
+  const int32_t* ls = a.lstart + 2 * ((int64_t)col * g.nz + z0);
+  const CT* coeff = (const CT*)a.coeff;
 
-  // prologue: planes z0-1 .. z0+5
-  {
-    float v[kPerThread];
-    for (int P = z0 - 1; P <= z0 + 5; ++P) {
-      ld.load(P, npad, v);
-      store_plane(lds, P & (kRing - 1), v);
-    }
+  RingLoader<CT> rl;
+  if (loader) {
+    rl.init(g, X0, Y0, wave - kCompute / 64, threadIdx.x & 63);
+    for (int P = z0 - 1; P <= z0 + 5; ++P) rl.load(coeff, g, ring, P);
+    PT_WAIT_VMCNT0();
+  } else {
+    for (int i = threadIdx.x; i <= nl; i += kCompute) lst[i] = ls[2 * i];
   }
-  float va[2][kPerThread], vb[2][kPerThread];
-  ld.load(z0 + 6, npad, va[0]);
-  ld.load(z0 + 7, npad, va[1]);
-  ld.load(z0 + 8, npad, vb[0]);
-  ld.load(z0 + 9, npad, vb[1]);
+  __syncthreads();
 
-  for (int zz = z0; zz < z1; zz += 2 * kSlab) {
+  const int lane = threadIdx.x & 3, grp = threadIdx.x >> 2;
+  PData pd[2];
+  auto prefetch = [&](int set, int s) {
+    const int zs = z0 + s * kSlab;
+    int64_t pb = 0, pe = 0;
+    if (zs < z1) {
+      pb = lst[zs - z0];
+      pe = lst[min(zs + kSlab, z1) - z0];
+    }
+    load_pdata<MODE>(a, pb + grp, pb + grp < pe, &pd[set]);
+  };
+  float umax = 0.0f;  // largest |ub| of this thread's particles (adjoint)
+  if (!loader) {
+    prefetch(0, 0);
+    prefetch(1, 1);
+  }
+  for (int s0 = 0; z0 + s0 * kSlab < z1; s0 += 2) {
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      const int zs = zz + half * kSlab;
+      const int s = s0 + half;
+      const int zs = z0 + s * kSlab;
       if (zs < z1) {
+        if (loader) {
+          // planes for the next slab go into the slots of zs-4, zs-3
+          rl.load(coeff, g, ring, zs + 6);
+          rl.load(coeff, g, ring, zs + 7);
+          PT_WAIT_VMCNT0();
+        } else {
+          const int64_t pb = lst[zs - z0];
+          const int64_t pe = lst[min(zs + kSlab, z1) - z0];
+          // passes of kGGroups particles; the data of pass k+1 is loaded
+          // (always, clamped) before pass k is processed
+          const int npass = (int)((pe - pb + kGGroups - 1) / kGGroups);
+          PData cur = pd[half];
+          for (int k = 0; k < npass; ++k) {
+            PData nxt;
+            const int64_t pn = pb + (int64_t)(k + 1) * kGGroups + grp;
+            load_pdata<MODE>(a, pn, pn < pe, &nxt);
+            if (cur.ok) ring_particle<CT, MODE>(a, ring, cur, X0, Y0, zs, lane, &umax);
+            cur = nxt;
+          }
+          prefetch(half, s + 2);
+        }
         __syncthreads();
-        const int64_t pb = ls[zs];
-        const int64_t pe = ls[min(zs + kSlab, z1)];
-        for (int64_t p = pb + grp; p < pe; p += kGroups)
-          process_particle<CT, MODE>(a, lds, p, X0, Y0, zs, lane);
-        __syncthreads();
-        float (*v)[kPerThread] = half == 0 ? va : vb;
-        store_plane(lds, (zs + 6) & (kRing - 1), v[0]);
-        store_plane(lds, (zs + 7) & (kRing - 1), v[1]);
-        ld.load(zs + 10, npad, v[0]);
-        ld.load(zs + 11, npad, v[1]);
       }
+    }
+  }
+  if (MODE == TILE_RK2_BWD_GRAD) {
+    // block maximum of |ub| for the fixed-point scale of the scatter
+    float* smax = (float*)(lst + a.seg_len + 4);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) umax = fmaxf(umax, __shfl_xor(umax, o, 64));
+    if ((threadIdx.x & 63) == 0) smax[wave] = umax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float m = 0.0f;
+      for (int w = 0; w < kGTB / 64; ++w) m = fmaxf(m, smax[w]);
+      atomicMax(a.defer_count + 1 + (blockIdx.x & (kMaxSlots - 1)), __float_as_int(m));
+    }
+  }
+}
+
+// Particles deferred by tile_gather, redone from global memory.
+template <typename CT, int MODE>
+__global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
+  const int64_t n = min((int64_t)*a.defer_count, a.np);
+  const GridDev& g = a.g;
+  const CT* coeff = (const CT*)a.coeff;
+  const int64_t np = a.np;
+  const int32_t* list = (const int32_t*)a.defer;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t p = list[i];
+    if (p < 0 || p >= np) continue;
+    double xn[3] = {a.x[p], a.x[np + p], a.x[2 * np + p]};
+    const Pt qn = locate_pt<0>(g, xn, 0, 0, 0, -1, a.err);
+    if (MODE == TILE_RK2_FWD) {
+      float u0[12], u1[12];
+      eval_global<CT, false>(coeff, g, qn, u0);
+      double xs[3];
+      for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)u0[c];
+      const Pt qs = locate_pt<0>(g, xs, 0, 0, 0, -1, a.err);
+      eval_global<CT, false>(coeff, g, qs, u1);
+      for (int c = 0; c < 3; ++c)
+        a.x_out[c * np + p] = xn[c] + 0.5 * a.dt * ((double)u0[c] + (double)u1[c]);
+    } else {
+      float on[12], os[12];
+      eval_global<CT, true>(coeff, g, qn, on);
+      double xs[3], lam[3];
+      for (int c = 0; c < 3; ++c) {
+        xs[c] = xn[c] + a.dt * (double)on[c];
+        lam[c] = a.lam[c * np + p];
+      }
+      const Pt qs = locate_pt<0>(g, xs, 0, 0, 0, -1, a.err);
+      eval_global<CT, true>(coeff, g, qs, os);
+      float ub1[3];
+      for (int c = 0; c < 3; ++c) ub1[c] = (float)(0.5 * a.dt * lam[c]);
+      double xbs[3];
+      float ub0[3];
+      for (int c = 0; c < 3; ++c) {
+        xbs[c] = (double)(ub1[0] * os[3 + c] + ub1[1] * os[6 + c] + ub1[2] * os[9 + c]);
+        ub0[c] = (float)(0.5 * a.dt * lam[c] + a.dt * xbs[c]);
+      }
+      float m = 0.0f;
+      for (int c = 0; c < 3; ++c) {
+        a.xbn[c * np + p] = lam[c] + xbs[c] +
+                            (double)(ub0[0] * on[3 + c] + ub0[1] * on[6 + c] + ub0[2] * on[9 + c]);
+        a.u0[c * np + p] = on[c];
+        a.ub0[c * np + p] = ub0[c];
+        m = fmaxf(m, fmaxf(fabsf(ub0[c]), fabsf(ub1[c])));
+      }
+      atomicMax(a.defer_count + 1 + (int)(p & (kMaxSlots - 1)), __float_as_int(m));
     }
   }
 }
 
 // ------------------------------------------------------- scatter kernel ---
-// Adjoint of the 64-term sums of both Heun stages, accumulated in an LDS ring
-// of the column's planes and flushed to g_coeff once a plane can receive no
-// further contribution.  Interior points of a column tile belong to it alone
-// and are updated with a plain read-modify-write; the 3-point strips shared
-// with neighbouring columns, and stencils outside the ring, use atomics.
-__device__ __forceinline__ void scatter_lds(float* lds, const Pt& q, int X0, int Y0, int lane,
-                                            const float gu[3]) {
+// Adjoint of the 64-term sums of both Heun stages:
+//   g_coeff += W(x^n)^T ub0 + W(x*)^T ub1  over the particles.
+// Each workgroup takes a 32 x 16 half of a column over a segment of layers and
+// sums the contributions in an LDS ring of planes of its tile (one-cell
+// margin, so predictor points that moved one cell out still land in it).  A
+// plane is added to g_coeff with a plain read-modify-write once nothing more
+// can reach it.  Launches run one colour (parities of cx, the half-row and the
+// segment) at a time, so no two concurrent workgroups touch the same
+// coefficient.  Stencils that do not fit the tile (periodic wrap, or a move of
+// more than one cell) go to a list that scatter_deferred adds with atomics
+// after all colours.
+//
+// The LDS sums are 64-bit fixed point: FP32 atomic adds to LDS run at a small
+// fraction of the rate of integer ones on this hardware.  Every contribution
+// w * ub is formed in FP32 with ub pre-scaled by 2^k (k chosen per launch from
+// the largest |ub|, so that |w ub 2^k| < 2^31), converted to a 32-bit integer
+// and added as a 64-bit integer; the plane flush converts back.  The rounding
+// of each contribution (2^-k absolute, about 2^-30 of the largest |ub|) is
+// far below the FP32 rounding of the contribution itself.
+constexpr int kSTW = kTileX + 5;           // 37: tile width with margin
+constexpr int kSTH = kTileY / 2 + 5;       // 21
+constexpr int kSComp = kSTW * kSTH;        // 777
+constexpr int kSPlane = 3 * kSComp;        // 2331
+constexpr int kSSlot = kSPlane + 1;        // slot pitch (64-bit words)
+constexpr int kSRing = 8;
+constexpr int kSTB = 512;
+constexpr int kSLanes = 8;                 // lanes per particle
+constexpr int kSGroups = kSTB / kSLanes;   // 64
+constexpr int kSPer = (kSPlane + kSTB - 1) / kSTB;  // plane words per thread (5)
+
+__device__ __forceinline__ int sslot(int P) { return (P + kSRing) & (kSRing - 1); }
+
+// Tile point of element e of a plane: component, row, column.
+__device__ __forceinline__ void selem(int e, int* c, int* y, int* x) {
+  *c = e / kSComp;
+  const int r = e - *c * kSComp;
+  *y = r / kSTW;
+  *x = r - *y * kSTW;
+}
+
+__device__ __forceinline__ void scatter_ring(long long* ring, const Pt& q, int X0, int Y0,
+                                             int lane, const float us[3]) {
+  // lane = (i, kh): x-offset i, planes k = 2 kh, 2 kh + 1
   float wx[4], wy[4], wz[4];
   bspline_w(q.t[0], wx);
   bspline_w(q.t[1], wy);
   bspline_w(q.t[2], wz);
-  const float wxi = lane == 0 ? wx[0] : lane == 1 ? wx[1] : lane == 2 ? wx[2] : wx[3];
-  const int col = (q.a - X0) + lane;
-  const int row0 = q.b - Y0;
+  const int i = lane & 3, kh = lane >> 2;
+  const float wxi = pick4(wx, i);
+  const int off = (q.b - Y0) * kSTW + (q.a - X0) + i;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    float* pl = lds + ((q.c + k) & (kRing - 1)) * kSlotP + col;
+  for (int kk = 0; kk < 2; ++kk) {
+    const int k = 2 * kh + kk;
+    const float wzk = kh == 0 ? (kk == 0 ? wz[0] : wz[1]) : (kk == 0 ? wz[2] : wz[3]);
+    long long* pl = ring + sslot(q.c + k) * kSSlot + off;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float w = wxi * wy[j] * wz[k];
+      const float w = wxi * wy[j] * wzk;
 #pragma unroll
-      for (int comp = 0; comp < 3; ++comp)
-        atomicAdd(pl + comp * kCompP + (row0 + j) * kRowP, w * gu[comp]);
+      for (int comp = 0; comp < 3; ++comp) {
+        const int v = (int)(w * us[comp]);
+        atomicAdd((unsigned long long*)(pl + comp * kSComp + j * kSTW),
+                  (unsigned long long)(long long)v);
+      }
     }
   }
 }
 
-__device__ __forceinline__ void scatter_global(float* gc, const GridDev& g, const Pt& q, int lane,
-                                               const float gu[3]) {
-  float wx[4], wy[4], wz[4];
-  bspline_w(q.t[0], wx);
-  bspline_w(q.t[1], wy);
-  bspline_w(q.t[2], wz);
-  const float wxi = lane == 0 ? wx[0] : lane == 1 ? wx[1] : lane == 2 ? wx[2] : wx[3];
-  const int64_t off = ((int64_t)q.c * g.py + q.b) * g.px + q.a + lane;
-  for (int k = 0; k < 4; ++k)
-    for (int j = 0; j < 4; ++j) {
-      const float w = wxi * wy[j] * wz[k];
-      for (int comp = 0; comp < 3; ++comp)
-        unsafeAtomicAdd(gc + comp * g.comp + off + k * g.plane + j * g.px, w * gu[comp]);
-    }
-}
+struct SData {
+  double x[3];
+  float u0[3];
+  float ub1[3];  // dt/2 lam
+  float ub0[3];
+  int p;
+  bool ok;
+};
 
-__device__ __forceinline__ void zero_slot(float* lds, int slot) {
-  for (int e = threadIdx.x; e < kSlotP; e += kTB) lds[slot * kSlotP + e] = 0.0f;
-}
-
-// Add LDS slot into padded plane P of g_coeff.
-__device__ __forceinline__ void flush_plane(float* lds, int slot, float* gc, const GridDev& g,
-                                            int P, int X0, int Y0) {
-  if (P < 0 || P >= g.nz + 3) return;
-  for (int e = threadIdx.x; e < kPlaneElems; e += kTB) {
-    const int c = e / (kTW * kTH);
-    const int r = e - c * (kTW * kTH);
-    const int y = r / kTW, x = r - y * kTW;
-    const int X = X0 + x, Y = Y0 + y;
-    if (X >= g.px || Y >= g.py) continue;
-    const float v = lds[slot * kSlotP + c * kCompP + y * kRowP + x];
-    if (v == 0.0f) continue;
-    float* dst = gc + c * g.comp + (int64_t)P * g.plane + (int64_t)Y * g.px + X;
-    // Other columns add into the same points concurrently (the shared 3-point
-    // strips, and stencils that left their own column), so every update is
-    // an atomic add.
-    unsafeAtomicAdd(dst, v);
+__device__ __forceinline__ void load_sdata(const TileArgs& a, int64_t p, bool ok, SData* d) {
+  const int64_t np = a.np;
+  const int64_t i = ok ? p : 0;
+  d->ok = ok;
+  d->p = (int)p;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    d->x[c] = a.x[c * np + i];
+    d->u0[c] = a.u0[c * np + i];
+    d->ub1[c] = (float)(0.5 * a.dt * a.lam[c * np + i]);
+    d->ub0[c] = a.ub0[c * np + i];
   }
 }
 
-__global__ __launch_bounds__(kTB) void tile_scatter(TileArgs a) {
-  extern __shared__ float lds[];
-  // one block per whole column (no segments: every plane is flushed once)
+__device__ __forceinline__ void defer_stencil(const TileArgs& a, int64_t p, int stage) {
+  const int i = atomicAdd(a.defer_count, 1);
+  if ((int64_t)i < 2 * a.np) a.defer[i] = (uint32_t)(2 * p + stage);
+}
+
+__device__ __forceinline__ void scatter_one(const TileArgs& a, long long* ring, const SData& d,
+                                            int X0, int Y0, int zz, int lane, float scale) {
+  const GridDev& g = a.g;
+  double xs[3];
+  float s0[3], s1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    xs[c] = d.x[c] + a.dt * (double)d.u0[c];
+    s0[c] = d.ub0[c] * scale;
+    s1[c] = d.ub1[c] * scale;
+  }
+  // cells with tile-local index in [0, kTileX + 2) x [0, kTileY/2 + 2) and
+  // layers zz-1 .. zz+2 have their stencils inside the tile and the ring
+  Pt qn = locate_pt<0>(g, d.x, X0, Y0, zz - 1, zz + kSlab, a.err);
+  {
+    const int lx = qn.a - X0, ly = qn.b - Y0;
+    qn.in_ring = lx >= 0 && lx < kTileX + 2 && ly >= 0 && ly < kTileY / 2 + 2 &&
+                 qn.c >= zz - 1 && qn.c <= zz + kSlab;
+  }
+  if (qn.in_ring) scatter_ring(ring, qn, X0, Y0, lane, s0);
+  else if (lane == 0) defer_stencil(a, d.p, 0);
+  Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
+  {
+    const int lx = qs.a - X0, ly = qs.b - Y0;
+    qs.in_ring = lx >= 0 && lx < kTileX + 2 && ly >= 0 && ly < kTileY / 2 + 2 &&
+                 qs.c >= zz - 1 && qs.c <= zz + kSlab;
+  }
+  if (qs.in_ring) scatter_ring(ring, qs, X0, Y0, lane, s1);
+  else if (lane == 0) defer_stencil(a, d.p, 1);
+}
+
+// Items of this launch's colour: half-columns with the given parities of cx
+// and of the half-row index 2 cy + h, and segments with the given parity;
+// remapped per XCD as in gather_item.
+__device__ __forceinline__ bool scatter_item(const TileArgs& a, int* col, int* half, int* z0,
+                                             int* z1) {
+  const int px2 = a.color & 1, py2 = (a.color >> 1) & 1, ps2 = (a.color >> 2) & 1;
+  const int nhy = 2 * a.ncy;
+  const int ncx2 = (a.ncx - px2 + 1) / 2, nhy2 = (nhy - py2 + 1) / 2;
+  const int nseg2 = (a.nseg - ps2 + 1) / 2;
+  const int nitems = ncx2 * nhy2 * nseg2;
   const int b = blockIdx.x;
-  const int per = (a.ncol + 7) / 8;
-  const int col = (b & 7) * per + (b >> 3);
-  if ((b >> 3) >= per || col >= a.ncol) return;
+  const int per = (nitems + 7) / 8;
+  const int item = (b & 7) * per + (b >> 3);
+  if ((b >> 3) >= per || item >= nitems) return false;
+  const int seg2 = item / (ncx2 * nhy2);
+  const int r = item - seg2 * ncx2 * nhy2;
+  const int hy2 = r / ncx2, cx2 = r - hy2 * ncx2;
+  const int cx = 2 * cx2 + px2, hy = 2 * hy2 + py2, seg = 2 * seg2 + ps2;
+  *col = (hy >> 1) * a.ncx + cx;
+  *half = hy & 1;
+  *z0 = seg * a.seg_len;
+  *z1 = min(*z0 + a.seg_len, a.g.nz);
+  return true;
+}
+
+__device__ __forceinline__ float scatter_scale(const TileArgs& a) {
+  float m = 0.0f;
+  for (int i = 1; i <= kMaxSlots; ++i) m = fmaxf(m, __int_as_float(a.defer_count[i]));
+  if (!(m > 0.0f) || !(m < 3.0e38f)) return 1.0f;
+  int e;
+  frexpf(m, &e);  // m < 2^e
+  return ldexpf(1.0f, 30 - e);
+}
+
+__device__ __forceinline__ void load_gv(const TileArgs& a, int X0, int Y0, int P, float* v) {
+  const GridDev& g = a.g;
+  const int Pc = min(max(P, 0), g.nz + 2);
+#pragma unroll
+  for (int q = 0; q < kSPer; ++q) {
+    const int e = min((int)threadIdx.x + q * kSTB, kSPlane - 1);
+    int c, y, x;
+    selem(e, &c, &y, &x);
+    const int X = min(max(X0 + x, 0), g.px - 1), Y = min(max(Y0 + y, 0), g.py - 1);
+    v[q] = a.gcoeff[c * g.comp + (int64_t)Pc * g.plane + (int64_t)Y * g.px + X];
+  }
+}
+
+__device__ __forceinline__ void flush_splane(const TileArgs& a, long long* ring, int X0, int Y0,
+                                             int P, const float* v, float inv_scale) {
+  const GridDev& g = a.g;
+  if (P < 0 || P >= g.nz + 3) return;
+  long long* sl = ring + sslot(P) * kSSlot;
+#pragma unroll
+  for (int q = 0; q < kSPer; ++q) {
+    const int e = threadIdx.x + q * kSTB;
+    if (e >= kSPlane) continue;
+    int c, y, x;
+    selem(e, &c, &y, &x);
+    const int X = X0 + x, Y = Y0 + y;
+    const long long acc = sl[e];
+    sl[e] = 0;
+    if (acc == 0 || X < 0 || X >= g.px || Y < 0 || Y >= g.py) continue;
+    a.gcoeff[c * g.comp + (int64_t)P * g.plane + (int64_t)Y * g.px + X] =
+        v[q] + (float)((double)acc * (double)inv_scale);
+  }
+}
+
+__global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
+  extern __shared__ long long ssm[];
+  long long* ring = ssm;
+  int* lst = (int*)(ssm + kSRing * kSSlot);  // [2 (nl + 1)] half-layer starts
+  int col, half, z0, z1;
+  if (!scatter_item(a, &col, &half, &z0, &z1)) return;
   const GridDev& g = a.g;
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
-  const int X0 = cx * kTileX, Y0 = cy * kTileY;
-  const int lane = threadIdx.x & 3, grp = threadIdx.x >> 2;
-  const int32_t* ls = a.lstart + (int64_t)col * g.nz;
-  const int64_t np = a.np;
-  for (int s = 0; s < kRing; ++s) zero_slot(lds, s);
-  for (int zs = 0; zs < g.nz; zs += kSlab) {
-    __syncthreads();
-    const int64_t pb = ls[zs];
-    const int64_t pe = ls[min(zs + kSlab, g.nz)];
-    for (int64_t p = pb + grp; p < pe; p += kGroups) {
-      const double xn[3] = {a.x[p], a.x[np + p], a.x[2 * np + p]};
-      double xs[3];
-      float ub1[3], ub0[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xs[d] = xn[d] + a.dt * (double)a.u0[d * np + p];
-        ub1[d] = (float)(0.5 * a.dt * a.lam[d * np + p]);
-        ub0[d] = a.ub0[d * np + p];
-      }
-      const Pt qn = locate_pt(g, xn, X0, Y0, zs - 1, zs + kSlab, a.err);
-      const Pt qs = locate_pt(g, xs, X0, Y0, zs - 1, zs + kSlab, a.err);
-      if (qn.in_ring) scatter_lds(lds, qn, X0, Y0, lane, ub0);
-      else scatter_global(a.gcoeff, g, qn, lane, ub0);
-      if (qs.in_ring) scatter_lds(lds, qs, X0, Y0, lane, ub1);
-      else scatter_global(a.gcoeff, g, qs, lane, ub1);
-    }
-    __syncthreads();
-    // planes zs-1 and zs are complete: later layers touch planes >= zs+1
-    for (int P = zs - 1; P <= zs; ++P) {
-      flush_plane(lds, P & (kRing - 1), a.gcoeff, g, P, X0, Y0);
-    }
-    __syncthreads();
-    zero_slot(lds, (zs - 1) & (kRing - 1));
-    zero_slot(lds, zs & (kRing - 1));
+  const int X0 = cx * kTileX - 1, Y0 = cy * kTileY + half * (kTileY / 2) - 1;
+  const int lane = threadIdx.x & (kSLanes - 1), grp = threadIdx.x / kSLanes;
+  const int nl = z1 - z0;
+  // starts of this half and of the next half-layer, for layers z0 .. z1
+  const int32_t* hs = a.lstart + 2 * ((int64_t)col * g.nz + z0) + half;
+  for (int i = threadIdx.x; i < nl; i += kSTB) {
+    lst[2 * i] = hs[2 * i];
+    lst[2 * i + 1] = hs[2 * i + 1];
   }
+  for (int e = threadIdx.x; e < kSRing * kSSlot; e += kSTB) ring[e] = 0;
+  const float scale = scatter_scale(a), inv_scale = 1.0f / scale;
   __syncthreads();
-  // remaining planes nz-1 .. nz+2 (the last slab flushed up to nz-1 or nz-2)
-  const int last_done = ((g.nz - 1) / kSlab) * kSlab;  // zs of the last slab
-  for (int P = last_done + 1; P <= g.nz + 2; ++P)
-    flush_plane(lds, P & (kRing - 1), a.gcoeff, g, P, X0, Y0);
+
+  // particles of slab s: layer zs (half) then layer zs+1 (half); quad group
+  // grp takes the particles grp * npass + k of that virtual list, so that the
+  // groups of a pass are spread over the slab (fewer same-word adds in dense
+  // clusters)
+  auto slab_range = [&](int zs, int64_t* r0, int64_t* n0, int64_t* r1, int64_t* n1) {
+    *r0 = *n0 = *r1 = *n1 = 0;
+    if (zs >= z1) return;
+    const int i0 = zs - z0;
+    *r0 = lst[2 * i0];
+    *n0 = lst[2 * i0 + 1] - *r0;
+    if (zs + 1 < z1) {
+      *r1 = lst[2 * i0 + 2];
+      *n1 = lst[2 * i0 + 3] - *r1;
+    }
+  };
+  auto vidx = [&](int64_t v, int64_t r0, int64_t n0, int64_t r1) {
+    return v < n0 ? r0 + v : r1 + (v - n0);
+  };
+  SData sd[2];
+  float gv[2][2][kSPer];
+  auto prefetch = [&](int set, int s) {
+    const int zs = z0 + s * kSlab;
+    int64_t r0, n0, r1, n1;
+    slab_range(zs, &r0, &n0, &r1, &n1);
+    const int64_t n = n0 + n1;
+    const int64_t npass = (n + kSGroups - 1) / kSGroups;
+    const int64_t v = grp * npass;
+    load_sdata(a, vidx(v, r0, n0, r1), v < n, &sd[set]);
+    // planes zs-1 and zs are flushed at the end of slab s
+    load_gv(a, X0, Y0, zs - 1, gv[set][0]);
+    load_gv(a, X0, Y0, zs, gv[set][1]);
+  };
+  prefetch(0, 0);
+  prefetch(1, 1);
+  for (int s0 = 0; z0 + s0 * kSlab < z1; s0 += 2) {
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      const int s = s0 + hf;
+      const int zs = z0 + s * kSlab;
+      if (zs < z1) {
+        int64_t r0, n0, r1, n1;
+        slab_range(zs, &r0, &n0, &r1, &n1);
+        const int64_t n = n0 + n1;
+        const int64_t npass = (n + kSGroups - 1) / kSGroups;
+        SData cur = sd[hf];
+        for (int64_t k = 0; k < npass; ++k) {
+          SData nxt;
+          const int64_t v = grp * npass + k + 1;
+          load_sdata(a, vidx(v, r0, n0, r1), k + 1 < npass && v < n, &nxt);
+          if (cur.ok) scatter_one(a, ring, cur, X0, Y0, zs, lane, scale);
+          cur = nxt;
+        }
+        __syncthreads();
+        // planes zs-1 and zs are complete: later particles sit in layers
+        // >= zs+2 and their predictor points in layers >= zs+1
+        flush_splane(a, ring, X0, Y0, zs - 1, gv[hf][0], inv_scale);
+        flush_splane(a, ring, X0, Y0, zs, gv[hf][1], inv_scale);
+        prefetch(hf, s + 2);
+        __syncthreads();
+      }
+    }
+  }
+  // planes above the last flushed one, up to z1 + 3 (the highest plane a
+  // predictor point of layer z1 - 1 reaches)
+  const int last_zs = z0 + ((nl - 1) / kSlab) * kSlab;
+  for (int P = last_zs + 1; P <= z1 + 3; ++P) {
+    float v[kSPer];
+    load_gv(a, X0, Y0, P, v);
+    flush_splane(a, ring, X0, Y0, P, v, inv_scale);
+    __syncthreads();
+  }
+}
+
+// Stencils that did not fit their column's tile, added with atomics once all
+// colours are done.
+__global__ __launch_bounds__(256) void scatter_deferred(TileArgs a) {
+  const int64_t n = min((int64_t)*a.defer_count, 2 * a.np);
+  const GridDev& g = a.g;
+  const int64_t np = a.np;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t e = a.defer[i];
+    const int64_t p = e >> 1;
+    if (p >= np) continue;
+    const int stage = e & 1;
+    double x[3];
+    float gu[3];
+    for (int c = 0; c < 3; ++c) {
+      const double xn = a.x[c * np + p];
+      if (stage == 0) {
+        x[c] = xn;
+        gu[c] = a.ub0[c * np + p];
+      } else {
+        x[c] = xn + a.dt * (double)a.u0[c * np + p];
+        gu[c] = (float)(0.5 * a.dt * a.lam[c * np + p]);
+      }
+    }
+    bool bad = false;
+    double t0, t1, t2;
+    const int ca = cell_1d(x[0], g.cs[0], g.nx, &t0, &bad);
+    const int cb = cell_1d(x[1], g.cs[1], g.ny, &t1, &bad);
+    const int cc = cell_1d(x[2], g.cs[2], g.nz, &t2, &bad);
+    float wx[4], wy[4], wz[4];
+    bspline_w((float)t0, wx);
+    bspline_w((float)t1, wy);
+    bspline_w((float)t2, wz);
+    const int64_t off = ((int64_t)cc * g.py + cb) * g.px + ca;
+    for (int k = 0; k < 4; ++k)
+      for (int j = 0; j < 4; ++j)
+        for (int ii = 0; ii < 4; ++ii) {
+          const float w = wx[ii] * wy[j] * wz[k];
+          for (int c = 0; c < 3; ++c)
+            unsafeAtomicAdd(a.gcoeff + c * g.comp + off + k * g.plane + j * g.px + ii, w * gu[c]);
+        }
+  }
+}
+
+__global__ void zero_defer_count(int* p) { p[0] = 0; }
+
+// defer header: [0] deferred-list length, [1 .. kMaxSlots] largest |ub|
+// (float bits) per group of gather blocks
+__global__ void zero_int(int* p) {
+  if (threadIdx.x <= kMaxSlots) p[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------- layer table ---
@@ -466,18 +988,24 @@ __global__ __launch_bounds__(256) void layer_table(const K* __restrict__ keys, i
                                                    int64_t nlayers, int32_t* __restrict__ ls) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i > np) return;
-  const int64_t lprev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> kLayerShift);
-  const int64_t lcur = i == np ? nlayers : (int64_t)(keys[i] >> kLayerShift);
+  const int64_t lprev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> kHalfShift);
+  const int64_t lcur = i == np ? nlayers : (int64_t)(keys[i] >> kHalfShift);
   for (int64_t L = lprev + 1; L <= lcur && L <= nlayers; ++L) ls[L] = (int32_t)i;
 }
 
 // ------------------------------------------------------------ host side ---
-static size_t tile_lds_bytes() { return (size_t)kRing * kSlotP * sizeof(float); }
+template <int M>
+static size_t tile_lds_bytes(int seg) {
+  return (size_t)Geo<M>::RingFloats * sizeof(float) + sizeof(int) * (size_t)(seg + 4);
+}
 
+// number of half-layers (entries of the particle table minus one)
 int64_t tile_nlayers(const pt_grid* g) {
   const int64_t ncx = (g->nx + kTileX - 1) / kTileX, ncy = (g->ny + kTileY - 1) / kTileY;
-  return ncx * ncy * g->nz;
+  return 2 * ncx * ncy * g->nz;
 }
+
+size_t tile_defer_bytes(int64_t np) { return 8 * (size_t)np + kDeferHeader; }
 
 pt_status build_layer_table(const pt_grid* g, int64_t np, const void* keys, int key_bytes,
                             int32_t* ls, hipStream_t s) {
@@ -493,14 +1021,15 @@ pt_status build_layer_table(const pt_grid* g, int64_t np, const void* keys, int 
 }
 
 static TileArgs tile_args(const pt_grid* g, const void* coeff, const int32_t* ls, int64_t np,
-                          double dt) {
+                          double dt, int seg) {
   TileArgs a{};
   a.g = make_grid_dev(g);
   a.coeff = coeff;
   a.lstart = ls;
   a.ncx = (g->nx + kTileX - 1) / kTileX;
-  a.ncol = a.ncx * ((g->ny + kTileY - 1) / kTileY);
-  a.seg_len = g->nz <= 128 ? g->nz : 128;
+  a.ncy = (g->ny + kTileY - 1) / kTileY;
+  a.ncol = a.ncx * a.ncy;
+  a.seg_len = g->nz <= seg ? g->nz : seg;
   a.nseg = (g->nz + a.seg_len - 1) / a.seg_len;
   a.np = np;
   a.dt = dt;
@@ -509,19 +1038,25 @@ static TileArgs tile_args(const pt_grid* g, const void* coeff, const int32_t* ls
 }
 
 template <typename F>
-static bool allow_lds(F* fn) {
+static bool allow_lds(F* fn, size_t bytes) {
   return hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)tile_lds_bytes()) == hipSuccess;
+                             (int)bytes) == hipSuccess;
 }
 
-static pt_status launch_gather(const TileArgs& a, pt_dtype dtype, int mode, hipStream_t s) {
+static pt_status launch_gather(TileArgs a, pt_dtype dtype, int mode, void* defer,
+                               hipStream_t s) {
   const int nitems = a.ncol * a.nseg;
   const unsigned blocks = (unsigned)(((nitems + 7) / 8) * 8);
-  const size_t lds = tile_lds_bytes();
-#define PT_TG(CT, M)                                                               \
-  do {                                                                             \
-    if (!allow_lds(tile_gather<CT, M>)) return PT_ERR_HIP;                          \
-    hipLaunchKernelGGL((tile_gather<CT, M>), dim3(blocks), dim3(kTB), lds, s, a);  \
+  const size_t lds = sizeof(uint32_t) * ((size_t)kGRing * kGSlot + a.seg_len + 4 + kGTB / 64);
+  a.defer_count = (int*)defer;
+  a.defer = (uint32_t*)((char*)defer + kDeferHeader);
+  hipLaunchKernelGGL(zero_int, dim3(1), dim3(128), 0, s, a.defer_count);
+  PT_LAUNCH_CHECK();
+#define PT_TG(CT, MD)                                                                  \
+  do {                                                                                 \
+    if (!allow_lds(tile_gather<CT, MD>, lds)) return PT_ERR_HIP;                       \
+    hipLaunchKernelGGL((tile_gather<CT, MD>), dim3(blocks), dim3(kGTB), lds, s, a);    \
+    hipLaunchKernelGGL((gather_deferred<CT, MD>), dim3(256), dim3(256), 0, s, a);      \
   } while (0)
   if (dtype == PT_F32) {
     if (mode == TILE_RK2_FWD) PT_TG(float, TILE_RK2_FWD);
@@ -535,29 +1070,51 @@ static pt_status launch_gather(const TileArgs& a, pt_dtype dtype, int mode, hipS
   return PT_OK;
 }
 
+// defer: workspace of tile_defer_bytes(np) bytes.
 pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
-                       int64_t np, double dt, const double* x, double* x_out, hipStream_t s) {
-  TileArgs a = tile_args(g, coeff, ls, np, dt);
+                       int64_t np, double dt, const double* x, double* x_out, void* defer,
+                       hipStream_t s) {
+  TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
   a.x = x;
   a.x_out = x_out;
-  return launch_gather(a, dtype, TILE_RK2_FWD, s);
+  return launch_gather(a, dtype, TILE_RK2_FWD, defer, s);
 }
 
+// defer: workspace of tile_defer_bytes(np) bytes.
 pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, const double* lam, double* xbn,
-                       float* u0, float* ub0, float* gcoeff, hipStream_t s) {
-  TileArgs a = tile_args(g, coeff, ls, np, dt);
+                       float* u0, float* ub0, float* gcoeff, void* defer, hipStream_t s) {
+  TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
   a.x = x;
   a.lam = lam;
   a.xbn = xbn;
   a.u0 = u0;
   a.ub0 = ub0;
-  a.gcoeff = gcoeff;
-  pt_status st = launch_gather(a, dtype, TILE_RK2_BWD_GRAD, s);
+  pt_status st = launch_gather(a, dtype, TILE_RK2_BWD_GRAD, defer, s);
   if (st != PT_OK || !gcoeff) return st;
-  const unsigned blocks = (unsigned)(((a.ncol + 7) / 8) * 8);
-  if (!allow_lds(tile_scatter)) return PT_ERR_HIP;
-  hipLaunchKernelGGL(tile_scatter, dim3(blocks), dim3(kTB), tile_lds_bytes(), s, a);
+  TileArgs b = tile_args(g, coeff, ls, np, dt, kScatterSeg);
+  b.x = x;
+  b.lam = lam;
+  b.u0 = u0;
+  b.ub0 = ub0;
+  b.gcoeff = gcoeff;
+  b.defer_count = (int*)defer;
+  b.defer = (uint32_t*)((char*)defer + kDeferHeader);
+  hipLaunchKernelGGL(zero_defer_count, dim3(1), dim3(1), 0, s, b.defer_count);
+  PT_LAUNCH_CHECK();
+  const size_t lds = sizeof(long long) * (size_t)kSRing * kSSlot + sizeof(int) * 2 * (b.seg_len + 2);
+  if (!allow_lds(tile_scatter, lds)) return PT_ERR_HIP;
+  for (int color = 0; color < 8; ++color) {
+    b.color = color;
+    const int px2 = color & 1, py2 = (color >> 1) & 1, ps2 = (color >> 2) & 1;
+    const int nitems =
+        ((b.ncx - px2 + 1) / 2) * ((2 * b.ncy - py2 + 1) / 2) * ((b.nseg - ps2 + 1) / 2);
+    if (nitems <= 0) continue;
+    const unsigned blocks = (unsigned)(((nitems + 7) / 8) * 8);
+    hipLaunchKernelGGL(tile_scatter, dim3(blocks), dim3(kTB), lds, s, b);
+    PT_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(scatter_deferred, dim3(1024), dim3(256), 0, s, b);
   PT_LAUNCH_CHECK();
   return PT_OK;
 }
