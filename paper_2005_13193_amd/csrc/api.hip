@@ -38,10 +38,12 @@ pt_status scatter_back(int64_t np, const double* in, const int32_t* perm, double
 int64_t tile_nlayers(const pt_grid* g);
 pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, double* x_out, void* defer,
-                       hipStream_t s);
+                       void* items_ws, hipStream_t s);
+size_t tile_items_bytes(const pt_grid* g, int64_t np, bool scatter);
 pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, const double* lam, double* xbn,
-                       float* u0, float* ub0, float* gcoeff, void* defer, hipStream_t s);
+                       float* u0, float* ub0, float* gcoeff, void* defer, void* items_ws,
+                       hipStream_t s);
 size_t tile_defer_bytes(int64_t np);
 
 // One non-finite-position flag per device, in the library's static device
@@ -107,11 +109,13 @@ struct Rk2Ws {
   float* u0;
   int32_t* lstart;
   void* defer;
+  void* items;
 };
 
 static size_t rk2_ws_bytes(const pt_grid* g, int64_t np) {
   return a256(sort_ws_bytes(g, np)) + a256(24 * (size_t)np) + 2 * a256(4 * (size_t)np) +
-         a256(12 * (size_t)np) + a256(lstart_bytes(g)) + a256(tile_defer_bytes(np));
+         a256(12 * (size_t)np) + a256(lstart_bytes(g)) + a256(tile_defer_bytes(np)) +
+         a256(tile_items_bytes(g, np, false));
 }
 
 static Rk2Ws carve_rk2(const pt_grid* g, int64_t np, void* ws) {
@@ -123,7 +127,8 @@ static Rk2Ws carve_rk2(const pt_grid* g, int64_t np, void* ws) {
   w.ids_tmp = (int32_t*)p; p += a256(4 * (size_t)np);
   w.u0 = (float*)p; p += a256(12 * (size_t)np);
   w.lstart = (int32_t*)p; p += a256(lstart_bytes(g));
-  w.defer = p;
+  w.defer = p; p += a256(tile_defer_bytes(np));
+  w.items = p;
   return w;
 }
 
@@ -137,11 +142,13 @@ struct Rk2BwdWs {
   float* ub0;
   int32_t* lstart;
   void* defer;
+  void* items;
 };
 
 static size_t rk2_bwd_ws_bytes(const pt_grid* g, int64_t np) {
   return a256(sort_ws_bytes(g, np)) + 3 * a256(24 * (size_t)np) + a256(4 * (size_t)np) +
-         2 * a256(12 * (size_t)np) + a256(lstart_bytes(g)) + a256(tile_defer_bytes(np));
+         2 * a256(12 * (size_t)np) + a256(lstart_bytes(g)) + a256(tile_defer_bytes(np)) +
+         a256(tile_items_bytes(g, np, false)) + a256(tile_items_bytes(g, np, true));
 }
 
 static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, void* ws) {
@@ -155,7 +162,8 @@ static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, void* ws) {
   w.u0 = (float*)p; p += a256(12 * (size_t)np);
   w.ub0 = (float*)p; p += a256(12 * (size_t)np);
   w.lstart = (int32_t*)p; p += a256(lstart_bytes(g));
-  w.defer = p;
+  w.defer = p; p += a256(tile_defer_bytes(np));
+  w.items = p;
   return w;
 }
 
@@ -272,7 +280,8 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
       PT_TRY(permute_ids(np, ids, w.perm, w.ids_tmp, stream));
       PT_HIP_CHECK(hipMemcpyAsync(ids, w.ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
     }
-    return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, pos, w.defer, stream);
+    return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, pos, w.defer, w.items,
+                        stream);
   }
   return rk2_advance(grid, coeff, dtype, np, dt, pos, pos, w.u0, stream);
 }
@@ -307,7 +316,7 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
     PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
                           stream));
     PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, g_pos, w.xbn, w.u0,
-                        w.ub0, g_coeff, w.defer, stream));
+                        w.ub0, g_coeff, w.defer, w.items, stream));
     return scatter_back(np, w.xbn, w.perm, g_pos, stream);
   }
   return rk2_backward(grid, coeff, dtype, np, dt, pos_n, g_pos, g_pos, g_coeff, w.u0, w.xbs,

@@ -55,7 +55,9 @@ struct TileArgs {
   const void* coeff;
   const int32_t* lstart;  // [ncol * nz + 1]: first particle of each (column, layer)
   int ncx, ncy, ncol, nseg, seg_len;
-  int color;              // scatter: parities (cx, cy, segment) of this launch
+  int color;              // scatter: colour of this launch
+  const int4* items;      // work items (column, half, z0, z1)
+  const int* item_range;  // [begin, end) of this launch's items in `items`
   int64_t np;
   double dt;
   const double* x;        // [3][np] positions (sorted)
@@ -438,19 +440,21 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
   }
 }
 
-// Work item of a gather block.  Blocks are dealt to the 8 XCDs round-robin;
-// item numbers are remapped so that each XCD walks a contiguous run of
-// neighbouring columns of one segment (their shared halos stay in its L2).
-__device__ __forceinline__ bool gather_item(const TileArgs& a, int* col, int* z0, int* z1) {
-  const int nitems = a.ncol * a.nseg;
+// Work item of a block.  Blocks are dealt to the 8 XCDs round-robin; item
+// numbers are remapped so that each XCD walks a contiguous run of items
+// (neighbouring columns of similar layers: their shared halos stay in its L2).
+__device__ __forceinline__ bool next_item(const TileArgs& a, int* col, int* half, int* z0,
+                                          int* z1) {
+  const int begin = a.item_range[0], n = a.item_range[1] - begin;
   const int b = blockIdx.x;
-  const int per = (nitems + 7) / 8;
+  const int per = (n + 7) / 8;
   const int item = (b & 7) * per + (b >> 3);
-  if ((b >> 3) >= per || item >= nitems) return false;
-  const int seg = item / a.ncol;
-  *col = item - seg * a.ncol;
-  *z0 = seg * a.seg_len;
-  *z1 = min(*z0 + a.seg_len, a.g.nz);
+  if ((b >> 3) >= per || item >= n) return false;
+  const int4 it = a.items[begin + item];
+  *col = it.x;
+  *half = it.y;
+  *z0 = it.z;
+  *z1 = it.w;
   return true;
 }
 
@@ -505,8 +509,8 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
   extern __shared__ uint32_t gsm[];
   uint32_t* ring = gsm;
   int* lst = (int*)(gsm + kGRing * kGSlot);  // layer starts of the segment
-  int col, z0, z1;
-  if (!gather_item(a, &col, &z0, &z1)) return;
+  int col, half_unused, z0, z1;
+  if (!next_item(a, &col, &half_unused, &z0, &z1)) return;
   const GridDev& g = a.g;
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
   const int X0 = cx * kTileX, Y0 = cy * kTileY;
@@ -770,31 +774,6 @@ __device__ __forceinline__ void scatter_one(const TileArgs& a, long long* ring, 
   else if (lane == 0) defer_stencil(a, d.p, 1);
 }
 
-// Items of this launch's colour: half-columns with the given parities of cx
-// and of the half-row index 2 cy + h, and segments with the given parity;
-// remapped per XCD as in gather_item.
-__device__ __forceinline__ bool scatter_item(const TileArgs& a, int* col, int* half, int* z0,
-                                             int* z1) {
-  const int px2 = a.color & 1, py2 = (a.color >> 1) & 1, ps2 = (a.color >> 2) & 1;
-  const int nhy = 2 * a.ncy;
-  const int ncx2 = (a.ncx - px2 + 1) / 2, nhy2 = (nhy - py2 + 1) / 2;
-  const int nseg2 = (a.nseg - ps2 + 1) / 2;
-  const int nitems = ncx2 * nhy2 * nseg2;
-  const int b = blockIdx.x;
-  const int per = (nitems + 7) / 8;
-  const int item = (b & 7) * per + (b >> 3);
-  if ((b >> 3) >= per || item >= nitems) return false;
-  const int seg2 = item / (ncx2 * nhy2);
-  const int r = item - seg2 * ncx2 * nhy2;
-  const int hy2 = r / ncx2, cx2 = r - hy2 * ncx2;
-  const int cx = 2 * cx2 + px2, hy = 2 * hy2 + py2, seg = 2 * seg2 + ps2;
-  *col = (hy >> 1) * a.ncx + cx;
-  *half = hy & 1;
-  *z0 = seg * a.seg_len;
-  *z1 = min(*z0 + a.seg_len, a.g.nz);
-  return true;
-}
-
 __device__ __forceinline__ float scatter_scale(const TileArgs& a) {
   float m = 0.0f;
   for (int i = 1; i <= kMaxSlots; ++i) m = fmaxf(m, __int_as_float(a.defer_count[i]));
@@ -842,7 +821,7 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   long long* ring = ssm;
   int* lst = (int*)(ssm + kSRing * kSSlot);  // [2 (nl + 1)] half-layer starts
   int col, half, z0, z1;
-  if (!scatter_item(a, &col, &half, &z0, &z1)) return;
+  if (!next_item(a, &col, &half, &z0, &z1)) return;
   const GridDev& g = a.g;
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
   const int X0 = cx * kTileX - 1, Y0 = cy * kTileY + half * (kTileY / 2) - 1;
@@ -993,6 +972,104 @@ __global__ __launch_bounds__(256) void layer_table(const K* __restrict__ keys, i
   for (int64_t L = lprev + 1; L <= lcur && L <= nlayers; ++L) ls[L] = (int32_t)i;
 }
 
+// ------------------------------------------------------- work items ---
+// Work items split each column (gather) or half-column (scatter) into runs of
+// layers holding at most pmax particles (but at least lmin layers, the last
+// run excepted) and at most lmax layers, so that dense clusters are spread
+// over many workgroups.  Scatter items carry a colour: parities of cx, of the
+// half-row 2 cy + h and of the run index; runs of one colour never share a
+// coefficient because every run between two of them is at least lmin >= 5
+// layers long and a run touches planes z0-1 .. z1+3 only.
+struct ItemCfg {
+  int pmax, lmin, lmax, scatter;
+};
+
+__device__ __forceinline__ int unit_layer_count(const int32_t* hs, int nz, int u, int z,
+                                                bool scatter) {
+  if (!scatter) {
+    const int64_t b = 2 * ((int64_t)u * nz + z);
+    return hs[b + 2] - hs[b];
+  }
+  const int64_t b = 2 * ((int64_t)(u >> 1) * nz + z) + (u & 1);
+  return hs[b + 1] - hs[b];
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(256) void build_items(const int32_t* __restrict__ hs, int nunits,
+                                                   int nz, int ncx, ItemCfg cfg,
+                                                   int* __restrict__ offsets,
+                                                   int4* __restrict__ items, int64_t capacity) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= nunits) return;
+  const bool sc = cfg.scatter != 0;
+  const int col = sc ? u >> 1 : u, half = sc ? u & 1 : 0;
+  const int cx = col % ncx, hy = 2 * (col / ncx) + half;
+  const int base = sc ? ((cx & 1) | ((hy & 1) << 1)) : 0;
+  int n_even = 0, n_odd = 0, k = 0, z0 = 0, acc = 0;
+  const int o_even = WRITE ? offsets[base * nunits + u] : 0;
+  const int o_odd = WRITE && sc ? offsets[(base | 4) * nunits + u] : 0;
+  auto emit = [&](int za, int zb) {
+    const bool odd = sc && (k & 1);
+    const int at = odd ? o_odd + n_odd : o_even + n_even;
+    if (WRITE && at < capacity) items[at] = make_int4(col, half, za, zb);
+    if (odd) ++n_odd;
+    else ++n_even;
+    ++k;
+  };
+  for (int z = 0; z < nz; ++z) {
+    const int c = unit_layer_count(hs, nz, u, z, sc);
+    const int len = z - z0;
+    if (len > 0 && (len >= cfg.lmax || (len >= cfg.lmin && acc + c > cfg.pmax))) {
+      emit(z0, z);
+      z0 = z;
+      acc = 0;
+    }
+    acc += c;
+  }
+  emit(z0, nz);
+  if (!WRITE) {
+    if (sc) {
+      for (int cc = 0; cc < 8; ++cc)
+        offsets[cc * nunits + u] = cc == base ? n_even : cc == (base | 4) ? n_odd : 0;
+    } else {
+      offsets[u] = n_even;
+    }
+  }
+}
+
+// Exclusive scan of n counts in one workgroup; range[c] = first item of
+// colour c (c = 0 .. ncolors), the counts being colour-major.
+__global__ __launch_bounds__(1024) void scan_items(int* data, int n, int nunits, int ncolors,
+                                                   int* range) {
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (n + 1023) / 1024;
+  const int b = tid * per;
+  int tot = 0;
+  for (int i = 0; i < per; ++i)
+    if (b + i < n) tot += data[b + i];
+  int incl = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int woff = 0;
+  for (int w = 0; w < wave; ++w) woff += wsum[w];
+  int run = woff + incl - tot;
+  for (int i = 0; i < per; ++i) {
+    if (b + i < n) {
+      const int v = data[b + i];
+      data[b + i] = run;
+      if ((b + i) % nunits == 0) range[(b + i) / nunits] = run;
+      run += v;
+    }
+  }
+  if (tid == 1023) range[ncolors] = woff + incl;
+}
+
 // ------------------------------------------------------------ host side ---
 template <int M>
 static size_t tile_lds_bytes(int seg) {
@@ -1037,16 +1114,68 @@ static TileArgs tile_args(const pt_grid* g, const void* coeff, const int32_t* ls
   return a;
 }
 
+constexpr int kItemPmax = 8192;
+
+static int64_t item_bound(int64_t nunits, int nz, int64_t np, int lmax) {
+  return nunits * ((nz + lmax - 1) / lmax + 1) + 2 * ((np + kItemPmax - 1) / kItemPmax) + 8;
+}
+
+// Workspace of build_tile_items: counts/offsets, colour ranges and items.
+size_t tile_items_bytes(const pt_grid* g, int64_t np, bool scatter) {
+  const int64_t ncol = (int64_t)((g->nx + kTileX - 1) / kTileX) * ((g->ny + kTileY - 1) / kTileY);
+  const int64_t nunits = scatter ? 2 * ncol : ncol;
+  const int64_t bound = item_bound(nunits, g->nz, np, scatter ? kScatterSeg : kGatherSeg);
+  return 256 + 4 * (size_t)(8 * nunits) + 16 * (size_t)bound;
+}
+
+struct ItemSet {
+  const int4* items;
+  const int* range;  // [ncolors + 1]
+  int64_t bound;
+};
+
+static pt_status build_tile_items(const pt_grid* g, int64_t np, const int32_t* hs, bool scatter,
+                                  void* ws, ItemSet* out, hipStream_t s) {
+  const int ncx = (g->nx + kTileX - 1) / kTileX;
+  const int64_t ncol = (int64_t)ncx * ((g->ny + kTileY - 1) / kTileY);
+  const int nunits = (int)(scatter ? 2 * ncol : ncol);
+  const int ncolors = scatter ? 8 : 1;
+  if ((int64_t)nunits * ncolors > 1024 * 256) return PT_ERR_UNSUPPORTED;
+  const int lmax = scatter ? kScatterSeg : kGatherSeg;
+  ItemCfg cfg{kItemPmax, scatter ? 6 : 2, lmax, scatter ? 1 : 0};
+  char* p = (char*)ws;
+  int* range = (int*)p;
+  int* offsets = (int*)(p + 256);
+  int4* items = (int4*)(p + 256 + 4 * (size_t)(8 * nunits));
+  const unsigned blocks = (unsigned)((nunits + 255) / 256);
+  const int64_t bound = item_bound(nunits, g->nz, np, lmax);
+  hipLaunchKernelGGL(build_items<false>, dim3(blocks), dim3(256), 0, s, hs, nunits, g->nz, ncx,
+                     cfg, offsets, items, bound);
+  hipLaunchKernelGGL(scan_items, dim3(1), dim3(1024), 0, s, offsets, nunits * ncolors, nunits,
+                     ncolors, range);
+  hipLaunchKernelGGL(build_items<true>, dim3(blocks), dim3(256), 0, s, hs, nunits, g->nz, ncx,
+                     cfg, offsets, items, bound);
+  PT_LAUNCH_CHECK();
+  out->items = items;
+  out->range = range;
+  out->bound = bound;
+  return PT_OK;
+}
+
 template <typename F>
 static bool allow_lds(F* fn, size_t bytes) {
   return hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)bytes) == hipSuccess;
 }
 
-static pt_status launch_gather(TileArgs a, pt_dtype dtype, int mode, void* defer,
-                               hipStream_t s) {
-  const int nitems = a.ncol * a.nseg;
-  const unsigned blocks = (unsigned)(((nitems + 7) / 8) * 8);
+static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int mode,
+                               void* defer, void* items_ws, hipStream_t s) {
+  ItemSet it;
+  pt_status st = build_tile_items(g, a.np, a.lstart, false, items_ws, &it, s);
+  if (st != PT_OK) return st;
+  a.items = it.items;
+  a.item_range = it.range;
+  const unsigned blocks = (unsigned)(((it.bound + 7) / 8) * 8);
   const size_t lds = sizeof(uint32_t) * ((size_t)kGRing * kGSlot + a.seg_len + 4 + kGTB / 64);
   a.defer_count = (int*)defer;
   a.defer = (uint32_t*)((char*)defer + kDeferHeader);
@@ -1070,27 +1199,29 @@ static pt_status launch_gather(TileArgs a, pt_dtype dtype, int mode, void* defer
   return PT_OK;
 }
 
-// defer: workspace of tile_defer_bytes(np) bytes.
+// defer: tile_defer_bytes(np) bytes; items_ws: tile_items_bytes(g, np, false)
 pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, double* x_out, void* defer,
-                       hipStream_t s) {
+                       void* items_ws, hipStream_t s) {
   TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
   a.x = x;
   a.x_out = x_out;
-  return launch_gather(a, dtype, TILE_RK2_FWD, defer, s);
+  return launch_gather(g, a, dtype, TILE_RK2_FWD, defer, items_ws, s);
 }
 
-// defer: workspace of tile_defer_bytes(np) bytes.
+// defer: tile_defer_bytes(np) bytes; items_ws: tile_items_bytes(g, np, false)
+// followed by tile_items_bytes(g, np, true) bytes.
 pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, const double* lam, double* xbn,
-                       float* u0, float* ub0, float* gcoeff, void* defer, hipStream_t s) {
+                       float* u0, float* ub0, float* gcoeff, void* defer, void* items_ws,
+                       hipStream_t s) {
   TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
   a.x = x;
   a.lam = lam;
   a.xbn = xbn;
   a.u0 = u0;
   a.ub0 = ub0;
-  pt_status st = launch_gather(a, dtype, TILE_RK2_BWD_GRAD, defer, s);
+  pt_status st = launch_gather(g, a, dtype, TILE_RK2_BWD_GRAD, defer, items_ws, s);
   if (st != PT_OK || !gcoeff) return st;
   TileArgs b = tile_args(g, coeff, ls, np, dt, kScatterSeg);
   b.x = x;
@@ -1100,18 +1231,20 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   b.gcoeff = gcoeff;
   b.defer_count = (int*)defer;
   b.defer = (uint32_t*)((char*)defer + kDeferHeader);
+  ItemSet it;
+  st = build_tile_items(g, np, ls, true, (char*)items_ws + tile_items_bytes(g, np, false), &it, s);
+  if (st != PT_OK) return st;
+  b.items = it.items;
   hipLaunchKernelGGL(zero_defer_count, dim3(1), dim3(1), 0, s, b.defer_count);
   PT_LAUNCH_CHECK();
-  const size_t lds = sizeof(long long) * (size_t)kSRing * kSSlot + sizeof(int) * 2 * (b.seg_len + 2);
+  const size_t lds =
+      sizeof(long long) * (size_t)kSRing * kSSlot + sizeof(int) * 2 * (b.seg_len + 2);
   if (!allow_lds(tile_scatter, lds)) return PT_ERR_HIP;
+  const unsigned blocks = (unsigned)(((it.bound + 7) / 8) * 8);
   for (int color = 0; color < 8; ++color) {
     b.color = color;
-    const int px2 = color & 1, py2 = (color >> 1) & 1, ps2 = (color >> 2) & 1;
-    const int nitems =
-        ((b.ncx - px2 + 1) / 2) * ((2 * b.ncy - py2 + 1) / 2) * ((b.nseg - ps2 + 1) / 2);
-    if (nitems <= 0) continue;
-    const unsigned blocks = (unsigned)(((nitems + 7) / 8) * 8);
-    hipLaunchKernelGGL(tile_scatter, dim3(blocks), dim3(kTB), lds, s, b);
+    b.item_range = it.range + color;
+    hipLaunchKernelGGL(tile_scatter, dim3(blocks), dim3(kSTB), lds, s, b);
     PT_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(scatter_deferred, dim3(1024), dim3(256), 0, s, b);
