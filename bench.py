@@ -38,10 +38,70 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def interp_bytes(n, np_, coeff_bytes, n_out=3):
-    """Algorithmic HBM bytes of one interpolation pass: the padded field read
-    once plus the particle I/O (FP64 positions in, FP32 outputs out)."""
-    return 3 * (n + 3) ** 3 * coeff_bytes + np_ * (24 + 4 * n_out)
+KERNELS = ("spline_x", "spline_y", "spline_y_pad", "spline_z", "spline_fold", "sort_keys",
+           "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter")
+
+
+def key_bytes(n):
+    """Bytes of one cell key on an n^3 grid (32 x 32-cell columns)."""
+    total = -(-n // 32) ** 2 * n * 1024
+    return 8 if (total - 1).bit_length() > 32 else 4
+
+
+def launch_bytes(kernel, n, np_, cb, launches_per_step):
+    """Algorithmic HBM bytes of one launch: every array the kernel must touch,
+    read or written once (n^3 grid points, (n+3)^3 padded coefficients per
+    component, np_ particles with FP64 positions)."""
+    n3, p3, kb = n ** 3, (n + 3) ** 3, key_bytes(n)
+    per_step = {
+        "spline_x": 8 * n3, "spline_y": 8 * n3, "spline_z": 8 * n3,
+        "spline_y_pad": 4 * n3 + cb * p3,
+        "spline_fold": 4 * p3 + 4 * n3,
+        "sort_keys": np_ * (24 + kb + 4),
+        "sort_pass": np_ * 2 * (kb + 4),
+        "sort_permute": np_ * (4 + 24 + 24),
+        # x in, x_out out; field once
+        "tile_rk2_fwd": 3 * p3 * cb + np_ * 48,
+        # x, lambda in; dL/dx_n, stage-1 velocity and its adjoint out
+        "tile_rk2_bwd_gather": 3 * p3 * cb + np_ * 96,
+        # all colours of one step together: the FP32 gradient read and
+        # written once, x, u0, lambda, ub0 read once
+        "tile_scatter": (3 * p3 * 4 * 2 + np_ * 72) / launches_per_step,
+    }
+    return per_step[kernel]
+
+
+def source_digest():
+    """SHA-256 over the HIP sources, to tie a stored counter figure to the
+    kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2005_13193_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, config, dtype, clustered):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary for this workload (FETCH_SIZE + WRITE_SIZE, scaled by the copy
+    calibration), or None if there is none or the kernels changed since."""
+    dist = "clustered" if clustered else "uniform"
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{config}_{dist}_{dtype}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(n_full, np_full):
@@ -92,6 +152,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uniform", action="store_true",
                     help="uniform particles instead of the configuration's distribution")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB between two device buffers 3 times (reference "
+                         "kernel for scaling HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has "
@@ -99,6 +162,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        nb = args.copy_calibration * 2 ** 20
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for i in range(3):
+            b.copy_(a)
+            torch.cuda.synchronize()
+            log(f"[bench] copy {i + 1}/3 of {nb} bytes done")
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb}), flush=True)
+        return
 
     import paper_2005_13193_amd as pt
     from paper_2005_13193_amd import _binding as B
@@ -170,6 +244,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
+    for k in KERNELS:  # drop anything recorded before the timed region
+        B.pt_timing_read(k)
+    B.pt_timing_enable(True)
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(True)
@@ -183,16 +260,17 @@ def main():
     per = {k: acc[k] / args.steps for k in names}
     value = 2.0 * np_ / (ms_step * 1e-3)
 
-    # algorithmic bytes per call
-    n3, p3 = n ** 3, (n + 3) ** 3
-    bytes_call = {
-        "spline": 3 * n3 * (8 + 8 + 4 + cb),
-        "spline_bwd": 3 * (p3 * 4 + n3 * 4) + 3 * 3 * n3 * 8,
-        "rk2_fwd": 2 * interp_bytes(n, np_, cb) + np_ * 24,
-        "rk2_bwd": 2 * interp_bytes(n, np_, cb) + 3 * p3 * 4 * 2 + np_ * 48,
-    }
-    dom = max(per, key=per.get)
-    achieved = bytes_call[dom] / (per[dom] * 1e-3) / 1e9
+    kstats = {}
+    for k in KERNELS:
+        ms, nl = B.pt_timing_read(k)
+        if nl:
+            kstats[k] = {"ms_per_step": ms / args.steps, "launches_per_step": nl / args.steps,
+                         "avg_launch_ms": ms / nl}
+    B.pt_timing_enable(False)
+    dom = max(kstats, key=lambda k: kstats[k]["ms_per_step"])
+    bpl = launch_bytes(dom, n, np_, cb, kstats[dom]["launches_per_step"])
+    achieved = bpl / (kstats[dom]["avg_launch_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(dom, args.config, args.dtype, clustered)
     out = {
         "metric": METRIC, "value": value, "unit": "particle-interpolations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -202,9 +280,10 @@ def main():
                    "fwd+adjoint Heun step with cell sort", "grid": n, "particles": np_,
                    "kmax": kmax, "dt": dt, "coeff_dtype": args.dtype},
         "breakdown_ms": per,
+        "kernels": kstats,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": traffic, "algorithmic_bytes_per_launch": bpl},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")

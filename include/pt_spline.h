@@ -192,6 +192,17 @@ pt_status pt_last_device_error(hipStream_t stream);
 /* Static description of a status code. */
 const char *pt_status_string(pt_status status);
 
+/* Kernel timing (diagnostics, not on the hot path).  While enabled, the
+ * library brackets each launch of its main kernels with a pair of HIP events
+ * recorded on the launch stream.  pt_timing_read synchronises on the events
+ * of `kernel`, returns their summed elapsed time and count, and forgets them.
+ * Kernel names: "spline_x", "spline_y", "spline_y_pad" (the y pass that
+ * writes the padded coefficients), "spline_z", "spline_fold",
+ * "sort_keys", "sort_pass", "sort_permute", "tile_rk2_fwd",
+ * "tile_rk2_bwd_gather", "tile_scatter", "interp". */
+pt_status pt_timing_enable(int on);
+pt_status pt_timing_read(const char *kernel, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,7 +35,7 @@ PT_OP_RK2_BWD = 4
 EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_sort_particles",
            "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
-           "pt_status_string")
+           "pt_status_string", "pt_timing_enable", "pt_timing_read")
 
 
 class PtGrid(ctypes.Structure):
@@ -72,6 +72,8 @@ def _load():
                             vp],
         "pt_last_device_error": [vp],
         "pt_status_string": [ctypes.c_int],
+        "pt_timing_enable": [ctypes.c_int],
+        "pt_timing_read": [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -235,3 +237,15 @@ def pt_rk2_step_bwd(grid, coeff, dt, pos_n, sort, g_pos, g_coeff, ws, stream=Non
 
 def pt_last_device_error(stream=None):
     return LIB.pt_last_device_error(_stream(stream))
+
+
+def pt_timing_enable(on):
+    _check("pt_timing_enable", LIB.pt_timing_enable(1 if on else 0))
+
+
+def pt_timing_read(kernel):
+    """(total milliseconds, launches) recorded for `kernel` since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check("pt_timing_read", LIB.pt_timing_read(kernel.encode(), ctypes.byref(ms),
+                                                ctypes.byref(n)))
+    return ms.value, n.value

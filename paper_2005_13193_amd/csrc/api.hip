@@ -1,7 +1,11 @@
 // C ABI entry points: host-side argument validation, workspace carving and
 // dispatch to the kernels of solve.hip, sort.hip, gather.hip and tile.hip.
 #include <math.h>
+#include <string.h>
+
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "pt_common.h"
 
@@ -64,6 +68,25 @@ int* device_error_flag() {
     g_flag_ptr[dev] = (int*)p;
   }
   return g_flag_ptr[dev];
+}
+
+// ------------------------------------------------------------- timing ---
+struct TimingRec {
+  std::string name;
+  hipEvent_t start, stop;
+};
+static std::mutex g_time_mu;
+static bool g_time_on = false;
+static std::vector<TimingRec> g_time_recs;
+
+bool timing_on() {
+  std::lock_guard<std::mutex> lock(g_time_mu);
+  return g_time_on;
+}
+
+void timing_record(const char* name, hipEvent_t start, hipEvent_t stop) {
+  std::lock_guard<std::mutex> lock(g_time_mu);
+  g_time_recs.push_back({name, start, stop});
 }
 
 static inline size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -335,6 +358,39 @@ pt_status pt_last_device_error(hipStream_t stream) {
     return PT_ERR_NONFINITE;
   }
   return PT_OK;
+}
+
+pt_status pt_timing_enable(int on) {
+  std::lock_guard<std::mutex> lock(g_time_mu);
+  g_time_on = on != 0;
+  return PT_OK;
+}
+
+pt_status pt_timing_read(const char* kernel, double* total_ms, int64_t* launches) {
+  if (!kernel || !total_ms || !launches) return PT_ERR_NULL;
+  std::lock_guard<std::mutex> lock(g_time_mu);
+  double sum = 0.0;
+  int64_t n = 0;
+  pt_status st = PT_OK;
+  std::vector<TimingRec> keep;
+  for (auto& r : g_time_recs) {
+    if (r.name != kernel) {
+      keep.push_back(r);
+      continue;
+    }
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.stop) != hipSuccess ||
+        hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
+      st = PT_ERR_HIP;
+    sum += ms;
+    ++n;
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  g_time_recs.swap(keep);
+  *total_ms = sum;
+  *launches = n;
+  return st;
 }
 
 const char* pt_status_string(pt_status s) {

@@ -240,6 +240,7 @@ pt_status interp_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_
   const GridDev gd = make_grid_dev(g);
   const dim3 grid(grid_1d(np, 256)), block(256);
   int* err = device_error_flag();
+  TimedLaunch t("interp", s);
   if (nout == 3) {
     if (dtype == PT_F32)
       hipLaunchKernelGGL((interp_kernel<float, 3>), grid, block, 0, s, gd, (const float*)coeff, np,

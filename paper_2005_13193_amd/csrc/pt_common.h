@@ -123,3 +123,35 @@ inline unsigned grid_1d(int64_t n, int block) {
   } while (0)
 
 #define PT_LAUNCH_CHECK() PT_HIP_CHECK(hipGetLastError())
+
+namespace pt {
+// Optional per-kernel timing: while enabled (pt_timing_enable), launches
+// wrapped in a TimedLaunch record a pair of HIP events on their stream.
+bool timing_on();
+void timing_record(const char* name, hipEvent_t start, hipEvent_t stop);
+
+struct TimedLaunch {
+  const char* name;
+  hipStream_t stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TimedLaunch(const char* n, hipStream_t s) : name(n), stream(s) {
+    if (!timing_on()) return;
+    if (hipEventCreate(&e0) != hipSuccess) {
+      e0 = nullptr;
+      return;
+    }
+    if (hipEventCreate(&e1) != hipSuccess) {
+      hipEventDestroy(e0);
+      e0 = e1 = nullptr;
+      return;
+    }
+    hipEventRecord(e0, stream);
+  }
+  ~TimedLaunch() {
+    if (e0 && e1) {
+      hipEventRecord(e1, stream);
+      timing_record(name, e0, e1);
+    }
+  }
+};
+}  // namespace pt

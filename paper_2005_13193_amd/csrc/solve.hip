@@ -188,6 +188,7 @@ static pt_status pass_rows(const float* in, float* out, int nx, int ny, int nz,
   const int rpb = 256 / cpr;
   const int64_t nrows = (int64_t)ny * nz;
   const unsigned blocks = (unsigned)((nrows + rpb - 1) / rpb);
+  TimedLaunch t("spline_x", s);
   hipLaunchKernelGGL(solve_rows, dim3(blocks), dim3(256), 0, s, in, out, nx, nrows, rpb, cpr);
   PT_LAUNCH_CHECK();
   return PT_OK;
@@ -214,6 +215,7 @@ static pt_status pass_strided(const float* in, void* out, int nx, int ny, int nz
   }
   const int nchunks = (a.na + kChunk - 1) / kChunk;
   dim3 grid((a.lx + 63) / 64, a.lb, (nchunks + 3) / 4);
+  TimedLaunch t(axis == 2 ? "spline_z" : (mode == OUT_PLAIN ? "spline_y" : "spline_y_pad"), s);
   if (mode == OUT_PLAIN)
     hipLaunchKernelGGL(solve_strided<OUT_PLAIN>, grid, dim3(256), 0, s, a);
   else if (mode == OUT_PAD_F32)
@@ -259,8 +261,11 @@ pt_status spline_bwd(const pt_grid* g, const float* gcoeff, float* gfield, float
   const int64_t p3 = (int64_t)(nx + 3) * (ny + 3) * (nz + 3);
   for (int c = 0; c < 3; ++c) {
     float* o = gfield + c * n3;
-    hipLaunchKernelGGL(fold_pad, dim3(grid_1d(n3, 256)), dim3(256), 0, s, gcoeff + c * p3, ws,
+    {
+      TimedLaunch t("spline_fold", s);
+      hipLaunchKernelGGL(fold_pad, dim3(grid_1d(n3, 256)), dim3(256), 0, s, gcoeff + c * p3, ws,
                        nx, ny, nz);
+    }
     PT_LAUNCH_CHECK();
     pt_status st = pass_strided(ws, o, nx, ny, nz, 1, OUT_PLAIN, s);  // y
     if (st != PT_OK) return st;

@@ -267,12 +267,16 @@ static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int3
   uint32_t* vbuf[2] = {(uint32_t*)perm, w.vals0};
   const int first_dst = (passes - 1) & 1;
   const int src0 = first_dst ^ 1;
-  hipLaunchKernelGGL(cell_key_kernel<K>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd, np, pos,
-                     kbuf[src0], vbuf[src0], device_error_flag());
+  {
+    TimedLaunch t("sort_keys", s);
+    hipLaunchKernelGGL(cell_key_kernel<K>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd, np, pos,
+                       kbuf[src0], vbuf[src0], device_error_flag());
+  }
   PT_LAUNCH_CHECK();
   int src = src0;
   for (int p = 0; p < passes; ++p) {
     const int dst = src ^ 1;
+    TimedLaunch t("sort_pass", s);
     hipLaunchKernelGGL(radix_hist<K>, dim3(tblocks), dim3(256), 0, s, kbuf[src], np, 8 * p,
                        w.counts, nwt);
     PT_LAUNCH_CHECK();
@@ -300,6 +304,7 @@ pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double
                      : sort_impl<uint32_t>(g, np, pos, perm, keys_out, lstart, ws, s);
   if (st != PT_OK) return st;
   if (pos_sorted) {
+    TimedLaunch t("sort_permute", s);
     hipLaunchKernelGGL(permute_pos, dim3(grid_1d(np, 256)), dim3(256), 0, s, np, pos, perm,
                        pos_sorted);
     PT_LAUNCH_CHECK();

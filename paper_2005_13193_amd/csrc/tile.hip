@@ -1184,7 +1184,10 @@ static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int
 #define PT_TG(CT, MD)                                                                  \
   do {                                                                                 \
     if (!allow_lds(tile_gather<CT, MD>, lds)) return PT_ERR_HIP;                       \
-    hipLaunchKernelGGL((tile_gather<CT, MD>), dim3(blocks), dim3(kGTB), lds, s, a);    \
+    {                                                                                  \
+      TimedLaunch t(MD == TILE_RK2_FWD ? "tile_rk2_fwd" : "tile_rk2_bwd_gather", s);   \
+      hipLaunchKernelGGL((tile_gather<CT, MD>), dim3(blocks), dim3(kGTB), lds, s, a);  \
+    }                                                                                  \
     hipLaunchKernelGGL((gather_deferred<CT, MD>), dim3(256), dim3(256), 0, s, a);      \
   } while (0)
   if (dtype == PT_F32) {
@@ -1244,6 +1247,7 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   for (int color = 0; color < 8; ++color) {
     b.color = color;
     b.item_range = it.range + color;
+    TimedLaunch t("tile_scatter", s);
     hipLaunchKernelGGL(tile_scatter, dim3(blocks), dim3(kSTB), lds, s, b);
     PT_LAUNCH_CHECK();
   }

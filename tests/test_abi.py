@@ -106,3 +106,11 @@ def test_status_strings(b):
     for s in range(-8, 1):
         assert b.status_string(s) != "unknown status"
     assert b.status_string(-99) == "unknown status"
+
+
+def test_timing_registry_without_launches(b):
+    b.pt_timing_enable(True)
+    assert b.pt_timing_read("tile_scatter") == (0.0, 0)
+    b.pt_timing_enable(False)
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert b.LIB.pt_timing_read(None, ctypes.byref(ms), ctypes.byref(n)) == b.PT_ERR_NULL
