@@ -38,7 +38,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNELS = ("spline_x", "spline_y", "spline_y_pad", "spline_z", "spline_fold", "sort_keys",
+KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold", "sort_keys",
            "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter")
 
 
@@ -55,8 +55,8 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step):
     n3, p3, kb = n ** 3, (n + 3) ** 3, key_bytes(n)
     per_step = {
         "spline_x": 8 * n3, "spline_y": 8 * n3, "spline_z": 8 * n3,
-        "spline_y_pad": 4 * n3 + cb * p3,
-        "spline_fold": 4 * p3 + 4 * n3,
+        "spline_x_pad": 4 * n3 + cb * p3,
+        "spline_x_fold": 4 * p3 + 4 * n3,
         "sort_keys": np_ * (24 + kb + 4),
         "sort_pass": np_ * 2 * (kb + 4),
         "sort_permute": np_ * (4 + 24 + 24),

@@ -102,8 +102,9 @@ pt_status pt_key_layout(const pt_grid *grid, int32_t *tile_x, int32_t *tile_y,
  * Along every grid line of every axis the coefficients S solve the periodic
  * tridiagonal system (S[m-1] + 4 S[m] + S[m+1]) / 6 = g[m], m = 0..n-1
  * (indices mod n), so that the tensor-product cubic B-spline with
- * coefficients S interpolates the grid values exactly.  Axes are solved in
- * the paper's order x, z, y; the last pass writes the padded layout (rounded
+ * coefficients S interpolates the grid values exactly.  The axis solves
+ * commute; they run in the order z, y, x (the paper's order is x, z, y, which
+ * differs only in rounding), and the x pass writes the padded layout (rounded
  * to nearest-even for PT_BF16).
  *   field  in   float [3][nz][ny][nx]
  *   coeff  out  [3][nz+3][ny+3][nx+3] of `dtype`; must not overlap field
@@ -196,8 +197,9 @@ const char *pt_status_string(pt_status status);
  * library brackets each launch of its main kernels with a pair of HIP events
  * recorded on the launch stream.  pt_timing_read synchronises on the events
  * of `kernel`, returns their summed elapsed time and count, and forgets them.
- * Kernel names: "spline_x", "spline_y", "spline_y_pad" (the y pass that
- * writes the padded coefficients), "spline_z", "spline_fold",
+ * Kernel names: "spline_x", "spline_y", "spline_z", "spline_x_pad" (the x
+ * pass that writes the padded coefficients), "spline_x_fold" (the adjoint's
+ * x pass that reads the padded gradient),
  * "sort_keys", "sort_pass", "sort_permute", "tile_rk2_fwd",
  * "tile_rk2_bwd_gather", "tile_scatter", "interp". */
 pt_status pt_timing_enable(int on);

@@ -1,227 +1,500 @@
 // Operation 1 of Sec. 2.2: periodic cubic-spline coefficients, one periodic
 // tridiagonal solve (S[m-1] + 4 S[m] + S[m+1]) / 6 = g[m] per grid line and
-// axis.
+// axis, and its adjoint.
 //
 // GPU formulation.  The paper solves each line with the Thomas algorithm.
-// Here every line is cut into chunks of kChunk outputs, one chunk per thread,
-// and each chunk is solved by the factorised form of the same inverse:
+// Here the same inverse is applied in factorised form:
 //   A = -(1 / (6 z1)) (1 - z1 q^-1)(1 - z1 q),   z1 = sqrt(3) - 2,
 // i.e. a causal recursion c[m] = g[m] + z1 c[m-1], an anti-causal recursion
-// d[m] = c[m] + z1 d[m+1], and S = -6 z1 d (q the periodic shift).  Each
-// recursion is started kWarm points outside the chunk (periodic indices), so
-// a chunk needs no data from other threads; the start-up error is damped by
-// |z1|^kWarm = 7.2e-10 before it reaches the chunk, two orders of magnitude
-// below FP32 rounding.  Lines are read and written once per axis pass with
-// coalesced accesses (lanes across x for the y and z passes; rows staged in
-// LDS for the x pass).
+// d[m] = c[m] + z1 d[m+1], and S = -6 z1 d (q the periodic shift).
+//
+// A line is cut into chunks, one per thread.  Each thread runs both
+// recursions over its chunk starting from zero; the true state entering a
+// chunk is then an affine function of the local end values of the other
+// chunks.  Chunk k maps the state entering it to the state leaving it by
+// C -> z1^len_k C + e_k, so the state entering chunk k is
+//   C_in(k) = (e_{k-1} + z1^len_{k-1} e_{k-2} + ...) / (1 - z1^n),
+// summed once around the periodic line (the denominator closes the loop).
+// Each thread then adds z1^(i+1) C_in to its local causal values (and the
+// mirrored correction after the anti-causal pass).  The result is the exact
+// periodic solve with no overlap between chunks: every input is read from HBM
+// once and every output written once.
+//
+// Axis order.  The axis solves commute, so their order changes only the
+// rounding.  The paper's order is x, z, y; here it is z, y, x, so that the
+// pass that writes the padded layout (and, in the adjoint, the pass that
+// reads it) runs along x and moves whole rows:
+//  * solve_lines - lines along y or z: lanes run across x in groups of G
+//    consecutive points (coalesced 4G-byte segments); the waves of a
+//    workgroup hold consecutive chunks of the same lines and combine their
+//    chunk maps through LDS.
+//  * solve_rows  - lines along x: one wave per row, staged through LDS so
+//    that global loads and stores are contiguous across lanes; lane l then
+//    holds a contiguous chunk and the chunk maps are combined by a wave scan.
+//    Variants write all padded copies of the row (last forward pass) or sum
+//    the padded copies of the row (first adjoint pass).
+#include <math.h>
+
+#include <type_traits>
+
 #include "pt_common.h"
 
 namespace pt {
 
-constexpr int kChunk = 32;  // outputs per thread
-constexpr int kWarm = 16;   // warm-up points of each recursion
 constexpr float kZ1 = -0.26794919243112270f;  // sqrt(3) - 2
 constexpr float kGain = 1.6076951545867361f;  // -6 z1
 
-enum OutMode { OUT_PLAIN = 0, OUT_PAD_F32 = 1, OUT_PAD_BF16 = 2 };
+// z1^k rounded to FP32 (0 once it underflows).
+static float z1_pow(int k) {
+  double p = 1.0;
+  const double z = sqrt(3.0) - 2.0;
+  for (int i = 0; i < k && p != 0.0; ++i) p *= z;
+  return (float)p;
+}
 
-// Lines along axis A (length na, input stride sa); 64 lanes across x (stride
-// 1); third axis B (length nb, input stride sb).  With a padded output the
-// lane and B indices run over the padded extents and read the periodic
-// source line (X - 1) mod n; the A index writes padded P = m + 1 plus the
-// three wrapped copies.
-struct StridedArgs {
-  const float* in;
-  void* out;
-  int nx, na, nb;
-  int64_t sa, sb;    // input strides
-  int lx, lb;        // lane / B extents of the launch (n or n + 3)
-  int64_t osa, osb;  // output strides along A and B
-};
+// Padded index that also holds grid index m (besides m + 1), or -1.
+__device__ __forceinline__ int pad_extra(int m, int n) {
+  return m == n - 1 ? 0 : (m == 0 ? n + 1 : (m == 1 ? n + 2 : -1));
+}
 
-template <int MODE>
-__global__ __launch_bounds__(256) void solve_strided(StridedArgs a) {
-  const int X = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int chunk = blockIdx.z * 4 + (threadIdx.x >> 6);
-  const int B = blockIdx.y;
-  const int m0 = chunk * kChunk;
-  if (X >= a.lx || m0 >= a.na) return;
-  const int x = MODE == OUT_PLAIN ? X : (X - 1 + a.nx) % a.nx;
-  const int b = MODE == OUT_PLAIN ? B : (B - 1 + a.nb) % a.nb;
-  const float* line = a.in + x + (int64_t)b * a.sb;
+// ------------------------------------------------------- chunk phases ---
+// A thread's chunk lives in v[0..Q) with len <= Q valid points.  The phases
+// touch all Q registers with selects instead of branches (FULL: len == Q),
+// and points past len stay zero through both recursions.
 
-  float cbuf[kChunk + kWarm];
-  float c = 0.0f;
-  int j = ((m0 - kWarm) % a.na + a.na) % a.na;
+// Causal recursion from zero; returns the local end state.
+template <int Q, bool FULL>
+__device__ __forceinline__ float causal_local(float (&v)[Q], int len) {
+  float c = 0.0f, e = 0.0f;
 #pragma unroll
-  for (int it = 0; it < kChunk + 2 * kWarm; ++it) {
-    c = line[(int64_t)j * a.sa] + kZ1 * c;
-    if (it >= kWarm) cbuf[it - kWarm] = c;
-    j = (j + 1 == a.na) ? 0 : j + 1;
+  for (int i = 0; i < Q; ++i) {
+    c = v[i] + kZ1 * c;
+    v[i] = (FULL || i < len) ? c : 0.0f;
+    e = FULL ? c : (i == len - 1 ? c : e);
   }
-  float res[kChunk];
+  return e;
+}
+
+// Adds z1^(i+1) cin to point i (the carry entering the chunk).
+template <int Q, bool FULL>
+__device__ __forceinline__ void causal_carry(float (&v)[Q], int len, float cin) {
+  float p = kZ1 * cin;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    v[i] += (FULL || i < len) ? p : 0.0f;
+    p *= kZ1;
+  }
+}
+
+// Anti-causal recursion from zero (points past len are zero, so it starts at
+// len - 1); returns the local state at the chunk start.
+template <int Q>
+__device__ __forceinline__ float anticausal_local(float (&v)[Q]) {
   float d = 0.0f;
 #pragma unroll
-  for (int it = kChunk + kWarm - 1; it >= 0; --it) {
-    d = cbuf[it] + kZ1 * d;
-    if (it < kChunk) res[it] = kGain * d;
+  for (int i = Q - 1; i >= 0; --i) {
+    d = v[i] + kZ1 * d;
+    v[i] = d;
   }
-  const int len = min(kChunk, a.na - m0);
-  if (MODE == OUT_PLAIN) {
-    float* o = (float*)a.out + x + (int64_t)b * a.sb + (int64_t)m0 * a.sa;
+  return d;
+}
+
+// Adds z1^(len-i) din to point i < len (the carry entering from the right).
+template <int Q, bool FULL>
+__device__ __forceinline__ void anticausal_carry(float (&v)[Q], int len, float din) {
+  float p = 0.0f;
 #pragma unroll
-    for (int it = 0; it < kChunk; ++it)
-      if (it < len) o[(int64_t)it * a.sa] = res[it];
-  } else {
-    const int64_t base = X + (int64_t)B * a.osb;
+  for (int i = Q - 1; i >= 0; --i) {
+    p = (FULL ? i == Q - 1 : i == len - 1) ? kZ1 * din : p * kZ1;
+    v[i] += p;
+  }
+}
+
+// ------------------------------------------------------------ x lines ---
+enum RowMode { ROW_PLAIN = 0, ROW_PAD_F32 = 1, ROW_PAD_BF16 = 2, ROW_FOLD = 3 };
+
+//  PLAIN: plain rows in and out.
+//  PAD_*: plain rows in; the solved row (y, z) is written to every padded
+//         row that holds it (y+1 and z+1, plus the wrapped copies), with its
+//         x padding.
+//  FOLD:  padded rows in: output row (y, z) is the solve of the sum of the
+//         padded copies of the row and, along x, of each point's copies.
+struct RowArgs {
+  const float* in;
+  void* out;
+  int nx, ny, nz;
+  int q;       // points per lane chunk, ceil(nx / 64)
+  int nrows;   // ny * nz
+  int pitch;   // LDS floats per wave
+};
+
+// LDS slot of row element p: one pad word per 16 keeps the chunk view
+// (lane l reads l q + i) free of bank conflicts for q = 16.
+__device__ __forceinline__ int lds_ix(int p) { return p + (p >> 4); }
+
+template <typename T>
+__device__ __forceinline__ void put(void* out, int64_t i, float s) {
+  if constexpr (sizeof(T) == 4) ((float*)out)[i] = s;
+  else ((uint16_t*)out)[i] = f32_to_bf16_rne(s);
+}
+
+template <int MODE, int Q>
+__global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int r = blockIdx.x * (blockDim.x >> 6) + wid;
+  const bool active = r < a.nrows;  // inactive waves still reach the barriers
+  const int nx = a.nx, px = nx + 3;
+  const int64_t py = a.ny + 3;
+  const int y = active ? r % a.ny : 0, z = active ? r / a.ny : 0;
+  float* L = lds + wid * a.pitch;
+
+  // 1. contiguous loads (all issued before the first LDS write), then LDS.
+  // A row has at most 64 Q + 3 points: Q + 1 loads per lane.
+  constexpr int J = Q + 1;
+  float w[J];
+  if (active) {
+    if (MODE == ROW_FOLD) {
+      const float* in = a.in;
+      const int ye = pad_extra(y, a.ny), ze = pad_extra(z, a.nz);
+      const float* r00 = in + ((int64_t)(z + 1) * py + (y + 1)) * px;
+      const float* r01 = in + ((int64_t)(z + 1) * py + ye) * px;
+      const float* r10 = in + ((int64_t)ze * py + (y + 1)) * px;
+      const float* r11 = in + ((int64_t)ze * py + ye) * px;
 #pragma unroll
-    for (int it = 0; it < kChunk; ++it) {
-      if (it < len) {
-        const int m = m0 + it;
-        float v = res[it];
-        int P[2] = {m + 1, m == a.na - 1 ? 0 : (m == 0 ? a.na + 1 : (m == 1 ? a.na + 2 : -1))};
+      for (int j = 0; j < J; ++j) {
+        const int p = lane + 64 * j;
+        w[j] = p < px ? r00[p] : 0.0f;
+      }
+      if (ye >= 0) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          if (P[q] < 0) continue;
-          int64_t idx = base + (int64_t)P[q] * a.osa;
-          if (MODE == OUT_PAD_F32) ((float*)a.out)[idx] = v;
-          else ((uint16_t*)a.out)[idx] = f32_to_bf16_rne(v);
+        for (int j = 0; j < J; ++j) {
+          const int p = lane + 64 * j;
+          if (p < px) w[j] += r01[p];
+        }
+      }
+      if (ze >= 0) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const int p = lane + 64 * j;
+          if (p < px) w[j] += r10[p] + (ye >= 0 ? r11[p] : 0.0f);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int p = lane + 64 * j;
+        if (p < px) L[lds_ix(p)] = w[j];
+      }
+    } else {
+      const float* src = a.in + (int64_t)r * nx;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int p = lane + 64 * j;
+        w[j] = p < nx ? src[p] : 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int p = lane + 64 * j;
+        if (p < nx) L[lds_ix(p)] = w[j];
+      }
+    }
+  }
+  __syncthreads();
+
+  // 2. chunk view: lane l takes points [l q, l q + len)
+  const int m0 = lane * a.q;
+  const int len = active ? min(max(nx - m0, 0), a.q) : 0;
+  const int last = max(len - 1, 0);
+  const int off = MODE == ROW_FOLD ? 1 : 0;  // padded position of point x is x + 1
+  float v[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int x = min(m0 + min(i, last), nx - 1);  // in the row even when len = 0
+    float t = L[lds_ix(x + off)];
+    if (MODE == ROW_FOLD) {
+      const int xe = pad_extra(x, nx);
+      if (xe >= 0) t += L[lds_ix(xe)];
+    }
+    v[i] = i < len ? t : 0.0f;
+  }
+  __syncthreads();
+
+  // 3. the periodic solve of the row
+  float a_len = 1.0f;  // z1^len
+#pragma unroll
+  for (int i = 0; i < Q; ++i) a_len = i < len ? a_len * kZ1 : a_len;
+  const float e = causal_local<Q, false>(v, len);
+  float sa = a_len, se = e;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const float pa = __shfl_up(sa, d), pe = __shfl_up(se, d);
+    if (lane >= d) {
+      se = sa * pe + se;
+      sa = sa * pa;
+    }
+  }
+  {
+    // the whole row maps C -> A C + B; periodicity fixes C = B / (1 - A)
+    const float A = __shfl(sa, 63), B = __shfl(se, 63);
+    const float C0 = B / (1.0f - A);
+    const float pa = __shfl_up(sa, 1), pe = __shfl_up(se, 1);
+    causal_carry<Q, false>(v, len, lane == 0 ? C0 : pa * C0 + pe);
+  }
+  const float f = anticausal_local<Q>(v);
+  sa = a_len;
+  float sf = f;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) {
+    const float pa = __shfl_down(sa, s), pf = __shfl_down(sf, s);
+    if (lane + s < 64) {
+      sf = sa * pf + sf;
+      sa = sa * pa;
+    }
+  }
+  {
+    const float A = __shfl(sa, 0), B = __shfl(sf, 0);
+    const float D0 = B / (1.0f - A);
+    const float pa = __shfl_down(sa, 1), pf = __shfl_down(sf, 1);
+    anticausal_carry<Q, false>(v, len, lane == 63 ? D0 : pa * D0 + pf);
+  }
+
+  // 4. results back to LDS (padded positions for PAD), then contiguous stores
+  const bool pad_out = MODE == ROW_PAD_F32 || MODE == ROW_PAD_BF16;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (i < len) {
+      const int x = m0 + i;
+      const float s = kGain * v[i];
+      if (pad_out) {
+        L[lds_ix(x + 1)] = s;
+        const int xe = pad_extra(x, nx);
+        if (xe >= 0) L[lds_ix(xe)] = s;
+      } else {
+        L[lds_ix(x)] = s;
+      }
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  const int n_out = pad_out ? px : nx;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int p = lane + 64 * j;
+    w[j] = p < n_out ? L[lds_ix(p)] : 0.0f;
+  }
+  if (pad_out) {
+    using T = typename std::conditional<MODE == ROW_PAD_F32, float, uint16_t>::type;
+    const int ye = pad_extra(y, a.ny), ze = pad_extra(z, a.nz);
+    const int Ys[2] = {y + 1, ye}, Zs[2] = {z + 1, ze};
+    for (int zc = 0; zc < 2; ++zc) {
+      if (Zs[zc] < 0) continue;
+      for (int yc = 0; yc < 2; ++yc) {
+        if (Ys[yc] < 0) continue;
+        const int64_t row = ((int64_t)Zs[zc] * py + Ys[yc]) * px;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const int p = lane + 64 * j;
+          if (p < px) put<T>(a.out, row + p, w[j]);
         }
       }
     }
+  } else {
+    float* dst = (float*)a.out + (int64_t)r * nx;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int p = lane + 64 * j;
+      if (p < nx) dst[p] = w[j];
+    }
   }
 }
 
-// x pass: rows (contiguous lines of nx points) staged through LDS.  Element p
-// of a row sits at LDS offset p + p/32 so that the 32 chunks of a row start
-// in different banks.
-constexpr int kRowLds = 8192 + 512;
+// ------------------------------------------------------- y / z lines ---
+// Lines along axis A (length na), stride sa; lanes across x; third axis B
+// (stride sb); plain layout in and out.
+struct LineArgs {
+  const float* in;
+  float* out;
+  int nx, na;
+  int64_t sa, sb;
+  int G;          // x points per lane group; a wave holds 64 / G chunks
+  int K;          // chunks per line
+  int L;          // chunk length
+  float a_full;   // z1^L
+  float a_last;   // z1^(length of the last, shorter chunk)
+  float closure;  // 1 / (1 - z1^na)
+  int bx0;        // first x-block of the launch
+};
 
-__global__ __launch_bounds__(256) void solve_rows(const float* __restrict__ in,
-                                                  float* __restrict__ out, int nx,
-                                                  int64_t nrows, int rows_per_block,
-                                                  int cpr) {
-  __shared__ float lds[kRowLds];
-  const int rs = nx + (nx >> 5) + 1;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-  const int nr = (int)min((int64_t)rows_per_block, nrows - r0);
-  const int tid = threadIdx.x;
-  const float* src = in + r0 * nx;
-  for (int r = 0; r < nr; ++r)
-    for (int p = tid; p < nx; p += 256) lds[r * rs + p + (p >> 5)] = src[(int64_t)r * nx + p];
-  __syncthreads();
-
-  const int r = tid / cpr, q = tid - r * cpr;
-  const int m0 = q * kChunk;
-  const bool active = r < nr && m0 < nx;
-  float res[kChunk];
-  if (active) {
-    const float* row = lds + r * rs;
-    float cbuf[kChunk + kWarm];
-    float c = 0.0f;
-    int j = ((m0 - kWarm) % nx + nx) % nx;
-#pragma unroll
-    for (int it = 0; it < kChunk + 2 * kWarm; ++it) {
-      c = row[j + (j >> 5)] + kZ1 * c;
-      if (it >= kWarm) cbuf[it - kWarm] = c;
-      j = (j + 1 == nx) ? 0 : j + 1;
-    }
-    float d = 0.0f;
-#pragma unroll
-    for (int it = kChunk + kWarm - 1; it >= 0; --it) {
-      d = cbuf[it] + kZ1 * d;
-      if (it < kChunk) res[it] = kGain * d;
-    }
-  }
-  __syncthreads();
-  if (active) {
-    float* row = lds + r * rs;
-    const int len = min(kChunk, nx - m0);
-#pragma unroll
-    for (int it = 0; it < kChunk; ++it) {
-      const int p = m0 + it;
-      if (it < len) row[p + (p >> 5)] = res[it];
-    }
-  }
-  __syncthreads();
-  float* dst = out + r0 * nx;
-  for (int rr = 0; rr < nr; ++rr)
-    for (int p = tid; p < nx; p += 256) dst[(int64_t)rr * nx + p] = lds[rr * rs + p + (p >> 5)];
+__device__ __forceinline__ float chunk_gain(const LineArgs& a, int k) {
+  const int lk = min(max(a.na - k * a.L, 0), a.L);
+  return lk == a.L ? a.a_full : (lk == 0 ? 1.0f : a.a_last);
 }
 
-// Adjoint of the padding: every grid point collects the padded entries that
-// copy it (P = m + 1 along each axis, plus P = 0 for m = n-1, P = n+1 for
-// m = 0 and P = n+2 for m = 1).
-__global__ __launch_bounds__(256) void fold_pad(const float* __restrict__ gpad,
-                                                float* __restrict__ g, int nx, int ny, int nz) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t n3 = (int64_t)nx * ny * nz;
-  if (i >= n3) return;
-  const int x = (int)(i % nx);
-  const int y = (int)((i / nx) % ny);
-  const int z = (int)(i / ((int64_t)nx * ny));
-  const int px = nx + 3, py = ny + 3;
-  auto extra = [](int m, int n) { return m == n - 1 ? 0 : (m == 0 ? n + 1 : (m == 1 ? n + 2 : -1)); };
-  const int X[2] = {x + 1, extra(x, nx)};
-  const int Y[2] = {y + 1, extra(y, ny)};
-  const int Z[2] = {z + 1, extra(z, nz)};
-  float s = 0.0f;
-  for (int c = 0; c < 2; ++c) {
-    if (Z[c] < 0) continue;
-    for (int b = 0; b < 2; ++b) {
-      if (Y[b] < 0) continue;
-      for (int a = 0; a < 2; ++a) {
-        if (X[a] < 0) continue;
-        s += gpad[((int64_t)Z[c] * py + Y[b]) * px + X[a]];
-      }
+// FULL: every thread of the launch holds a whole chunk of Q = L points
+// (launched only on x-blocks inside nx, with K * L = na).
+template <int Q, bool FULL>
+__global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
+  __shared__ float s_e[1024];
+  __shared__ float s_f[1024];
+  const int lane = threadIdx.x & 63;
+  const int xg = lane & (a.G - 1);
+  const int k = (threadIdx.x >> 6) * (64 / a.G) + lane / a.G;
+  const int x = (blockIdx.x + a.bx0) * a.G + xg;
+  const int b = blockIdx.y;
+  const int m0 = k * a.L;
+  const int len = FULL ? Q : (x < a.nx ? min(max(a.na - m0, 0), a.L) : 0);
+  const int last = max(len - 1, 0);
+
+  float v[Q];
+  {
+    // clamped addresses keep every load in bounds; selects zero the rest
+    const float* src = len > 0 ? a.in + x + (int64_t)b * a.sb + (int64_t)m0 * a.sa : a.in;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float t = *src;
+      v[i] = (FULL || i < len) ? t : 0.0f;
+      src += (FULL || i < last) ? a.sa : 0;
     }
   }
-  g[i] = s;
+
+  s_e[k * a.G + xg] = causal_local<Q, FULL>(v, len);
+  __syncthreads();
+  {
+    float cin = 0.0f, P = 1.0f;
+    for (int j = 1; j <= a.K && P != 0.0f; ++j) {
+      int kk = k - j;
+      if (kk < 0) kk += a.K;
+      cin += P * s_e[kk * a.G + xg];
+      P *= chunk_gain(a, kk);
+    }
+    causal_carry<Q, FULL>(v, len, cin * a.closure);
+  }
+  s_f[k * a.G + xg] = anticausal_local<Q>(v);
+  __syncthreads();
+  {
+    float din = 0.0f, R = 1.0f;
+    for (int j = 1; j <= a.K && R != 0.0f; ++j) {
+      int kk = k + j;
+      if (kk >= a.K) kk -= a.K;
+      din += R * s_f[kk * a.G + xg];
+      R *= chunk_gain(a, kk);
+    }
+    anticausal_carry<Q, FULL>(v, len, din * a.closure);
+  }
+
+  float* o = a.out + x + (int64_t)b * a.sb + (int64_t)m0 * a.sa;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (FULL || i < len) *o = kGain * v[i];
+    o += a.sa;
+  }
 }
 
 // ------------------------------------------------------------ launchers ---
 
-static pt_status pass_rows(const float* in, float* out, int nx, int ny, int nz,
+static pt_status pass_rows(const float* in, void* out, int nx, int ny, int nz, int mode,
                            hipStream_t s) {
-  const int cpr = (nx + kChunk - 1) / kChunk;
-  if (cpr > 256) return PT_ERR_UNSUPPORTED;
-  const int rpb = 256 / cpr;
-  const int64_t nrows = (int64_t)ny * nz;
-  const unsigned blocks = (unsigned)((nrows + rpb - 1) / rpb);
-  TimedLaunch t("spline_x", s);
-  hipLaunchKernelGGL(solve_rows, dim3(blocks), dim3(256), 0, s, in, out, nx, nrows, rpb, cpr);
+  RowArgs a;
+  a.in = in;
+  a.out = out;
+  a.nx = nx; a.ny = ny; a.nz = nz;
+  a.q = (nx + 63) / 64;
+  a.nrows = ny * nz;
+  const int px = nx + 3;
+  a.pitch = px + (px >> 4) + 1;
+  const int waves = 4 * (size_t)a.pitch * 4 <= 64 * 1024 ? 4 : 1;
+  const size_t lds = (size_t)waves * a.pitch * 4;
+  const unsigned blocks = (unsigned)((a.nrows + waves - 1) / waves);
+  const char* name = mode == ROW_FOLD ? "spline_x_fold"
+                     : mode == ROW_PLAIN ? "spline_x" : "spline_x_pad";
+  TimedLaunch t(name, s);
+#define PT_ROWS(M, QQ) \
+  hipLaunchKernelGGL((solve_rows<M, QQ>), dim3(blocks), dim3(64 * waves), lds, s, a)
+#define PT_ROWS_Q(M)                    \
+  do {                                  \
+    if (a.q <= 4) PT_ROWS(M, 4);        \
+    else if (a.q <= 8) PT_ROWS(M, 8);   \
+    else if (a.q <= 16) PT_ROWS(M, 16); \
+    else if (a.q <= 32) PT_ROWS(M, 32); \
+    else if (a.q <= 64) PT_ROWS(M, 64); \
+    else PT_ROWS(M, 128);               \
+  } while (0)
+  if (a.q > 128) return PT_ERR_UNSUPPORTED;
+  switch (mode) {
+    case ROW_PLAIN: PT_ROWS_Q(ROW_PLAIN); break;
+    case ROW_PAD_F32: PT_ROWS_Q(ROW_PAD_F32); break;
+    case ROW_PAD_BF16: PT_ROWS_Q(ROW_PAD_BF16); break;
+    default: PT_ROWS_Q(ROW_FOLD); break;
+  }
+#undef PT_ROWS_Q
+#undef PT_ROWS
   PT_LAUNCH_CHECK();
   return PT_OK;
 }
 
-// axis 1 = y, axis 2 = z; padded output only for the last pass along y.
-static pt_status pass_strided(const float* in, void* out, int nx, int ny, int nz, int axis,
-                              int mode, hipStream_t s) {
-  StridedArgs a;
+// Chunking of a line of length na into at most 16 waves: (Q points per
+// chunk at most, G x-points per lane group).  Wide lane groups come first:
+// measured at 1024^3, 256-byte row segments (G = 64) beat 128-byte ones by
+// 10-20 %, and 64-byte ones are 1.6x slower.  Long lines (the large grids)
+// take Q = 64 to keep G = 64.
+static bool line_shape(int na, int* Q, int* G, int* waves) {
+  static const int kCand[8][2] = {{64, 64}, {32, 64}, {32, 32}, {64, 64}, {64, 32},
+                                  {32, 16}, {64, 16}, {64, 8}};
+  for (int i = na >= 1024 ? 0 : 1; i < 8; ++i) {
+    const int q = kCand[i][0], g = kCand[i][1];
+    const int per_wave = 64 / g;
+    const int w = (na + per_wave * q - 1) / (per_wave * q);
+    if (w <= 16) {
+      *Q = q;
+      *G = g;
+      *waves = w;
+      return true;
+    }
+  }
+  return false;
+}
+
+// axis 1 = y, axis 2 = z; plain layout in and out.
+static pt_status pass_lines(const float* in, float* out, int nx, int ny, int nz, int axis,
+                            hipStream_t s) {
+  LineArgs a;
   a.in = in;
   a.out = out;
   a.nx = nx;
+  int nb;
   if (axis == 1) {
-    a.na = ny; a.sa = nx; a.nb = nz; a.sb = (int64_t)nx * ny;
+    a.na = ny; nb = nz;
+    a.sa = nx; a.sb = (int64_t)nx * ny;
   } else {
-    a.na = nz; a.sa = (int64_t)nx * ny; a.nb = ny; a.sb = nx;
+    a.na = nz; nb = ny;
+    a.sa = (int64_t)nx * ny; a.sb = nx;
   }
-  if (mode == OUT_PLAIN) {
-    a.lx = nx; a.lb = a.nb; a.osa = a.sa; a.osb = a.sb;
-  } else {
-    // padded layout [nz+3][ny+3][nx+3], lines along y, B = z
-    if (axis != 1) return PT_ERR_UNSUPPORTED;
-    a.lx = nx + 3; a.lb = nz + 3; a.osa = nx + 3; a.osb = (int64_t)(nx + 3) * (ny + 3);
+  int Q = 0, G = 0, waves = 0;
+  if (!line_shape(a.na, &Q, &G, &waves)) return PT_ERR_UNSUPPORTED;
+  a.G = G;
+  a.K = waves * (64 / G);
+  a.L = (a.na + a.K - 1) / a.K;
+  a.a_full = z1_pow(a.L);
+  a.a_last = z1_pow(a.na - (a.na / a.L) * a.L);
+  a.closure = (float)(1.0 / (1.0 - (double)z1_pow(a.na)));
+  // Whole chunks everywhere except possibly a last, partial x-block: the
+  // FULL kernel takes the whole x-blocks, the general one the rest.
+  const int xblocks = (nx + G - 1) / G;
+  const int full_x = (a.L == Q && a.K * a.L == a.na) ? nx / G : 0;
+  const dim3 block(64 * waves);
+  TimedLaunch t(axis == 2 ? "spline_z" : "spline_y", s);
+  if (full_x > 0) {
+    a.bx0 = 0;
+    if (Q == 32) hipLaunchKernelGGL((solve_lines<32, true>), dim3(full_x, nb), block, 0, s, a);
+    else hipLaunchKernelGGL((solve_lines<64, true>), dim3(full_x, nb), block, 0, s, a);
   }
-  const int nchunks = (a.na + kChunk - 1) / kChunk;
-  dim3 grid((a.lx + 63) / 64, a.lb, (nchunks + 3) / 4);
-  TimedLaunch t(axis == 2 ? "spline_z" : (mode == OUT_PLAIN ? "spline_y" : "spline_y_pad"), s);
-  if (mode == OUT_PLAIN)
-    hipLaunchKernelGGL(solve_strided<OUT_PLAIN>, grid, dim3(256), 0, s, a);
-  else if (mode == OUT_PAD_F32)
-    hipLaunchKernelGGL(solve_strided<OUT_PAD_F32>, grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(solve_strided<OUT_PAD_BF16>, grid, dim3(256), 0, s, a);
+  if (full_x < xblocks) {
+    a.bx0 = full_x;
+    const dim3 g2(xblocks - full_x, nb);
+    if (Q == 32) hipLaunchKernelGGL((solve_lines<32, false>), g2, block, 0, s, a);
+    else hipLaunchKernelGGL((solve_lines<64, false>), g2, block, 0, s, a);
+  }
   PT_LAUNCH_CHECK();
   return PT_OK;
 }
@@ -238,22 +511,26 @@ pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype
   const int64_t p3 = (int64_t)(nx + 3) * (ny + 3) * (nz + 3);
   for (int c = 0; c < 3; ++c) {
     const float* f = field + c * n3;
-    // x pass into a scratch line set, z pass, then the y pass writes the
-    // padded coefficients (the paper's axis order x, z, y).  For FP32 output
-    // the component's own output block serves as the first scratch array.
+    // z pass into a scratch array, y pass, then the x pass writes the padded
+    // coefficients.  For FP32 output the component's own output block (read
+    // by the y pass before the x pass overwrites it) is the first scratch.
     float* t1 = dtype == PT_F32 ? (float*)coeff + c * p3 : ws;
     float* t2 = dtype == PT_F32 ? ws : ws + n3;
-    pt_status st = pass_rows(f, t1, nx, ny, nz, s);
+    pt_status st = pass_lines(f, t1, nx, ny, nz, 2, s);
     if (st != PT_OK) return st;
-    st = pass_strided(t1, t2, nx, ny, nz, 2, OUT_PLAIN, s);
+    st = pass_lines(t1, t2, nx, ny, nz, 1, s);
     if (st != PT_OK) return st;
-    void* o = dtype == PT_F32 ? (void*)((float*)coeff + c * p3) : (void*)((uint16_t*)coeff + c * p3);
-    st = pass_strided(t2, o, nx, ny, nz, 1, dtype == PT_F32 ? OUT_PAD_F32 : OUT_PAD_BF16, s);
+    void* o = dtype == PT_F32 ? (void*)((float*)coeff + c * p3)
+                              : (void*)((uint16_t*)coeff + c * p3);
+    st = pass_rows(t2, o, nx, ny, nz, dtype == PT_F32 ? ROW_PAD_F32 : ROW_PAD_BF16, s);
     if (st != PT_OK) return st;
   }
   return PT_OK;
 }
 
+// Adjoint.  The forward map is pad(A_x^-1 A_y^-1 A_z^-1 g); its transpose is
+// A_z^-1 A_y^-1 A_x^-1 fold(S_bar) (A symmetric): the same solves in reverse
+// axis order, the first one reading and folding the padded gradient.
 pt_status spline_bwd(const pt_grid* g, const float* gcoeff, float* gfield, float* ws,
                      hipStream_t s) {
   const int nx = g->nx, ny = g->ny, nz = g->nz;
@@ -261,17 +538,11 @@ pt_status spline_bwd(const pt_grid* g, const float* gcoeff, float* gfield, float
   const int64_t p3 = (int64_t)(nx + 3) * (ny + 3) * (nz + 3);
   for (int c = 0; c < 3; ++c) {
     float* o = gfield + c * n3;
-    {
-      TimedLaunch t("spline_fold", s);
-      hipLaunchKernelGGL(fold_pad, dim3(grid_1d(n3, 256)), dim3(256), 0, s, gcoeff + c * p3, ws,
-                       nx, ny, nz);
-    }
-    PT_LAUNCH_CHECK();
-    pt_status st = pass_strided(ws, o, nx, ny, nz, 1, OUT_PLAIN, s);  // y
+    pt_status st = pass_rows(gcoeff + c * p3, o, nx, ny, nz, ROW_FOLD, s);  // fold + x
     if (st != PT_OK) return st;
-    st = pass_strided(o, ws, nx, ny, nz, 2, OUT_PLAIN, s);  // z
+    st = pass_lines(o, ws, nx, ny, nz, 1, s);  // y
     if (st != PT_OK) return st;
-    st = pass_rows(ws, o, nx, ny, nz, s);  // x
+    st = pass_lines(ws, o, nx, ny, nz, 2, s);  // z
     if (st != PT_OK) return st;
   }
   return PT_OK;

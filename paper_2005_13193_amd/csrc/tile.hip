@@ -980,9 +980,30 @@ __global__ __launch_bounds__(256) void layer_table(const K* __restrict__ keys, i
 // half-row 2 cy + h and of the run index; runs of one colour never share a
 // coefficient because every run between two of them is at least lmin >= 5
 // layers long and a run touches planes z0-1 .. z1+3 only.
+// Gather units are (z-block of lmax layers, column), ordered z-block first
+// and, inside a z-block, by groups of 8 x 4 neighbouring columns: the
+// workgroups that run at the same time on one XCD take neighbouring columns
+// over the same layers, so the halo rows and columns they share are read
+// from HBM once and then hit in that XCD's L2.  Ragged groups leave empty
+// units, which emit no item.
+constexpr int kGroupW = 8, kGroupH = 4;
+
 struct ItemCfg {
   int pmax, lmin, lmax, scatter;
+  int ncy, ngx, ngy;  // gather: columns in y, column groups in x and y
 };
+
+__device__ __forceinline__ bool gather_unit(const ItemCfg& cfg, int ncx, int u, int* col,
+                                            int* zb) {
+  const int per_zb = cfg.ngx * cfg.ngy * kGroupW * kGroupH;
+  *zb = u / per_zb;
+  const int r = u - *zb * per_zb;
+  const int grp = r / (kGroupW * kGroupH), l = r % (kGroupW * kGroupH);
+  const int cx = (grp % cfg.ngx) * kGroupW + l % kGroupW;
+  const int cy = (grp / cfg.ngx) * kGroupH + l / kGroupW;
+  *col = cy * ncx + cx;
+  return cx < ncx && cy < cfg.ncy;
+}
 
 __device__ __forceinline__ int unit_layer_count(const int32_t* hs, int nz, int u, int z,
                                                 bool scatter) {
@@ -1002,7 +1023,31 @@ __global__ __launch_bounds__(256) void build_items(const int32_t* __restrict__ h
   const int u = blockIdx.x * 256 + threadIdx.x;
   if (u >= nunits) return;
   const bool sc = cfg.scatter != 0;
-  const int col = sc ? u >> 1 : u, half = sc ? u & 1 : 0;
+  if (!sc) {
+    // gather: the layers of one z-block of one column
+    int col = 0, zb = 0;
+    const bool real = gather_unit(cfg, ncx, u, &col, &zb);
+    const int zs = zb * cfg.lmax, ze = min(nz, zs + cfg.lmax);
+    int n = 0, z0 = zs, acc = 0;
+    const int o = WRITE ? offsets[u] : 0;
+    if (real) {
+      for (int z = zs; z < ze; ++z) {
+        const int c = unit_layer_count(hs, nz, col, z, false);
+        if (z > z0 && z - z0 >= cfg.lmin && acc + c > cfg.pmax) {
+          if (WRITE && o + n < capacity) items[o + n] = make_int4(col, 0, z0, z);
+          ++n;
+          z0 = z;
+          acc = 0;
+        }
+        acc += c;
+      }
+      if (WRITE && o + n < capacity) items[o + n] = make_int4(col, 0, z0, ze);
+      ++n;
+    }
+    if (!WRITE) offsets[u] = n;
+    return;
+  }
+  const int col = u >> 1, half = u & 1;
   const int cx = col % ncx, hy = 2 * (col / ncx) + half;
   const int base = sc ? ((cx & 1) | ((hy & 1) << 1)) : 0;
   int n_even = 0, n_odd = 0, k = 0, z0 = 0, acc = 0;
@@ -1120,11 +1165,27 @@ static int64_t item_bound(int64_t nunits, int nz, int64_t np, int lmax) {
   return nunits * ((nz + lmax - 1) / lmax + 1) + 2 * ((np + kItemPmax - 1) / kItemPmax) + 8;
 }
 
+// Units of the item builder: half-columns (scatter) or (z-block, column)
+// slots of the grouped column order (gather).
+static int64_t item_units(const pt_grid* g, bool scatter, ItemCfg* cfg) {
+  const int ncx = (g->nx + kTileX - 1) / kTileX, ncy = (g->ny + kTileY - 1) / kTileY;
+  if (cfg) {
+    cfg->ncy = ncy;
+    cfg->ngx = (ncx + kGroupW - 1) / kGroupW;
+    cfg->ngy = (ncy + kGroupH - 1) / kGroupH;
+  }
+  if (scatter) return 2 * (int64_t)ncx * ncy;
+  const int64_t nzb = (g->nz + kGatherSeg - 1) / kGatherSeg;
+  return nzb * ((ncx + kGroupW - 1) / kGroupW) * ((ncy + kGroupH - 1) / kGroupH) * kGroupW *
+         kGroupH;
+}
+
 // Workspace of build_tile_items: counts/offsets, colour ranges and items.
 size_t tile_items_bytes(const pt_grid* g, int64_t np, bool scatter) {
-  const int64_t ncol = (int64_t)((g->nx + kTileX - 1) / kTileX) * ((g->ny + kTileY - 1) / kTileY);
-  const int64_t nunits = scatter ? 2 * ncol : ncol;
-  const int64_t bound = item_bound(nunits, g->nz, np, scatter ? kScatterSeg : kGatherSeg);
+  const int64_t nunits = item_units(g, scatter, nullptr);
+  // a gather unit spans one z-block: at most 1 + (splits by particle count)
+  const int64_t bound = scatter ? item_bound(nunits, g->nz, np, kScatterSeg)
+                                : nunits + 2 * ((np + kItemPmax - 1) / kItemPmax) + 8;
   return 256 + 4 * (size_t)(8 * nunits) + 16 * (size_t)bound;
 }
 
@@ -1137,18 +1198,19 @@ struct ItemSet {
 static pt_status build_tile_items(const pt_grid* g, int64_t np, const int32_t* hs, bool scatter,
                                   void* ws, ItemSet* out, hipStream_t s) {
   const int ncx = (g->nx + kTileX - 1) / kTileX;
-  const int64_t ncol = (int64_t)ncx * ((g->ny + kTileY - 1) / kTileY);
-  const int nunits = (int)(scatter ? 2 * ncol : ncol);
-  const int ncolors = scatter ? 8 : 1;
-  if ((int64_t)nunits * ncolors > 1024 * 256) return PT_ERR_UNSUPPORTED;
   const int lmax = scatter ? kScatterSeg : kGatherSeg;
-  ItemCfg cfg{kItemPmax, scatter ? 6 : 2, lmax, scatter ? 1 : 0};
+  ItemCfg cfg{kItemPmax, scatter ? 6 : 2, lmax, scatter ? 1 : 0, 0, 0, 0};
+  const int64_t nunits64 = item_units(g, scatter, &cfg);
+  const int ncolors = scatter ? 8 : 1;
+  if (nunits64 * ncolors > (int64_t)1 << 26) return PT_ERR_UNSUPPORTED;
+  const int nunits = (int)nunits64;
   char* p = (char*)ws;
   int* range = (int*)p;
   int* offsets = (int*)(p + 256);
   int4* items = (int4*)(p + 256 + 4 * (size_t)(8 * nunits));
   const unsigned blocks = (unsigned)((nunits + 255) / 256);
-  const int64_t bound = item_bound(nunits, g->nz, np, lmax);
+  const int64_t bound = scatter ? item_bound(nunits, g->nz, np, lmax)
+                                : nunits + 2 * ((np + kItemPmax - 1) / kItemPmax) + 8;
   hipLaunchKernelGGL(build_items<false>, dim3(blocks), dim3(256), 0, s, hs, nunits, g->nz, ncx,
                      cfg, offsets, items, bound);
   hipLaunchKernelGGL(scan_items, dim3(1), dim3(1024), 0, s, offsets, nunits * ncolors, nunits,

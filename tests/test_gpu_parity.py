@@ -74,9 +74,13 @@ def field_for(nx, ny, nz, seed=0):
 
 
 SHAPES = [(32, 32, 32), (45, 37, 20), (4, 4, 4), (64, 64, 64), (100, 6, 33)]
+# long lines: every chunking of the line solvers (rows of up to 65 points
+# per lane; y/z lines split over lane groups of 32, 16 and 8 x-points)
+LONG_SHAPES = [(7, 1100, 5), (5, 6, 2500), (4100, 4, 5), (2049, 4, 4), (4, 4, 8192),
+               (65, 1025, 4)]
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + LONG_SHAPES)
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_spline_coeffs_parity(pt, shape, dtype):
     import torch
@@ -217,7 +221,8 @@ def test_interp_bwd_parity(pt):
     assert normwise(host(gco).reshape(3, -1), rc.reshape(3, -1)) < F32_TOL
 
 
-@pytest.mark.parametrize("shape", [(32, 32, 32), (45, 37, 20), (4, 5, 6)])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (45, 37, 20), (4, 5, 6), (4, 4, 4),
+                                   (100, 6, 33)] + LONG_SHAPES)
 def test_spline_bwd_parity(pt, shape):
     nx, ny, nz = shape
     rng = np.random.default_rng(11)
