@@ -3,17 +3,25 @@
 // a stable least-significant-digit radix sort of (key, index) with 8-bit
 // digits, and the permutation of the particle arrays.
 //
-// Radix pass structure: the input is cut into wave tiles of kWaveItems
-// consecutive elements.  A histogram kernel counts the digits of every tile,
-// an exclusive scan over the digit-major count table gives every (digit,
-// tile) its output offset, and a scatter kernel re-reads each tile in order
-// and ranks equal digits with wave ballots, which keeps the sort stable.
+// Radix pass structure: the input is cut into block tiles of kSortTile
+// consecutive elements (8 waves x 16 rounds x 64 lanes).  A histogram kernel
+// counts the digits of every tile, an exclusive scan over the digit-major
+// count table gives every (digit, tile) its output offset, and a scatter
+// kernel re-reads each tile, ranks equal digits in input order (wave ballots
+// within a round, running per-wave counts across rounds, wave prefixes
+// across the tile), reorders the tile by digit in LDS, and writes each
+// digit's run contiguously (about 32 elements per digit and tile).
+#include <hip/hip_runtime.h>
+
 #include "pt_common.h"
 
 namespace pt {
 
-constexpr int kRounds = 16;
-constexpr int kWaveItems = 64 * kRounds;  // elements per wave tile
+constexpr int kSortThreads = 512;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortRounds = 16;
+constexpr int kWaveItems = 64 * kSortRounds;            // elements per wave
+constexpr int kSortTile = kSortThreads * kSortRounds;   // elements per tile
 constexpr int kScanItems = 8;             // per thread in the scan kernels
 constexpr int kScanBlock = 256 * kScanItems;
 
@@ -50,64 +58,132 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
   return peers;
 }
 
+// Digit counts of one tile: counts[d * ntiles + tile].
 template <typename K>
-__global__ __launch_bounds__(256) void radix_hist(const K* __restrict__ keys, int64_t n, int shift,
-                                                  uint32_t* __restrict__ counts, int64_t nwt) {
-  __shared__ uint32_t h[4][256];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+__global__ __launch_bounds__(kSortThreads) void radix_hist(const K* __restrict__ keys, int64_t n,
+                                                           int shift,
+                                                           uint32_t* __restrict__ counts,
+                                                           int64_t ntiles) {
+  __shared__ uint32_t h[kSortWaves][256];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int i = lane; i < 256; i += 64) h[wave][i] = 0;
-  __syncthreads();
-  const int64_t wt = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t tile = blockIdx.x;
+  const int64_t base = tile * kSortTile + (int64_t)wave * kWaveItems;
   const uint64_t lt = (1ull << lane) - 1;
-  if (wt < nwt) {
-    const int64_t base = wt * kWaveItems;
-    for (int r = 0; r < kRounds; ++r) {
-      const int64_t idx = base + r * 64 + lane;
-      const bool ok = idx < n;
-      const uint32_t d = ok ? (uint32_t)((keys[idx] >> shift) & 255) : 0u;
-      const uint64_t peers = match_digit(d, __ballot(ok));
-      if (ok && (peers & lt) == 0) h[wave][d] += (uint32_t)__popcll(peers);
+  uint32_t d[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t idx = base + r * 64 + lane;
+    d[r] = idx < n ? (uint32_t)((keys[idx] >> shift) & 255) : 256u;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const bool ok = d[r] < 256u;
+    const uint64_t peers = match_digit(d[r] & 255u, __ballot(ok));
+    if (ok && (peers & lt) == 0) h[wave][d[r]] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  if (tid < 256) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) c += h[w][tid];
+    counts[(int64_t)tid * ntiles + tile] = c;
+  }
+}
+
+// Stable scatter of one tile to the offsets of the scanned count table.
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void radix_scatter(
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
+    uint32_t* __restrict__ vout, int64_t n, int shift, const uint32_t* __restrict__ offsets,
+    int64_t ntiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  K* tk = (K*)smem;                                          // [kSortTile]
+  uint32_t* tv = (uint32_t*)(tk + kSortTile);                // [kSortTile]
+  uint32_t* h = tv + kSortTile;                              // [kSortWaves][256]
+  uint32_t* dstart = h + kSortWaves * 256;                   // [256]
+  uint32_t* goff = dstart + 256;                             // [256]
+  uint32_t* wsum = goff + 256;                               // [4]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t tile = blockIdx.x;
+  const int64_t tbase = tile * kSortTile;
+  const int tile_n = (int)min((int64_t)kSortTile, n - tbase);
+  const int64_t base = tbase + (int64_t)wave * kWaveItems;
+  for (int i = lane; i < 256; i += 64) h[wave * 256 + i] = 0;
+  if (tid < 256) goff[tid] = offsets[(int64_t)tid * ntiles + tile];
+
+  K k[kSortRounds];
+  uint32_t v[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t idx = base + r * 64 + lane;
+    const bool ok = idx < n;
+    k[r] = ok ? kin[idx] : (K)0;
+    v[r] = ok ? vin[idx] : 0u;
+  }
+  // wave-local ranks: rank = earlier rounds' count of the digit + lanes below
+  const uint64_t lt = (1ull << lane) - 1;
+  uint32_t dr[kSortRounds];  // digit << 16 | wave-local rank
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const bool ok = base + r * 64 + lane < n;
+    const uint32_t d = (uint32_t)((k[r] >> shift) & 255);
+    const uint64_t peers = match_digit(d, __ballot(ok));
+    const uint32_t start = ok ? h[wave * 256 + d] : 0u;
+    dr[r] = (d << 16) | (start + (uint32_t)__popcll(peers & lt));
+    // the lowest lane of each digit group advances the running count; its
+    // new value depends on the value it read, so the read completes first
+    if (ok && (peers & lt) == 0) h[wave * 256 + d] = start + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // per digit: exclusive prefixes over the waves, then over the digits
+  if (tid < 256) {
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      const uint32_t c = h[w * 256 + tid];
+      h[w * 256 + tid] = run;
+      run += c;
+    }
+    uint32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    dstart[tid] = incl - run;  // exclusive within the wave for now
+  }
+  __syncthreads();
+  if (tid < 256) {
+    uint32_t woff = 0;
+    for (int w = 0; w < wave; ++w) woff += wsum[w];
+    dstart[tid] += woff;
+  }
+  __syncthreads();
+  // reorder the tile by digit in LDS
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    if (base + r * 64 + lane < n) {
+      const uint32_t d = dr[r] >> 16;
+      const uint32_t lp = dstart[d] + h[wave * 256 + d] + (dr[r] & 0xffffu);
+      tk[lp] = k[r];
+      tv[lp] = v[r];
     }
   }
   __syncthreads();
-  if (wt < nwt)
-    for (int i = lane; i < 256; i += 64) counts[(int64_t)i * nwt + wt] = h[wave][i];
-}
-
-template <typename K>
-__global__ __launch_bounds__(256) void radix_scatter(const K* __restrict__ kin,
-                                                     const uint32_t* __restrict__ vin,
-                                                     K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                     int64_t n, int shift,
-                                                     const uint32_t* __restrict__ offsets,
-                                                     int64_t nwt) {
-  __shared__ uint32_t h[4][256];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t wt = (int64_t)blockIdx.x * 4 + wave;
-  if (wt < nwt)
-    for (int i = lane; i < 256; i += 64) h[wave][i] = offsets[(int64_t)i * nwt + wt];
-  __syncthreads();
-  if (wt >= nwt) return;
-  const uint64_t lt = (1ull << lane) - 1;
-  const int64_t base = wt * kWaveItems;
-  for (int r = 0; r < kRounds; ++r) {
-    const int64_t idx = base + r * 64 + lane;
-    const bool ok = idx < n;
-    K k = 0;
-    uint32_t v = 0;
-    if (ok) { k = kin[idx]; v = vin[idx]; }
-    const uint32_t d = (uint32_t)((k >> shift) & 255);
-    const uint64_t peers = match_digit(d, __ballot(ok));
-    const uint32_t start = ok ? h[wave][d] : 0u;
-    if (ok) {
-      const uint32_t dst = start + (uint32_t)__popcll(peers & lt);
+  // each digit's run goes to consecutive global positions
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int i = r * kSortThreads + tid;
+    if (i < tile_n) {
+      const K key = tk[i];
+      const uint32_t d = (uint32_t)((key >> shift) & 255);
+      const uint32_t dst = goff[d] + ((uint32_t)i - dstart[d]);
       if (dst < (uint64_t)n) {  // always true for consistent counts; guards the store
-        kout[dst] = k;
-        vout[dst] = v;
+        kout[dst] = key;
+        vout[dst] = tv[i];
       }
-      // the lowest lane of each digit group advances the running offset; its
-      // new value depends on the value it read, so the read completes first
-      if ((peers & lt) == 0) h[wave][d] = start + (uint32_t)__popcll(peers);
     }
   }
 }
@@ -228,23 +304,24 @@ struct SortWs {
   uint32_t* scan;
 };
 
+static int64_t sort_tiles(int64_t np) { return (np + kSortTile - 1) / kSortTile; }
+
 size_t sort_ws_bytes(const pt_grid* g, int64_t np) {
   const size_t kb = key_bits(g) > 32 ? 8 : 4;
-  const int64_t nwt = (np + kWaveItems - 1) / kWaveItems;
-  const size_t ncount = (size_t)nwt * 256;
+  const size_t ncount = (size_t)sort_tiles(np) * 256;
   return 2 * align256(kb * (size_t)np) + align256(4 * (size_t)np) + align256(4 * ncount) +
          align256(4 * scan_scratch_words((int64_t)ncount));
 }
 
 static SortWs carve_sort_ws(const pt_grid* g, int64_t np, void* ws) {
   const size_t kb = key_bits(g) > 32 ? 8 : 4;
-  const int64_t nwt = (np + kWaveItems - 1) / kWaveItems;
+  const int64_t nt = sort_tiles(np);
   char* p = (char*)ws;
   SortWs w;
   w.keys[0] = p; p += align256(kb * (size_t)np);
   w.keys[1] = p; p += align256(kb * (size_t)np);
   w.vals0 = (uint32_t*)p; p += align256(4 * (size_t)np);
-  w.counts = (uint32_t*)p; p += align256(4 * (size_t)nwt * 256);
+  w.counts = (uint32_t*)p; p += align256(4 * (size_t)nt * 256);
   w.scan = (uint32_t*)p;
   return w;
 }
@@ -259,8 +336,11 @@ static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int3
   SortWs w = carve_sort_ws(g, np, ws);
   const int bits = key_bits(g);
   const int passes = (bits + 7) / 8;
-  const int64_t nwt = (np + kWaveItems - 1) / kWaveItems;
-  const unsigned tblocks = (unsigned)((nwt + 3) / 4);
+  const int64_t nt = sort_tiles(np);
+  const size_t lds = (size_t)kSortTile * (sizeof(K) + 4) + 4 * (kSortWaves * 256 + 512 + 4);
+  if (hipFuncSetAttribute((const void*)radix_scatter<K>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return PT_ERR_HIP;
   K* kbuf[2] = {(K*)w.keys[0], (K*)w.keys[1]};
   // pass i writes value buffer (passes - 1 - i) & 1: 0 = perm, 1 = scratch,
   // so that the last pass lands in perm.
@@ -277,13 +357,13 @@ static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int3
   for (int p = 0; p < passes; ++p) {
     const int dst = src ^ 1;
     TimedLaunch t("sort_pass", s);
-    hipLaunchKernelGGL(radix_hist<K>, dim3(tblocks), dim3(256), 0, s, kbuf[src], np, 8 * p,
-                       w.counts, nwt);
+    hipLaunchKernelGGL(radix_hist<K>, dim3((unsigned)nt), dim3(kSortThreads), 0, s, kbuf[src],
+                       np, 8 * p, w.counts, nt);
     PT_LAUNCH_CHECK();
-    pt_status st = exclusive_scan(w.counts, nwt * 256, w.scan, s);
+    pt_status st = exclusive_scan(w.counts, nt * 256, w.scan, s);
     if (st != PT_OK) return st;
-    hipLaunchKernelGGL(radix_scatter<K>, dim3(tblocks), dim3(256), 0, s, kbuf[src], vbuf[src],
-                       kbuf[dst], vbuf[dst], np, 8 * p, w.counts, nwt);
+    hipLaunchKernelGGL(radix_scatter<K>, dim3((unsigned)nt), dim3(kSortThreads), lds, s,
+                       kbuf[src], vbuf[src], kbuf[dst], vbuf[dst], np, 8 * p, w.counts, nt);
     PT_LAUNCH_CHECK();
     src = dst;
   }
