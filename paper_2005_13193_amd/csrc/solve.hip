@@ -499,6 +499,10 @@ static pt_status pass_lines(const float* in, float* out, int nx, int ny, int nz,
   return PT_OK;
 }
 
+static float* align256f(float* p) {
+  return (float*)(((uintptr_t)p + 255) & ~(uintptr_t)255);
+}
+
 size_t spline_ws_floats(const pt_grid* g, pt_dtype dtype) {
   const size_t n3 = (size_t)g->nx * g->ny * g->nz;
   return dtype == PT_BF16 ? 2 * n3 : n3;
@@ -513,8 +517,10 @@ pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype
     const float* f = field + c * n3;
     // z pass into a scratch array, y pass, then the x pass writes the padded
     // coefficients.  For FP32 output the component's own output block (read
-    // by the y pass before the x pass overwrites it) is the first scratch.
-    float* t1 = dtype == PT_F32 ? (float*)coeff + c * p3 : ws;
+    // by the y pass before the x pass overwrites it) is the first scratch,
+    // started at a 256-byte boundary inside the block (p3 >= n3 + 279):
+    // misaligned rows cost the z and y passes up to 2x.
+    float* t1 = dtype == PT_F32 ? align256f((float*)coeff + c * p3) : ws;
     float* t2 = dtype == PT_F32 ? ws : ws + n3;
     pt_status st = pass_lines(f, t1, nx, ny, nz, 2, s);
     if (st != PT_OK) return st;

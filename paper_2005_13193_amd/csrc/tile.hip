@@ -58,6 +58,7 @@ struct TileArgs {
   int color;              // scatter: colour of this launch
   const int4* items;      // work items (column, half, z0, z1)
   const int* item_range;  // [begin, end) of this launch's items in `items`
+  int* item_ctr;          // 8 zeroed counters of this launch (one per XCD range)
   int64_t np;
   double dt;
   const double* x;        // [3][np] positions (sorted)
@@ -440,17 +441,41 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
   }
 }
 
-// Work item of a block.  Blocks are dealt to the 8 XCDs round-robin; item
-// numbers are remapped so that each XCD walks a contiguous run of items
-// (neighbouring columns of similar layers: their shared halos stay in its L2).
-__device__ __forceinline__ bool next_item(const TileArgs& a, int* col, int* half, int* z0,
-                                          int* z1) {
-  const int begin = a.item_range[0], n = a.item_range[1] - begin;
-  const int b = blockIdx.x;
-  const int per = (n + 7) / 8;
-  const int item = (b & 7) * per + (b >> 3);
-  if ((b >> 3) >= per || item >= n) return false;
-  const int4 it = a.items[begin + item];
+// Work items of a launch.  The items are cut into 8 contiguous ranges, one
+// per XCD (blocks are dealt to the XCDs round-robin, block b to XCD b % 8):
+// neighbouring columns of similar layers run on one XCD and share its L2.
+// The blocks of an XCD take the items of its range from a counter, then help
+// the other ranges; a block ends when every range is used up (at most 8 more
+// counter draws), so the launch needs only as many blocks as fit on the chip
+// and no block is left idle behind a heavy item.
+// Starts with a barrier: the previous item's LDS contents are no longer read.
+__device__ __forceinline__ bool next_item(const TileArgs& a, int* range_k, int* col, int* half,
+                                          int* z0, int* z1) {
+  __shared__ int s_next[2];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int begin = a.item_range[0], n = a.item_range[1] - begin;
+    const int per = (n + 7) / 8;
+    const int x0 = blockIdx.x & 7;
+    int k = *range_k, item = -1;
+    for (; k < 8; ++k) {
+      const int x = (x0 + k) & 7;
+      const int lo = x * per, hi = min(n, lo + per);
+      if (lo >= hi) continue;
+      const int t = atomicAdd(a.item_ctr + x, 1);
+      if (lo + t < hi) {
+        item = begin + lo + t;
+        break;
+      }
+    }
+    s_next[0] = item;
+    s_next[1] = k;
+  }
+  __syncthreads();
+  const int item = s_next[0];
+  *range_k = s_next[1];
+  if (item < 0) return false;
+  const int4 it = a.items[item];
   *col = it.x;
   *half = it.y;
   *z0 = it.z;
@@ -509,13 +534,14 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
   extern __shared__ uint32_t gsm[];
   uint32_t* ring = gsm;
   int* lst = (int*)(gsm + kGRing * kGSlot);  // layer starts of the segment
-  int col, half_unused, z0, z1;
-  if (!next_item(a, &col, &half_unused, &z0, &z1)) return;
   const GridDev& g = a.g;
-  const int cy = col / a.ncx, cx = col - cy * a.ncx;
-  const int X0 = cx * kTileX, Y0 = cy * kTileY;
   const int wave = threadIdx.x >> 6;
   const bool loader = wave >= kCompute / 64;
+  float umax = 0.0f;  // largest |ub| of this thread's particles (adjoint)
+  int col, half_unused, z0, z1, range_k = 0;
+  while (next_item(a, &range_k, &col, &half_unused, &z0, &z1)) {
+  const int cy = col / a.ncx, cx = col - cy * a.ncx;
+  const int X0 = cx * kTileX, Y0 = cy * kTileY;
   const int nl = z1 - z0;
   const int32_t* ls = a.lstart + 2 * ((int64_t)col * g.nz + z0);
   const CT* coeff = (const CT*)a.coeff;
@@ -541,7 +567,6 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
     }
     load_pdata<MODE>(a, pb + grp, pb + grp < pe, &pd[set]);
   };
-  float umax = 0.0f;  // largest |ub| of this thread's particles (adjoint)
   if (!loader) {
     prefetch(0, 0);
     prefetch(1, 1);
@@ -577,6 +602,7 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
       }
     }
   }
+  }  // items
   if (MODE == TILE_RK2_BWD_GRAD) {
     // block maximum of |ub| for the fixed-point scale of the scatter
     float* smax = (float*)(lst + a.seg_len + 4);
@@ -820,9 +846,10 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   extern __shared__ long long ssm[];
   long long* ring = ssm;
   int* lst = (int*)(ssm + kSRing * kSSlot);  // [2 (nl + 1)] half-layer starts
-  int col, half, z0, z1;
-  if (!next_item(a, &col, &half, &z0, &z1)) return;
   const GridDev& g = a.g;
+  const float scale = scatter_scale(a), inv_scale = 1.0f / scale;
+  int col, half, z0, z1, range_k = 0;
+  while (next_item(a, &range_k, &col, &half, &z0, &z1)) {
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
   const int X0 = cx * kTileX - 1, Y0 = cy * kTileY + half * (kTileY / 2) - 1;
   const int lane = threadIdx.x & (kSLanes - 1), grp = threadIdx.x / kSLanes;
@@ -834,7 +861,6 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
     lst[2 * i + 1] = hs[2 * i + 1];
   }
   for (int e = threadIdx.x; e < kSRing * kSSlot; e += kSTB) ring[e] = 0;
-  const float scale = scatter_scale(a), inv_scale = 1.0f / scale;
   __syncthreads();
 
   // particles of slab s: layer zs (half) then layer zs+1 (half); quad group
@@ -908,6 +934,7 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
     flush_splane(a, ring, X0, Y0, P, v, inv_scale);
     __syncthreads();
   }
+  }  // items
 }
 
 // Stencils that did not fit their column's tile, added with atomics once all
@@ -1159,6 +1186,10 @@ static TileArgs tile_args(const pt_grid* g, const void* coeff, const int32_t* ls
   return a;
 }
 
+// Items workspace: colour ranges (bytes 0..63), item counters (64..319),
+// per-unit counts / offsets, items.
+constexpr size_t kItemsHeader = 512;
+
 constexpr int kItemPmax = 8192;
 
 static int64_t item_bound(int64_t nunits, int nz, int64_t np, int lmax) {
@@ -1186,14 +1217,19 @@ size_t tile_items_bytes(const pt_grid* g, int64_t np, bool scatter) {
   // a gather unit spans one z-block: at most 1 + (splits by particle count)
   const int64_t bound = scatter ? item_bound(nunits, g->nz, np, kScatterSeg)
                                 : nunits + 2 * ((np + kItemPmax - 1) / kItemPmax) + 8;
-  return 256 + 4 * (size_t)(8 * nunits) + 16 * (size_t)bound;
+  return kItemsHeader + 4 * (size_t)(8 * nunits) + 16 * (size_t)bound;
 }
 
 struct ItemSet {
   const int4* items;
   const int* range;  // [ncolors + 1]
+  int* ctr;          // [ncolors][8] zeroed item counters
   int64_t bound;
 };
+
+__global__ void zero_ctr(int* p) {
+  if (threadIdx.x < 64) p[threadIdx.x] = 0;
+}
 
 static pt_status build_tile_items(const pt_grid* g, int64_t np, const int32_t* hs, bool scatter,
                                   void* ws, ItemSet* out, hipStream_t s) {
@@ -1206,8 +1242,9 @@ static pt_status build_tile_items(const pt_grid* g, int64_t np, const int32_t* h
   const int nunits = (int)nunits64;
   char* p = (char*)ws;
   int* range = (int*)p;
-  int* offsets = (int*)(p + 256);
-  int4* items = (int4*)(p + 256 + 4 * (size_t)(8 * nunits));
+  int* ctr = (int*)(p + 64);  // [8 colours][8 XCD ranges]
+  int* offsets = (int*)(p + kItemsHeader);
+  int4* items = (int4*)(p + kItemsHeader + 4 * (size_t)(8 * nunits));
   const unsigned blocks = (unsigned)((nunits + 255) / 256);
   const int64_t bound = scatter ? item_bound(nunits, g->nz, np, lmax)
                                 : nunits + 2 * ((np + kItemPmax - 1) / kItemPmax) + 8;
@@ -1218,10 +1255,26 @@ static pt_status build_tile_items(const pt_grid* g, int64_t np, const int32_t* h
   hipLaunchKernelGGL(build_items<true>, dim3(blocks), dim3(256), 0, s, hs, nunits, g->nz, ncx,
                      cfg, offsets, items, bound);
   PT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(zero_ctr, dim3(1), dim3(64), 0, s, ctr);
+  PT_LAUNCH_CHECK();
   out->items = items;
   out->range = range;
+  out->ctr = ctr;
   out->bound = bound;
   return PT_OK;
+}
+
+// Blocks of a tiled launch: one per compute unit (the tiled kernels hold one
+// workgroup per CU), a multiple of 8 (the XCD ranges), at most one per item.
+static unsigned item_blocks(int64_t bound) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  const int64_t want = ((int64_t)cus + 7) / 8 * 8;
+  const int64_t cap = (bound + 7) / 8 * 8;
+  return (unsigned)(want < cap ? want : cap);
 }
 
 template <typename F>
@@ -1237,7 +1290,8 @@ static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int
   if (st != PT_OK) return st;
   a.items = it.items;
   a.item_range = it.range;
-  const unsigned blocks = (unsigned)(((it.bound + 7) / 8) * 8);
+  a.item_ctr = it.ctr;
+  const unsigned blocks = item_blocks(it.bound);
   const size_t lds = sizeof(uint32_t) * ((size_t)kGRing * kGSlot + a.seg_len + 4 + kGTB / 64);
   a.defer_count = (int*)defer;
   a.defer = (uint32_t*)((char*)defer + kDeferHeader);
@@ -1305,10 +1359,11 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   const size_t lds =
       sizeof(long long) * (size_t)kSRing * kSSlot + sizeof(int) * 2 * (b.seg_len + 2);
   if (!allow_lds(tile_scatter, lds)) return PT_ERR_HIP;
-  const unsigned blocks = (unsigned)(((it.bound + 7) / 8) * 8);
+  const unsigned blocks = item_blocks(it.bound);
   for (int color = 0; color < 8; ++color) {
     b.color = color;
     b.item_range = it.range + color;
+    b.item_ctr = it.ctr + 8 * color;
     TimedLaunch t("tile_scatter", s);
     hipLaunchKernelGGL(tile_scatter, dim3(blocks), dim3(kSTB), lds, s, b);
     PT_LAUNCH_CHECK();
