@@ -267,10 +267,11 @@ __device__ __forceinline__ void eval_point(const float* lds, const CT* coeff, co
 // load queue of a wave retires in order, so keeping the plane loads in waves
 // of their own means the compute waves never wait on them, and the loaders
 // wait for exactly their own loads before the barrier that publishes them.
-constexpr int kGRing = 10;                     // planes z-1 .. z+7 in use + spare
+constexpr int kGRing = 11;  // planes zs-1 .. zs+5 in use, zs+6 .. zs+9 in flight
 constexpr int kGTW = kTileX + 3, kGTH = kTileY + 3;
 constexpr int kGComp = kGTW * kGTH;            // 1225 words per component
-constexpr int kGSlot = 3 * kGComp + 5;         // slot pitch (words)
+constexpr int kGSlot = 3 * kGComp + 13;        // slot pitch (words), 40 mod 64
+static_assert(kGSlot % 64 == 40, "planes of one stencil in distinct LDS banks");
 constexpr int kCompute = 512;                  // compute threads (8 waves)
 constexpr int kLoaders = 2;                    // loader waves
 constexpr int kGTB = kCompute + 64 * kLoaders;
@@ -292,7 +293,11 @@ __device__ __forceinline__ float ring_val<uint16_t>(const uint32_t* w) {
 }
 
 // Value (GRAD: and gradient) at a resident point; every lane of the quad
-// returns the full result.
+// returns the full result.  Lane k of the quad takes plane k of the 4x4x4
+// stencil and reads its 12 x-runs of 4 words (3 components x 4 rows) as word
+// pairs; with the slot pitch of 40 banks mod 64, the 16 words of the 4 planes
+// of one point fall into distinct banks, and each LDS instruction moves twice
+// the data of a single-word read.
 template <typename CT, bool GRAD>
 __device__ __forceinline__ void eval_ring(const uint32_t* ring, const GridDev& g, const Pt& q,
                                           int X0, int Y0, int lane, float out[12]) {
@@ -305,36 +310,30 @@ __device__ __forceinline__ void eval_ring(const uint32_t* ring, const GridDev& g
     bspline_dw(q.t[1], dwy);
     bspline_dw(q.t[2], dwz);
   }
-  const float wxi = pick4(wx, lane);
-  const float dwxi = GRAD ? pick4(dwx, lane) : 0.0f;
-  const int off = (q.b - Y0) * kGTW + (q.a - X0) + lane;
-  int sl[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) sl[k] = gslot(q.c + k) * kGSlot + off;
+  const float wzk = pick4(wz, lane);
+  const float dwzk = GRAD ? pick4(dwz, lane) : 0.0f;
+  const uint32_t* base = ring + gslot(q.c + lane) * kGSlot + (q.b - Y0) * kGTW + (q.a - X0);
 #pragma unroll
   for (int comp = 0; comp < 3; ++comp) {
-    float A = 0.f, B = 0.f, C = 0.f;
+    float A = 0.f, Bx = 0.f, By = 0.f;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t* pl = ring + sl[k] + comp * kGComp;
-      float sy = 0.f, sdy = 0.f;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float v = ring_val<CT>(pl + j * kGTW);
-        sy += wy[j] * v;
-        if (GRAD) sdy += dwy[j] * v;
-      }
-      A += wz[k] * sy;
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t* r = base + comp * kGComp + j * kGTW;
+      const float v0 = ring_val<CT>(r), v1 = ring_val<CT>(r + 1);
+      const float v2 = ring_val<CT>(r + 2), v3 = ring_val<CT>(r + 3);
+      const float sx = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
+      A += wy[j] * sx;
       if (GRAD) {
-        B += wz[k] * sdy;
-        C += dwz[k] * sy;
+        const float sdx = dwx[0] * v0 + dwx[1] * v1 + dwx[2] * v2 + dwx[3] * v3;
+        Bx += wy[j] * sdx;
+        By += dwy[j] * sx;
       }
     }
-    out[comp] = quad_sum(wxi * A);
+    out[comp] = quad_sum(wzk * A);
     if (GRAD) {
-      out[3 + 3 * comp + 0] = quad_sum(dwxi * A) * g.inv_h[0];
-      out[3 + 3 * comp + 1] = quad_sum(wxi * B) * g.inv_h[1];
-      out[3 + 3 * comp + 2] = quad_sum(wxi * C) * g.inv_h[2];
+      out[3 + 3 * comp + 0] = quad_sum(wzk * Bx) * g.inv_h[0];
+      out[3 + 3 * comp + 1] = quad_sum(wzk * By) * g.inv_h[1];
+      out[3 + 3 * comp + 2] = quad_sum(dwzk * A) * g.inv_h[2];
     }
   }
 }
@@ -487,6 +486,7 @@ __device__ __forceinline__ bool next_item(const TileArgs& a, int* range_k, int* 
 // plane and component), then one direct-to-LDS load per chunk.
 template <typename CT>
 struct RingLoader {
+  static constexpr int kCopies = 3 * kGChunksPerLoader;  // direct-to-LDS copies per plane
   int rel[kGChunksPerLoader];
   bool act[kGChunksPerLoader];
   int chunk0;
@@ -528,6 +528,19 @@ struct RingLoader {
 
 // s_waitcnt vmcnt(0) with the other counters left alone
 #define PT_WAIT_VMCNT0() __builtin_amdgcn_s_waitcnt(0x0F70)
+// s_waitcnt vmcnt(N) with the other counters left alone (N < 64).
+#define PT_WAIT_VMCNT(N) \
+  __builtin_amdgcn_s_waitcnt(((N) & 0xF) | (((N) >> 4) << 14) | 0x0F70)
+
+// Workgroup barrier that waits only for this wave's LDS operations.  A
+// __syncthreads() would also wait for every global access of the wave (its
+// fence covers the direct-to-LDS copies, tracked by the vector memory
+// counter), which would drain the loaders' prefetches at every step; here the
+// loaders wait for exactly the copies the next step reads.  The memory
+// clobber keeps the compiler from moving accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 template <typename CT, int MODE>
 __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
@@ -549,12 +562,12 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
   RingLoader<CT> rl;
   if (loader) {
     rl.init(g, X0, Y0, wave - kCompute / 64, threadIdx.x & 63);
-    for (int P = z0 - 1; P <= z0 + 5; ++P) rl.load(coeff, g, ring, P);
-    PT_WAIT_VMCNT0();
+    for (int P = z0 - 1; P <= z0 + 7; ++P) rl.load(coeff, g, ring, P);
+    PT_WAIT_VMCNT(2 * RingLoader<CT>::kCopies);  // planes z0-1 .. z0+5 are in
   } else {
     for (int i = threadIdx.x; i <= nl; i += kCompute) lst[i] = ls[2 * i];
   }
-  __syncthreads();
+  lds_barrier();
 
   const int lane = threadIdx.x & 3, grp = threadIdx.x >> 2;
   PData pd[2];
@@ -578,10 +591,12 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
       const int zs = z0 + s * kSlab;
       if (zs < z1) {
         if (loader) {
-          // planes for the next slab go into the slots of zs-4, zs-3
-          rl.load(coeff, g, ring, zs + 6);
-          rl.load(coeff, g, ring, zs + 7);
-          PT_WAIT_VMCNT0();
+          // planes of the slab after next go into the slots of zs-3, zs-2
+          // (free since the previous step); wait for the ones of the next
+          // slab, issued one step ago
+          rl.load(coeff, g, ring, zs + 8);
+          rl.load(coeff, g, ring, zs + 9);
+          PT_WAIT_VMCNT(2 * RingLoader<CT>::kCopies);
         } else {
           const int64_t pb = lst[zs - z0];
           const int64_t pe = lst[min(zs + kSlab, z1) - z0];
@@ -591,17 +606,21 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
           PData cur = pd[half];
           for (int k = 0; k < npass; ++k) {
             PData nxt;
-            const int64_t pn = pb + (int64_t)(k + 1) * kGGroups + grp;
-            load_pdata<MODE>(a, pn, pn < pe, &nxt);
+            const bool more = k + 1 < npass;  // uniform
+            if (more) {
+              const int64_t pn = pb + (int64_t)(k + 1) * kGGroups + grp;
+              load_pdata<MODE>(a, pn, pn < pe, &nxt);
+            }
             if (cur.ok) ring_particle<CT, MODE>(a, ring, cur, X0, Y0, zs, lane, &umax);
-            cur = nxt;
+            if (more) cur = nxt;
           }
           prefetch(half, s + 2);
         }
-        __syncthreads();
+        lds_barrier();
       }
     }
   }
+  if (loader) PT_WAIT_VMCNT0();  // no copy into the ring outlives the item
   }  // items
   if (MODE == TILE_RK2_BWD_GRAD) {
     // block maximum of |ub| for the fixed-point scale of the scatter
