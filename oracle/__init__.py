@@ -46,9 +46,15 @@ def _load():
         lib.oracle_spline_coeffs_bwd.argtypes = [i32, i32, i32, vp, vp]
         lib.oracle_rk2_step_bwd.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, dbl,
                                             vp, vp, vp]
+        lib.oracle_coeffs_at.argtypes = [i32, i32, i32, vp, i32, i32, i64, vp, vp]
+        lib.oracle_interp_window.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i32, i32,
+                                             i64, vp, i32, vp]
+        lib.oracle_rk2_window.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i32, i32, i64,
+                                          dbl, i32, vp]
         for name in ("oracle_solve_line", "oracle_spline_coeffs", "oracle_cell_keys",
                      "oracle_interp", "oracle_rk2_step", "oracle_interp_bwd",
-                     "oracle_spline_coeffs_bwd", "oracle_rk2_step_bwd"):
+                     "oracle_spline_coeffs_bwd", "oracle_rk2_step_bwd", "oracle_coeffs_at",
+                     "oracle_interp_window", "oracle_rk2_window"):
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -208,3 +214,45 @@ def loss_and_grads(grid, field, pos0, dt, steps):
         lam, gcoeff = rk2_step_bwd(grid, coeff, traj[k], dt, lam, gcoeff)
     gfield = spline_coeffs_bwd(gcoeff)
     return loss, lam, gfield
+
+
+# --------------------------------------------------- windowed closed form ---
+# Coefficients through the closed-form periodic inverse summed over a window
+# of +-W points per axis (lines of at most 2W+1 points in full), evaluated
+# only where needed: for grids too large for a full FP64 solve on the host.
+# The field may be float32 (kept as is, read in FP64) or float64.
+
+def _field_arg(field):
+    if field.dtype == np.float32:
+        return np.ascontiguousarray(field), 1
+    return _f64(field), 0
+
+
+def coeffs_at(field, pts, W=28):
+    """S[c] at integer grid points pts [3][n] (x, y, z); returns [3][n]."""
+    f, is32 = _field_arg(field)
+    nz, ny, nx = f.shape[1:]
+    pts = np.ascontiguousarray(pts, dtype=np.int32)
+    out = np.empty((3, pts.shape[1]), dtype=np.float64)
+    _chk(_load().oracle_coeffs_at(nx, ny, nz, _ptr(f), is32, W, pts.shape[1], _ptr(pts),
+                                  _ptr(out)))
+    return out
+
+
+def interp_window(grid, field, pos, n_out=3, W=28):
+    """As interp(), with the coefficients formed from the field itself."""
+    f, is32 = _field_arg(field)
+    pos = _f64(pos)
+    out = np.empty((n_out, pos.shape[1]), dtype=np.float64)
+    _chk(_load().oracle_interp_window(*grid.args, _ptr(f), is32, W, pos.shape[1], _ptr(pos),
+                                      n_out, _ptr(out)))
+    return out
+
+
+def rk2_window(grid, field, pos, dt, steps, W=28):
+    """`steps` Heun steps (as rk2_step), coefficients formed from the field."""
+    f, is32 = _field_arg(field)
+    p = _f64(pos).copy()
+    _chk(_load().oracle_rk2_window(*grid.args, _ptr(f), is32, W, p.shape[1], dt, steps,
+                                   _ptr(p)))
+    return p

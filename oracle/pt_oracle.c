@@ -480,3 +480,223 @@ int oracle_rk2_step_bwd(int nx, int ny, int nz, double lx, double ly, double lz,
   }
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Coefficients from the closed-form periodic inverse, at chosen points.     */
+/* ------------------------------------------------------------------------ */
+/* The inverse of the periodic system (S[m-1] + 4 S[m] + S[m+1]) / 6 = g[m]  */
+/* of Operation 1 has the closed form                                        */
+/*   (A^-1)[m][m'] = sqrt(3) (z^d + z^(n-d)) / (1 - z^n),                     */
+/*   d = (m - m') mod n,  z = sqrt(3) - 2,                                    */
+/* so S at one grid point is a weighted sum of the line's g values whose      */
+/* weights decay like |z|^d (|z| = 0.268).  Summing d over [-W, W] instead   */
+/* of the whole line leaves out at most 2 sqrt(3) |z|^(W+1) / (1 - |z|)      */
+/* times max |g| (4.6e-16 max |g| for W = 28); lines with n <= 2 W + 1 are   */
+/* summed in full.  The 3-D coefficients are the product of the three line   */
+/* inverses (tensor-product interpolant), applied axis by axis over the      */
+/* window around the 4 x 4 x 4 stencil of each particle.  This restates      */
+/* Operation 1 through a different exact method than the Thomas solve above, */
+/* for grids too large for a full FP64 solve on the host.                    */
+
+static double inv_entry(int n, int d) {
+  const double z = sqrt(3.0) - 2.0;
+  d = wrapi(d, n);
+  return sqrt(3.0) * (pow(z, d) + pow(z, n - d)) / (1.0 - pow(z, n));
+}
+
+/* Offsets d and weights K(d) of one axis: the whole line when it is short. */
+static int line_kernel(int n, int W, int *off, double *kw) {
+  int cnt = 0;
+  if (n <= 2 * W + 1) {
+    for (int d = 0; d < n; ++d) { off[cnt] = d; kw[cnt] = inv_entry(n, d); ++cnt; }
+  } else {
+    for (int d = -W; d <= W; ++d) { off[cnt] = d; kw[cnt] = inv_entry(n, d); ++cnt; }
+  }
+  return cnt;
+}
+
+#define OR_WMAX 64
+
+/* g value of component c at grid point (x, y, z) (periodic), from an FP32 or
+ * FP64 field. */
+static inline double field_at(const void *field, int is_f32, int64_t npts, int c, int nx,
+                              int ny, int x, int y, int z) {
+  const int64_t i = (int64_t)c * npts + ((int64_t)z * ny + y) * nx + x;
+  return is_f32 ? (double)((const float *)field)[i] : ((const double *)field)[i];
+}
+
+/* Axis positions reached by the sums of one block: u = 0 .. U-1 stands for
+ * grid index pos(u); output index k with kernel entry d reads u = uidx(k, d). */
+typedef struct {
+  int U, full, n, start, cnt;
+} axis_win;
+
+static axis_win make_axis(int n, int W, int a) {
+  axis_win w;
+  w.n = n;
+  w.full = n <= 2 * W + 1;
+  w.U = w.full ? n : 4 + 2 * W;
+  w.start = w.full ? a - 1 : a - 1 - W;
+  w.cnt = w.full ? n : 2 * W + 1;
+  return w;
+}
+
+static inline int axis_pos(const axis_win *w, int u) { return wrapi(w->start + u, w->n); }
+static inline int axis_u(const axis_win *w, int k, int d) {
+  return w->full ? (k + d) % w->n : k + d;
+}
+
+/* The 3 x 4 x 4 x 4 coefficient block S[c][k][j][i] at grid points
+ * (a0 - 1 + i, a1 - 1 + j, a2 - 1 + k) (mod n): sums along x, then y, then z,
+ * each over the window of every point the next sum needs. */
+static void coeff_block(const void *field, int is_f32, int nx, int ny, int nz, int W,
+                        const int a[3], double blk[3][4][4][4]) {
+  int off[3][2 * OR_WMAX + 1];
+  double kw[3][2 * OR_WMAX + 1];
+  const int n3[3] = {nx, ny, nz};
+  axis_win ax[3];
+  for (int d = 0; d < 3; ++d) {
+    line_kernel(n3[d], W, off[d], kw[d]);
+    ax[d] = make_axis(n3[d], W, a[d]);
+  }
+  const int64_t npts = (int64_t)nx * ny * nz;
+  const int Uz = ax[2].U, Uy = ax[1].U;
+  double *t1 = (double *)malloc(sizeof(double) * (size_t)Uz * Uy * 4);
+  double *t2 = (double *)malloc(sizeof(double) * (size_t)Uz * 16);
+  for (int c = 0; c < 3; ++c) {
+    for (int uz = 0; uz < Uz; ++uz) {
+      const int z = axis_pos(&ax[2], uz);
+      for (int uy = 0; uy < Uy; ++uy) {
+        const int y = axis_pos(&ax[1], uy);
+        for (int i = 0; i < 4; ++i) {
+          double sum = 0.0;
+          for (int d = 0; d < ax[0].cnt; ++d) {
+            const int x = axis_pos(&ax[0], axis_u(&ax[0], i, d));
+            sum += kw[0][d] * field_at(field, is_f32, npts, c, nx, ny, x, y, z);
+          }
+          t1[((size_t)uz * Uy + uy) * 4 + i] = sum;
+        }
+      }
+    }
+    for (int uz = 0; uz < Uz; ++uz)
+      for (int j = 0; j < 4; ++j)
+        for (int i = 0; i < 4; ++i) {
+          double sum = 0.0;
+          for (int d = 0; d < ax[1].cnt; ++d)
+            sum += kw[1][d] * t1[((size_t)uz * Uy + axis_u(&ax[1], j, d)) * 4 + i];
+          t2[((size_t)uz * 4 + j) * 4 + i] = sum;
+        }
+    for (int k = 0; k < 4; ++k)
+      for (int j = 0; j < 4; ++j)
+        for (int i = 0; i < 4; ++i) {
+          double sum = 0.0;
+          for (int d = 0; d < ax[2].cnt; ++d)
+            sum += kw[2][d] * t2[((size_t)axis_u(&ax[2], k, d) * 4 + j) * 4 + i];
+          blk[c][k][j][i] = sum;
+        }
+  }
+  free(t1);
+  free(t2);
+}
+
+/* eq. (spline) on a coefficient block: out12 as in eval_particle. */
+static void eval_block(const double blk[3][4][4][4], const double t[3], const double inv_h[3],
+                       int want_grad, double *out12) {
+  double w[3][4], dw[3][4];
+  for (int d = 0; d < 3; ++d) {
+    basis(t[d], w[d]);
+    basis_dt(t[d], dw[d]);
+    for (int i = 0; i < 4; ++i) dw[d][i] *= inv_h[d];
+  }
+  for (int q = 0; q < 12; ++q) out12[q] = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    double v = 0, gx = 0, gy = 0, gz = 0;
+    for (int k = 0; k < 4; ++k)
+      for (int j = 0; j < 4; ++j)
+        for (int i = 0; i < 4; ++i) {
+          const double s = blk[c][k][j][i];
+          v += w[0][i] * w[1][j] * w[2][k] * s;
+          gx += dw[0][i] * w[1][j] * w[2][k] * s;
+          gy += w[0][i] * dw[1][j] * w[2][k] * s;
+          gz += w[0][i] * w[1][j] * dw[2][k] * s;
+        }
+    out12[c] = v;
+    if (want_grad) {
+      out12[3 + 3 * c + 0] = gx;
+      out12[3 + 3 * c + 1] = gy;
+      out12[3 + 3 * c + 2] = gz;
+    }
+  }
+}
+
+static void eval_window(const or_grid *gr, const void *field, int is_f32, int W,
+                        const double xyz[3], int want_grad, double *out12) {
+  int n[3] = {gr->nx, gr->ny, gr->nz};
+  double L[3] = {gr->lx, gr->ly, gr->lz};
+  int a[3];
+  double t[3], inv_h[3];
+  for (int d = 0; d < 3; ++d) {
+    cell_1d(xyz[d], (double)n[d] / L[d], n[d], &a[d], &t[d]);
+    inv_h[d] = (double)n[d] / L[d];
+  }
+  double blk[3][4][4][4];
+  coeff_block(field, is_f32, gr->nx, gr->ny, gr->nz, W, a, blk);
+  eval_block(blk, t, inv_h, want_grad, out12);
+}
+
+/* Coefficients S[c] at npt grid points pts[3][npt] (grid indices x, y, z),
+ * out[3][npt]. */
+int oracle_coeffs_at(int nx, int ny, int nz, const void *field, int is_f32, int W,
+                     int64_t npt, const int32_t *pts, double *out) {
+  if (nx < 4 || ny < 4 || nz < 4 || W < 1 || W > OR_WMAX) return OR_ERR_SIZE;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t p = 0; p < npt; ++p) {
+    /* the block at a = point + 1 starts at the point itself */
+    const int a[3] = {pts[p] + 1, pts[npt + p] + 1, pts[2 * npt + p] + 1};
+    double blk[3][4][4][4];
+    coeff_block(field, is_f32, nx, ny, nz, W, a, blk);
+    for (int c = 0; c < 3; ++c) out[c * npt + p] = blk[c][0][0][0];
+  }
+  return OR_OK;
+}
+
+/* oracle_interp from the field itself (windowed closed-form coefficients). */
+int oracle_interp_window(int nx, int ny, int nz, double lx, double ly, double lz,
+                         const void *field, int is_f32, int W, int64_t np, const double *pos,
+                         int n_out, double *out) {
+  if (n_out != 3 && n_out != 12) return OR_ERR_SIZE;
+  if (nx < 4 || ny < 4 || nz < 4 || W < 1 || W > OR_WMAX) return OR_ERR_SIZE;
+  if (!check_finite(np, pos)) return OR_ERR_NONFINITE;
+  or_grid gr = {nx, ny, nz, lx, ly, lz};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t p = 0; p < np; ++p) {
+    const double xyz[3] = {pos[p], pos[np + p], pos[2 * np + p]};
+    double o[12];
+    eval_window(&gr, field, is_f32, W, xyz, n_out == 12, o);
+    for (int q = 0; q < n_out; ++q) out[q * np + p] = o[q];
+  }
+  return OR_OK;
+}
+
+/* nsteps Heun steps (as oracle_rk2_step) from the field itself; pos is
+ * advanced in place. */
+int oracle_rk2_window(int nx, int ny, int nz, double lx, double ly, double lz,
+                      const void *field, int is_f32, int W, int64_t np, double dt,
+                      int nsteps, double *pos) {
+  if (nx < 4 || ny < 4 || nz < 4 || W < 1 || W > OR_WMAX) return OR_ERR_SIZE;
+  if (!check_finite(np, pos)) return OR_ERR_NONFINITE;
+  or_grid gr = {nx, ny, nz, lx, ly, lz};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t p = 0; p < np; ++p) {
+    double x0[3] = {pos[p], pos[np + p], pos[2 * np + p]};
+    for (int s = 0; s < nsteps; ++s) {
+      double u0[12], u1[12], xs[3];
+      eval_window(&gr, field, is_f32, W, x0, 0, u0);
+      for (int d = 0; d < 3; ++d) xs[d] = x0[d] + dt * u0[d];
+      eval_window(&gr, field, is_f32, W, xs, 0, u1);
+      for (int d = 0; d < 3; ++d) x0[d] = x0[d] + 0.5 * dt * (u0[d] + u1[d]);
+    }
+    for (int d = 0; d < 3; ++d) pos[d * np + p] = x0[d];
+  }
+  return OR_OK;
+}
