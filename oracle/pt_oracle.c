@@ -460,23 +460,49 @@ int oracle_spline_coeffs_bwd(int nx, int ny, int nz, const double *gcoeff,
  *   ub1 = ub0 = dt/2 lambda;  xbs = J(x*)^T ub1;  ub0 += dt xbs;
  *   xbn = lambda + xbs + J(x^n)^T ub0;
  *   gcoeff += W(x*)^T ub1 + W(x^n)^T ub0  (gcoeff may be NULL). */
+/* Particles are independent: large particle sets are split into contiguous
+ * blocks, one per thread, each summing its W^T terms into a private copy of
+ * gcoeff; the copies are then added in block order (only the rounding of
+ * the FP64 sums depends on the thread count). */
 int oracle_rk2_step_bwd(int nx, int ny, int nz, double lx, double ly, double lz,
                         const double *coeff, int64_t np, double dt,
                         const double *pos_n, double *gpos, double *gcoeff) {
   if (!check_finite(np, pos_n)) return OR_ERR_NONFINITE;
   or_grid gr = {nx, ny, nz, lx, ly, lz};
-  for (int64_t p = 0; p < np; ++p) {
-    double x0[3] = {pos_n[p], pos_n[np + p], pos_n[2 * np + p]};
-    double u0[12], xs[3];
-    eval_particle(&gr, coeff, x0[0], x0[1], x0[2], 0, u0);
-    for (int d = 0; d < 3; ++d) xs[d] = x0[d] + dt * u0[d];
-    double lam[3] = {gpos[p], gpos[np + p], gpos[2 * np + p]};
-    double ub1[3], ub0[3], xbs[3] = {0, 0, 0}, xbn[3] = {0, 0, 0};
-    for (int d = 0; d < 3; ++d) ub1[d] = ub0[d] = 0.5 * dt * lam[d];
-    particle_bwd(&gr, coeff, xs, ub1, xbs, gcoeff);
-    for (int d = 0; d < 3; ++d) ub0[d] += dt * xbs[d];
-    particle_bwd(&gr, coeff, x0, ub0, xbn, gcoeff);
-    for (int d = 0; d < 3; ++d) gpos[d * np + p] = lam[d] + xbs[d] + xbn[d];
+  const int64_t ppts = 3 * (int64_t)(nx + 3) * (ny + 3) * (nz + 3);
+  int nt = oracle_num_threads();
+  if (np < 4096 || nt < 2) nt = 1;
+  double *priv = NULL;
+  if (nt > 1 && gcoeff) {
+    priv = (double *)calloc((size_t)nt * ppts, sizeof(double));
+    if (!priv) nt = 1;
+  }
+#pragma omp parallel for schedule(static, 1) num_threads(nt) if (nt > 1)
+  for (int b = 0; b < nt; ++b) {
+    const int64_t p0 = np * b / nt, p1 = np * (b + 1) / nt;
+    double *gc = gcoeff ? (priv ? priv + (int64_t)b * ppts : gcoeff) : NULL;
+    for (int64_t p = p0; p < p1; ++p) {
+      double x0[3] = {pos_n[p], pos_n[np + p], pos_n[2 * np + p]};
+      double u0[12], xs[3];
+      eval_particle(&gr, coeff, x0[0], x0[1], x0[2], 0, u0);
+      for (int d = 0; d < 3; ++d) xs[d] = x0[d] + dt * u0[d];
+      double lam[3] = {gpos[p], gpos[np + p], gpos[2 * np + p]};
+      double ub1[3], ub0[3], xbs[3] = {0, 0, 0}, xbn[3] = {0, 0, 0};
+      for (int d = 0; d < 3; ++d) ub1[d] = ub0[d] = 0.5 * dt * lam[d];
+      particle_bwd(&gr, coeff, xs, ub1, xbs, gc);
+      for (int d = 0; d < 3; ++d) ub0[d] += dt * xbs[d];
+      particle_bwd(&gr, coeff, x0, ub0, xbn, gc);
+      for (int d = 0; d < 3; ++d) gpos[d * np + p] = lam[d] + xbs[d] + xbn[d];
+    }
+  }
+  if (priv) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < ppts; ++i) {
+      double s = gcoeff[i];
+      for (int b = 0; b < nt; ++b) s += priv[(int64_t)b * ppts + i];
+      gcoeff[i] = s;
+    }
+    free(priv);
   }
   return OR_OK;
 }
