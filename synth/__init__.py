@@ -93,6 +93,55 @@ def spectral_field_torch(n, kmax, seed=0, device="cuda"):
     return out
 
 
+def spectral_field_torch_chunked(n, kmax, seed=0, device="cuda", chunk=128):
+    """As spectral_field_torch for grids too large to hold three complex
+    spectra at once (2048^3 needs 0.1 TB of device memory for the field alone):
+    the random vectors of each slab of chunk kz-planes come from a generator
+    seeded with (seed, slab), so every component can redraw them; the inverse
+    transform runs one axis at a time over slabs.  Same spectrum and
+    projection, a different random stream."""
+    import torch
+
+    kf = torch.fft.fftfreq(n, d=1.0 / n, device=device, dtype=torch.float32)
+    kh = torch.fft.rfftfreq(n, d=1.0 / n, device=device, dtype=torch.float32)
+    nh = n // 2 + 1
+    out = torch.empty((3, n, n, n), dtype=torch.float32, device=device)
+    for c in range(3):
+        spec = torch.empty((n, n, nh), dtype=torch.complex64, device=device)
+        for z0 in range(0, n, chunk):
+            z1 = min(n, z0 + chunk)
+            gen = torch.Generator(device=device)
+            gen.manual_seed(seed * 1000003 + z0)
+            shape = (z1 - z0, n, nh)
+            a = [torch.complex(torch.randn(shape, generator=gen, device=device),
+                               torch.randn(shape, generator=gen, device=device))
+                 for _ in range(3)]
+            kz = kf[z0:z1].view(-1, 1, 1)
+            ky = kf.view(1, n, 1)
+            kx = kh.view(1, 1, nh)
+            kk2 = kz * kz + ky * ky + kx * kx
+            kk = kk2.sqrt()
+            inv = torch.where(kk2 > 0, 1.0 / kk2, torch.zeros_like(kk2))
+            kdot = (kx * a[0] + ky * a[1] + kz * a[2]) * inv
+            amp = torch.where((kk >= 1.0) & (kk <= kmax), kk.clamp_min(1.0).pow(-11.0 / 6.0),
+                              torch.zeros_like(kk))
+            kc = (kx, ky, kz)[c]
+            spec[z0:z1] = (a[c] - kc * kdot) * amp
+            del a, kdot, kk2, kk, inv, amp
+        for y0 in range(0, n, chunk):  # along z
+            spec[:, y0:y0 + chunk] = torch.fft.ifft(spec[:, y0:y0 + chunk], dim=0)
+        for z0 in range(0, n, chunk):  # along y, then the real transform along x
+            blk = torch.fft.ifft(spec[z0:z0 + chunk], dim=1)
+            out[c, z0:z0 + chunk] = torch.fft.irfft(blk, n=n, dim=2)
+            del blk
+        del spec
+        ss = torch.zeros((), dtype=torch.float64, device=device)
+        for z0 in range(0, n, chunk):
+            ss += out[c, z0:z0 + chunk].double().square().sum()
+        out[c] /= float((ss / float(n) ** 3).sqrt())
+    return out
+
+
 def uniform_particles_np(np_, L=TWO_PI, seed=1):
     """FP64 positions [3][np] uniform in [0, L)^3."""
     rng = np.random.Generator(np.random.PCG64(seed))

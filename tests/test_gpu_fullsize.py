@@ -1,0 +1,197 @@
+"""Parity at the full sizes of the workloads, on sampled outputs.
+
+The FP64 oracle cannot solve a 1024^3 or 2048^3 field on the host in test
+time, so the sampled references come from the windowed closed-form oracle
+(coefficients from the closed-form periodic inverse over +-28 points per axis,
+exact to 5e-16 of max|g|; pinned in test_oracle_window.py) applied to the very
+FP32 field the GPU used.  The 256^3 differentiation workload is compared in
+full with the plain oracle.
+
+  1024^3, 64M clustered particles: sampled coefficients, (u,v,w) and the nine
+    gradients at 256 sampled particles, and their displacement after 20 Heun
+    steps with the cell sort every step (FP32 and BF16-stored coefficients);
+  2048^3, 256M uniform particles (64-bit sort keys): sort, the 12-output
+    gather on the sorted particles and one sorted Heun step, sampled;
+  256^3, 1M particles: L = sum |x(8)|^2 through TrackParticles (checkpoints
+    every 2 steps) against the oracle's hand adjoint, all outputs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+F32_TOL = 1e-5
+BF16_TOL = 5e-3
+GRAD_BF16_TOL = 2e-2
+
+
+@pytest.fixture(scope="module")
+def pt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_13193_amd as pt
+    return pt
+
+
+def log(*a):
+    print("[fullsize]", *a, file=sys.stderr, flush=True)
+
+
+def normwise(y, ref):
+    y = np.asarray(y, dtype=np.float64).reshape(ref.shape[0], -1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(ref.shape[0], -1)
+    return max(np.abs(y[r] - ref[r]).max() / max(np.abs(ref[r]).max(), 1e-300)
+               for r in range(ref.shape[0]))
+
+
+def max_abs(t):
+    """max |t| without a temporary of the size of t."""
+    return max(float(t.max()), -float(t.min()))
+
+
+def free_bytes():
+    import torch
+    return torch.cuda.mem_get_info()[0]
+
+
+def field_to_host(field):
+    """FP32 host copy of a [3][n][n][n] device field, slab by slab."""
+    out = np.empty(tuple(field.shape), dtype=np.float32)
+    n = field.shape[1]
+    step = max(1, n // 16)
+    for c in range(3):
+        for z0 in range(0, n, step):
+            out[c, z0:z0 + step] = field[c, z0:z0 + step].cpu().numpy()
+    return out
+
+
+def slots_of(ids, sample):
+    """Positions in the (permuted) particle arrays of the original ids."""
+    import torch
+    inv = torch.empty_like(ids)
+    inv[ids.long()] = torch.arange(ids.numel(), dtype=ids.dtype, device=ids.device)
+    return inv[sample].long()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_c3_1024_sampled(pt, dtype):
+    import torch
+    from paper_2005_13193_amd import _binding as B
+    n, np_, kmax, steps = 1024, 64 * 2 ** 20, 341, 20
+    if free_bytes() < 40 * 2 ** 30:
+        pytest.skip("needs 40 GiB of free device memory")
+    dev = torch.device("cuda:0")
+    cdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    g, og = pt.Grid(n), oracle.Grid(n)
+    log(f"c3 {dtype}: field 1024^3")
+    field = synth.spectral_field_torch(n, kmax, seed=0, device=dev)
+    dt = synth.cfl_dt(max_abs(field), n)
+    coeff = pt.spline_coeffs(g, field, cdt)
+    torch.cuda.synchronize()
+    fh = field_to_host(field)
+    del field
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(8)
+    if dtype == "f32":
+        pts = rng.integers(0, n, size=(3, 200))
+        ref = oracle.coeffs_at(fh, pts)
+        got = coeff[:, torch.from_numpy(pts[2] + 1).to(dev), torch.from_numpy(pts[1] + 1).to(dev),
+                    torch.from_numpy(pts[0] + 1).to(dev)].double().cpu().numpy()
+        assert normwise(got, ref) < F32_TOL
+        log("sampled coefficients ok")
+    pos = synth.clustered_particles_torch(np_, sigma=0.1, device=dev)
+    # 256 ids: 128 of the uniform half, 128 of the clustered half
+    sample = torch.arange(0, np_, np_ // 256, device=dev)
+    pos0 = pos[:, sample].cpu().numpy()
+    # (u,v,w) and gradients at the sampled starting points
+    out12 = pt.interp_grad(g, coeff, pos[:, sample].contiguous()).double().cpu().numpy()
+    ref12 = oracle.interp_window(og, fh, pos0, n_out=12)
+    assert normwise(out12[:3], ref12[:3]) < (F32_TOL if dtype == "f32" else BF16_TOL)
+    assert normwise(out12[3:], ref12[3:]) < (F32_TOL if dtype == "f32" else GRAD_BF16_TOL)
+    log("sampled gather ok")
+    ids = torch.arange(np_, dtype=torch.int32, device=dev)
+    ws = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
+    for s in range(steps):
+        pt.rk2_step(g, coeff, pos, dt, ids=ids, sort=True, ws=ws)
+    assert pt.last_device_error() == 0
+    fin = pos[:, slots_of(ids, sample)].cpu().numpy()
+    log("20 steps done; oracle trajectories")
+    ref = oracle.rk2_window(og, fh, pos0, dt, steps)
+    err = normwise(fin - pos0, ref - pos0)
+    log(f"c3 {dtype}: displacement error {err:.3e}")
+    assert err < (F32_TOL if dtype == "f32" else BF16_TOL)
+    del pos, ids, ws, coeff
+    torch.cuda.empty_cache()
+
+
+def test_c5_2048_sampled(pt):
+    import torch
+    from paper_2005_13193_amd import _binding as B
+    n, np_, kmax = 2048, 256 * 2 ** 20, 682
+    if free_bytes() < 250 * 2 ** 30:
+        pytest.skip("needs 250 GiB of free device memory")
+    dev = torch.device("cuda:0")
+    g, og = pt.Grid(n), oracle.Grid(n)
+    log("c5: field 2048^3")
+    field = synth.spectral_field_torch_chunked(n, kmax, seed=0, device=dev)
+    torch.cuda.empty_cache()
+    dt = synth.cfl_dt(max_abs(field), n)
+    coeff = pt.spline_coeffs(g, field)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log("c5: coefficients done; host copy of the field")
+    fh = field_to_host(field)
+    del field
+    torch.cuda.empty_cache()
+    pos = synth.uniform_particles_torch(np_, seed=1, device=dev)
+    sample = torch.arange(0, np_, np_ // 128, device=dev)
+    pos0 = pos[:, sample].cpu().numpy()
+    ps, perm, _ = pt.sort_particles(g, pos, want_keys=False)
+    out12 = pt.interp_grad(g, coeff, ps)
+    inv = torch.empty_like(perm)
+    inv[perm.long()] = torch.arange(np_, dtype=perm.dtype, device=dev)
+    got = out12[:, inv[sample].long()].double().cpu().numpy()
+    del ps, perm, out12, inv
+    torch.cuda.empty_cache()
+    ref12 = oracle.interp_window(og, fh, pos0, n_out=12)
+    assert normwise(got, ref12) < F32_TOL
+    log("c5: sorted 12-output gather ok")
+    ids = torch.arange(np_, dtype=torch.int32, device=dev)
+    pt.rk2_step(g, coeff, pos, dt, ids=ids, sort=True)
+    assert pt.last_device_error() == 0
+    fin = pos[:, slots_of(ids, sample)].cpu().numpy()
+    ref = oracle.rk2_window(og, fh, pos0, dt, 1)
+    err = normwise(fin - pos0, ref - pos0)
+    log(f"c5: step displacement error {err:.3e}")
+    assert err < F32_TOL
+    del pos, ids, coeff
+    torch.cuda.empty_cache()
+
+
+def test_c4_256_adjoint_k8(pt):
+    import torch
+    from paper_2005_13193_amd.autograd import TrackParticles
+    n, np_, kmax, K = 256, 2 ** 20, 85, 8
+    dev = torch.device("cuda:0")
+    g, og = pt.Grid(n), oracle.Grid(n)
+    field = synth.spectral_field_torch(n, kmax, seed=0, device=dev)
+    dt = synth.cfl_dt(max_abs(field), n)
+    pos0 = synth.uniform_particles_torch(np_, seed=1, device=dev)
+    f = field.clone().requires_grad_(True)
+    p = pos0.clone().requires_grad_(True)
+    pos_k, _ids = TrackParticles.apply(f, p, g, dt, K)
+    loss = (pos_k * pos_k).sum()
+    loss.backward()
+    assert pt.last_device_error() == 0
+    log("c4: GPU adjoint done; oracle")
+    ref_loss, ref_gpos, ref_gfield = oracle.loss_and_grads(
+        og, field.double().cpu().numpy(), pos0.cpu().numpy(), dt, K)
+    assert abs(loss.item() - ref_loss) <= 1e-6 * ref_loss
+    assert normwise(p.grad.cpu().numpy(), ref_gpos) < F32_TOL
+    assert normwise(f.grad.reshape(3, -1).cpu().numpy(), ref_gfield.reshape(3, -1)) < F32_TOL
