@@ -104,18 +104,25 @@ def measured_traffic(kernel, config, dtype, clustered):
         return None
 
 
-def cpu_baseline(n_full, np_full):
+def cpu_baseline(n_full, np_full, clustered):
     """FP64 oracle, timed on this host, on a bounded sample of the same step:
-    the spline solve on a 256^3 grid and the fwd+adjoint particle work for
-    2^21 particles, each scaled linearly to the full grid and particle count."""
+    the spline solve and its adjoint on a 512^3 grid and the fwd+adjoint
+    particle work (sort, Heun step, re-sort, step adjoint) for 2^24 particles
+    of the workload's distribution, each scaled linearly to the full grid and
+    particle count."""
     import numpy as np
 
     import oracle
     import synth
 
-    ns, nps = 256, 2 ** 21
-    f = synth.spectral_field_np(ns, 85, seed=0)
-    pos = synth.uniform_particles_np(nps, seed=1)
+    ns, nps = 512, 2 ** 24
+    # the same synthetic spectrum; generated on the device (numpy's FFT at
+    # 512^3 would take longer than the timed sample), timed work is host-only
+    f = synth.spectral_field_torch(ns, ns // 3, seed=0, device="cuda:0").double().cpu().numpy()
+    if clustered:
+        pos = synth.clustered_particles_np(nps)
+    else:
+        pos = synth.uniform_particles_np(nps, seed=1)
     g = oracle.Grid(ns)
     dt = synth.cfl_dt(np.abs(f).max(), ns)
     t0 = time.perf_counter()
@@ -137,7 +144,8 @@ def cpu_baseline(n_full, np_full):
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": (f"FP64 oracle: spline solve + solve adjoint on a {ns}^3 grid "
                        f"(x{grid_scale:.0f} to {n_full}^3) and sort + Heun step + step adjoint "
-                       f"for {nps} uniform particles (x{part_scale:.0f} to {np_full}); "
+                       f"for {nps} {'clustered' if clustered else 'uniform'} particles "
+                       f"(x{part_scale:.0f} to {np_full}); "
                        f"sample took {t3 - t0:.1f} s"),
             "ms_per_step_est": 1e3 * t_step}
 
@@ -287,7 +295,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(n, np_)
+        out["cpu_baseline"] = cpu_baseline(n, np_, clustered)
     print(json.dumps(out), flush=True)
 
 

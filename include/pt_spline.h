@@ -169,7 +169,7 @@ pt_status pt_interp_uvw_bwd(const pt_grid *grid, const void *coeff, pt_dtype dty
 /* Adjoint of pt_spline_coeffs.  Each padded coefficient gradient is folded
  * onto the grid line it copies, then the transposed line solves are applied
  * (the 1-4-1 periodic matrix is symmetric, so they are the same solves) in the
- * order y, z, x.  g_coeff float [3][nz+3][ny+3][nx+3] in (not modified);
+ * order x (fused with the fold), y, z.  g_coeff float [3][nz+3][ny+3][nx+3] in (not modified);
  * g_field float [3][nz][ny][nx] out (overwritten). */
 pt_status pt_spline_coeffs_bwd(const pt_grid *grid, const float *g_coeff, float *g_field,
                                void *ws, size_t ws_bytes, hipStream_t stream);

@@ -1,32 +1,31 @@
 // Column-tiled gathers and scatter for particles ordered by cell.
 //
 // After pt_sort_particles the particles of a column of kTileX x kTileY cells
-// are contiguous and ordered by layer z.  One workgroup takes one column over
-// a segment of layers and marches up in z with a ring of kRing padded
-// coefficient planes of the column's tile staged in LDS, so that every
-// coefficient is read from HBM about once per column (plus the three shared
-// halo rows/columns and the planes at segment ends).  Per slab of kSlab
-// layers the ring holds planes z-1 .. z+5: the stencils of the particles of
-// the slab and of points up to one layer away (the RK2 predictor moves a
-// particle by at most ~0.6 cell per step).  Points whose stencil is not in
-// the ring (they left the column or moved more than one layer) take a slow
-// path from global memory.
+// are contiguous and ordered by layer z.  Work items are runs of layers of
+// one column (gather) or half-column (scatter); a launch holds one workgroup
+// per compute unit, and the workgroups draw items from per-XCD counters until
+// every item is taken.  Each workgroup marches up in z through its item with
+// a ring of padded coefficient planes of the column's tile in LDS, so that
+// every coefficient is read from HBM about once per column (plus the halo
+// rows/columns shared with neighbouring columns, which hit in L2, and the
+// planes at item ends).
 //
-// Latency: the load queue of a wave retires in order, so waiting on one load
-// waits on every older one.  Every iteration therefore issues its prefetch
-// (plane data and first-pass particle data for the next-but-one slab) at its
-// very end, after all loads it waits on itself.
+// tile_gather: both Heun stages (forward) or the step adjoint's gather half
+// (backward) per particle.  Two loader waves fill the ring with direct
+// global-to-LDS loads several planes ahead; eight compute waves evaluate the
+// particles of the current slab of layers, four lanes per point.  Points
+// whose stencil is not in the ring (the predictor left the column or moved
+// more than one layer) are deferred to gather_deferred, which redoes them from
+// global memory.
 //
-// Four lanes evaluate one point: lane i holds the x-offset i of the 4x4x4
-// stencil, sums the 16 (y, z) rows for each component, and the partial sums
-// are combined with quad DPP moves.
+// tile_scatter: the adjoint of the 64-term sums into the coefficient
+// gradient, summed in 64-bit fixed point in an LDS ring and added to HBM one
+// plane at a time; launches by colour keep concurrent workgroups on disjoint
+// coefficients, and stencils that do not fit go to scatter_deferred.
 #include "pt_common.h"
 
 namespace pt {
 
-constexpr int kTB = 512;          // threads per workgroup
-constexpr int kGroups = kTB / 4;  // points per pass
-constexpr int kRing = 8;          // LDS plane slots (power of two)
 constexpr int kSlab = 2;          // layers per iteration
 constexpr int kGatherSeg = 128;   // layers per gather work item
 constexpr int kScatterSeg = 256;  // layers per scatter work item
@@ -36,19 +35,6 @@ constexpr int kHalfShift = 9;     // log2(kTileX * kTileY / 2)
 constexpr int kMaxSlots = 64;     // slots for the largest |ub| (see zero_int)
 constexpr int kDeferHeader = 512; // bytes before the deferred list
 static_assert(kTileX * kTileY == (2 << kHalfShift), "half-layer shift");
-
-// Tile geometry with an M-cell margin around the column in x and y.
-template <int M>
-struct Geo {
-  static constexpr int TW = kTileX + 3 + 2 * M;  // tile width in padded points
-  static constexpr int TH = kTileY + 3 + 2 * M;
-  static constexpr int RowP = TW + 1;
-  static constexpr int CompP = TH * RowP + 4;
-  static constexpr int SlotP = 3 * CompP + 4;
-  static constexpr int Elems = 3 * TW * TH;
-  static constexpr int PerThread = (Elems + kTB - 1) / kTB;
-  static constexpr int RingFloats = kRing * SlotP;
-};
 
 struct TileArgs {
   GridDev g;
@@ -83,55 +69,6 @@ __device__ __forceinline__ float pick4(const float w[4], int i) {
   return i == 0 ? w[0] : i == 1 ? w[1] : i == 2 ? w[2] : w[3];
 }
 
-// ------------------------------------------------------ plane staging ---
-// Thread-to-element map of one tile plane: element e = tid + q * kTB is
-// component c, row y, column x.  Every load is issued (addresses clamped into
-// the array) so that each iteration issues the same number of loads.
-template <int M>
-__device__ __forceinline__ void plane_elem(int q, int* c, int* y, int* x, bool* in) {
-  using G = Geo<M>;
-  int e = threadIdx.x + q * kTB;
-  *in = e < G::Elems;
-  e = *in ? e : G::Elems - 1;
-  *c = e / (G::TW * G::TH);
-  const int r = e - *c * (G::TW * G::TH);
-  *y = r / G::TW;
-  *x = r - *y * G::TW;
-}
-
-template <typename CT, int M>
-__device__ __forceinline__ void load_plane(const CT* coeff, const GridDev& g, int X0, int Y0,
-                                           int P, float* v) {
-  using G = Geo<M>;
-  const int npad = g.nz + 3;
-  const bool pok = P >= 0 && P < npad;
-  const int Pc = min(max(P, 0), npad - 1);
-#pragma unroll
-  for (int q = 0; q < G::PerThread; ++q) {
-    int c, y, x;
-    bool in;
-    plane_elem<M>(q, &c, &y, &x, &in);
-    const int X = X0 + x, Y = Y0 + y;
-    const bool ok = in && pok && X >= 0 && X < g.px && Y >= 0 && Y < g.py;
-    const int Xc = min(max(X, 0), g.px - 1), Yc = min(max(Y, 0), g.py - 1);
-    const float t =
-        load_coeff(coeff + c * g.comp + (int64_t)Pc * g.plane + (int64_t)Yc * g.px + Xc);
-    v[q] = ok ? t : 0.0f;
-  }
-}
-
-template <int M>
-__device__ __forceinline__ void store_plane(float* lds, int slot, const float* v) {
-  using G = Geo<M>;
-#pragma unroll
-  for (int q = 0; q < G::PerThread; ++q) {
-    int c, y, x;
-    bool in;
-    plane_elem<M>(q, &c, &y, &x, &in);
-    if (in) lds[slot * G::SlotP + c * G::CompP + y * G::RowP + x] = v[q];
-  }
-}
-
 // ---------------------------------------------------- point evaluation ---
 struct Pt {
   int a, b, c;     // cell
@@ -160,54 +97,8 @@ __device__ __forceinline__ Pt locate_pt(const GridDev& g, const double p[3], int
   return q;
 }
 
-// Value (GRAD: and gradient) of the three components at a resident point;
-// every lane of the quad returns the full result.
-template <int M, bool GRAD>
-__device__ __forceinline__ void eval_lds(const float* lds, const GridDev& g, const Pt& q, int X0,
-                                         int Y0, int lane, float out[12]) {
-  using G = Geo<M>;
-  float wx[4], wy[4], wz[4], dwx[4], dwy[4], dwz[4];
-  bspline_w(q.t[0], wx);
-  bspline_w(q.t[1], wy);
-  bspline_w(q.t[2], wz);
-  if (GRAD) {
-    bspline_dw(q.t[0], dwx);
-    bspline_dw(q.t[1], dwy);
-    bspline_dw(q.t[2], dwz);
-  }
-  const float wxi = pick4(wx, lane);
-  const float dwxi = GRAD ? pick4(dwx, lane) : 0.0f;
-  const int col = (q.a - X0) + lane;
-  const int row0 = q.b - Y0;
-#pragma unroll
-  for (int comp = 0; comp < 3; ++comp) {
-    float A = 0.f, B = 0.f, C = 0.f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float* pl = lds + ((q.c + k) & (kRing - 1)) * G::SlotP + comp * G::CompP + col;
-      float sy = 0.f, sdy = 0.f;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float s = pl[(row0 + j) * G::RowP];
-        sy += wy[j] * s;
-        if (GRAD) sdy += dwy[j] * s;
-      }
-      A += wz[k] * sy;
-      if (GRAD) {
-        B += wz[k] * sdy;
-        C += dwz[k] * sy;
-      }
-    }
-    out[comp] = quad_sum(wxi * A);
-    if (GRAD) {
-      out[3 + 3 * comp + 0] = quad_sum(dwxi * A) * g.inv_h[0];
-      out[3 + 3 * comp + 1] = quad_sum(wxi * B) * g.inv_h[1];
-      out[3 + 3 * comp + 2] = quad_sum(wxi * C) * g.inv_h[2];
-    }
-  }
-}
-
-// Same quantity from global memory (points outside the ring).
+// Value (GRAD: and gradient) of the three components at a point, read from
+// global memory (points whose stencil is not resident in LDS).
 template <typename CT, bool GRAD>
 __device__ __forceinline__ void eval_global(const CT* __restrict__ coeff, const GridDev& g,
                                             const Pt& q, float out[12]) {
@@ -251,13 +142,6 @@ __device__ __forceinline__ void eval_global(const CT* __restrict__ coeff, const 
       out[3 + 3 * comp + 2] = gz * g.inv_h[2];
     }
   }
-}
-
-template <typename CT, bool GRAD>
-__device__ __forceinline__ void eval_point(const float* lds, const CT* coeff, const GridDev& g,
-                                           const Pt& q, int X0, int Y0, int lane, float out[12]) {
-  if (q.in_ring) eval_lds<0, GRAD>(lds, g, q, X0, Y0, lane, out);
-  else eval_global<CT, GRAD>(coeff, g, q, out);
 }
 
 // ------------------------------------------------------- gather kernels ---
@@ -760,10 +644,13 @@ __device__ __forceinline__ void scatter_ring(long long* ring, const Pt& q, int X
   }
 }
 
+// Per-particle data of a scatter pass, kept as loaded: any arithmetic on a
+// loaded value here would make the wave wait for that load (and every older
+// one) at prefetch time.
 struct SData {
   double x[3];
   float u0[3];
-  float ub1[3];  // dt/2 lam
+  double lam[3];  // ub1 = dt/2 lam is formed at use
   float ub0[3];
   int p;
   bool ok;
@@ -778,7 +665,7 @@ __device__ __forceinline__ void load_sdata(const TileArgs& a, int64_t p, bool ok
   for (int c = 0; c < 3; ++c) {
     d->x[c] = a.x[c * np + i];
     d->u0[c] = a.u0[c * np + i];
-    d->ub1[c] = (float)(0.5 * a.dt * a.lam[c * np + i]);
+    d->lam[c] = a.lam[c * np + i];
     d->ub0[c] = a.ub0[c * np + i];
   }
 }
@@ -797,7 +684,7 @@ __device__ __forceinline__ void scatter_one(const TileArgs& a, long long* ring, 
   for (int c = 0; c < 3; ++c) {
     xs[c] = d.x[c] + a.dt * (double)d.u0[c];
     s0[c] = d.ub0[c] * scale;
-    s1[c] = d.ub1[c] * scale;
+    s1[c] = (float)(0.5 * a.dt * d.lam[c]) * scale;
   }
   // cells with tile-local index in [0, kTileX + 2) x [0, kTileY/2 + 2) and
   // layers zz-1 .. zz+2 have their stencils inside the tile and the ring
@@ -926,13 +813,17 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
         slab_range(zs, &r0, &n0, &r1, &n1);
         const int64_t n = n0 + n1;
         const int64_t npass = (n + kSGroups - 1) / kSGroups;
-        SData cur = sd[hf];
-        for (int64_t k = 0; k < npass; ++k) {
-          SData nxt;
-          const int64_t v = grp * npass + k + 1;
-          load_sdata(a, vidx(v, r0, n0, r1), k + 1 < npass && v < n, &nxt);
-          if (cur.ok) scatter_one(a, ring, cur, X0, Y0, zs, lane, scale);
-          cur = nxt;
+        // passes alternate between two register sets, the next pass loading
+        // into the set not in use (no copies between sets, which would make
+        // the wave wait for the loads in flight)
+        SData sb;
+        for (int64_t k = 0; k < npass; k += 2) {
+          const int64_t v = grp * npass + k;
+          if (k + 1 < npass) load_sdata(a, vidx(v + 1, r0, n0, r1), v + 1 < n, &sb);
+          if (sd[hf].ok) scatter_one(a, ring, sd[hf], X0, Y0, zs, lane, scale);
+          if (k + 1 >= npass) break;
+          if (k + 2 < npass) load_sdata(a, vidx(v + 2, r0, n0, r1), v + 2 < n, &sd[hf]);
+          if (sb.ok) scatter_one(a, ring, sb, X0, Y0, zs, lane, scale);
         }
         __syncthreads();
         // planes zs-1 and zs are complete: later particles sit in layers
@@ -1162,11 +1053,6 @@ __global__ __launch_bounds__(1024) void scan_items(int* data, int n, int nunits,
 }
 
 // ------------------------------------------------------------ host side ---
-template <int M>
-static size_t tile_lds_bytes(int seg) {
-  return (size_t)Geo<M>::RingFloats * sizeof(float) + sizeof(int) * (size_t)(seg + 4);
-}
-
 // number of half-layers (entries of the particle table minus one)
 int64_t tile_nlayers(const pt_grid* g) {
   const int64_t ncx = (g->nx + kTileX - 1) / kTileX, ncy = (g->ny + kTileY - 1) / kTileY;
