@@ -41,6 +41,7 @@ def _load():
         lib.oracle_stable_sort.restype = None
         lib.oracle_interp.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, vp, i32, vp]
         lib.oracle_rk2_step.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, dbl, vp]
+        lib.oracle_rk2_step_tv.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, vp, i64, dbl, vp]
         lib.oracle_interp_bwd.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, vp, vp,
                                           vp, vp]
         lib.oracle_spline_coeffs_bwd.argtypes = [i32, i32, i32, vp, vp]
@@ -52,7 +53,8 @@ def _load():
         lib.oracle_rk2_window.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i32, i32, i64,
                                           dbl, i32, vp]
         for name in ("oracle_solve_line", "oracle_spline_coeffs", "oracle_cell_keys",
-                     "oracle_interp", "oracle_rk2_step", "oracle_interp_bwd",
+                     "oracle_interp", "oracle_rk2_step", "oracle_rk2_step_tv",
+                     "oracle_interp_bwd",
                      "oracle_spline_coeffs_bwd", "oracle_rk2_step_bwd", "oracle_coeffs_at",
                      "oracle_interp_window", "oracle_rk2_window"):
             getattr(lib, name).restype = i32
@@ -155,6 +157,16 @@ def rk2_step(grid, coeff, pos, dt):
     coeff = _f64(coeff)
     p = _f64(pos).copy()
     _chk(_load().oracle_rk2_step(*grid.args, _ptr(coeff), p.shape[1], dt, _ptr(p)))
+    return p
+
+
+def rk2_step_tv(grid, coeff_n, coeff_np1, pos, dt):
+    """One Heun step whose predictor uses the field at t_n (coeff_n) and whose
+    corrector uses the field at t_n + dt (coeff_np1); new positions."""
+    coeff_n, coeff_np1 = _f64(coeff_n), _f64(coeff_np1)
+    p = _f64(pos).copy()
+    _chk(_load().oracle_rk2_step_tv(*grid.args, _ptr(coeff_n), _ptr(coeff_np1), p.shape[1], dt,
+                                    _ptr(p)))
     return p
 
 

@@ -375,6 +375,29 @@ int oracle_rk2_step(int nx, int ny, int nz, double lx, double ly, double lz,
   return OR_OK;
 }
 
+/* One Heun step in a field that changes over the step.  In the paper's
+ * production runs (Sec. 4.3, Table 5) the particles are advanced at each
+ * sub-step of the flow solver's second-order Runge-Kutta scheme, with spline
+ * coefficients recomputed from the velocity field of that sub-step: the
+ * predictor uses the field at t_n, the corrector the field at t_n + dt.
+ *   u0 = u^n(x);  x* = x + dt u0;  x <- x + dt/2 (u0 + u^{n+1}(x*)). */
+int oracle_rk2_step_tv(int nx, int ny, int nz, double lx, double ly, double lz,
+                       const double *coeff_n, const double *coeff_np1, int64_t np,
+                       double dt, double *pos) {
+  if (!check_finite(np, pos)) return OR_ERR_NONFINITE;
+  or_grid gr = {nx, ny, nz, lx, ly, lz};
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < np; ++p) {
+    double x0[3] = {pos[p], pos[np + p], pos[2 * np + p]};
+    double u0[12], u1[12], xs[3];
+    eval_particle(&gr, coeff_n, x0[0], x0[1], x0[2], 0, u0);
+    for (int d = 0; d < 3; ++d) xs[d] = x0[d] + dt * u0[d];
+    eval_particle(&gr, coeff_np1, xs[0], xs[1], xs[2], 0, u1);
+    for (int d = 0; d < 3; ++d) pos[d * np + p] = x0[d] + 0.5 * dt * (u0[d] + u1[d]);
+  }
+  return OR_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Adjoints (hand-derived; the paper has no differentiation).               */
 /* ------------------------------------------------------------------------ */
