@@ -156,6 +156,44 @@ pt_status pt_rk2_step(const pt_grid *grid, const void *coeff, pt_dtype dtype,
                       int64_t np, double dt, double *pos, int32_t *ids, int sort,
                       void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The same step in a field that changes over the step, in two calls.  In the
+ * paper's production runs (Sec. 4.3, Table 5) the particles are advanced at
+ * each sub-step of the flow solver's second-order Runge-Kutta scheme, with
+ * the spline coefficients of that sub-step's velocity field: the predictor
+ * uses the field at t_n, the corrector the field at t_n + dt.
+ *
+ * Stage 1, with the coefficients of u(., t_n):
+ *   u_n = u^n(x)
+ * If sort != 0 the particles are first re-ordered as by pt_sort_particles;
+ * pos (and ids, if not NULL) come back in the new order, and ws keeps the
+ * table of particles per cell layer for stage 2.
+ *   coeff_n  in   padded coefficients of the field at t_n, of `dtype`
+ *   pos      in/out double [3][np]  (only re-ordered)
+ *   ids      in/out int32 [np] or NULL
+ *   u_n      out  float [3][np], in the order pos leaves in
+ *   ws            >= pt_workspace_bytes(PT_OP_RK2, ...) bytes */
+pt_status pt_rk2_stage1(const pt_grid *grid, const void *coeff_n, pt_dtype dtype,
+                        int64_t np, double *pos, int32_t *ids, int sort, float *u_n,
+                        void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Stage 2, with the coefficients of u(., t_n + dt):
+ *   x* = x + dt u_n;  x <- x + dt/2 (u_n + u^{n+1}(x*))
+ * (FP64 positions, FP32 velocities), pos updated in place.  With sorted != 0
+ * the particles are taken in the cell order of the stage 1 that sorted them,
+ * and ws must be that call's workspace (same grid, np and size).  The table
+ * it holds is checked on the device; a table that is not a partition of the
+ * np particles (ws reused in between) makes every particle go through the
+ * slower path that reads the coefficients from global memory, with the same
+ * result.  Positions moved since stage 1 are handled the same way.
+ *   coeff_np1  in   padded coefficients of the field at t_n + dt
+ *   pos        in/out double [3][np]
+ *   u_n        in   float [3][np] from stage 1
+ *   ws              >= pt_workspace_bytes(PT_OP_RK2, ...) bytes (unused when
+ *                   sorted == 0, may then be NULL) */
+pt_status pt_rk2_stage2(const pt_grid *grid, const void *coeff_np1, pt_dtype dtype,
+                        int64_t np, double dt, double *pos, const float *u_n, int sorted,
+                        void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Adjoint of pt_interp_uvw (not in the paper).  With gu = dL/d(u,v,w):
  *   g_pos[d][p]  += sum_c gu[c][p] du_c/dx_d (p)          (may be NULL)
  *   g_coeff[c][.] += b_i c_j d_k gu[c][p] over each stencil (may be NULL),
@@ -201,7 +239,8 @@ const char *pt_status_string(pt_status status);
  * pass that writes the padded coefficients), "spline_x_fold" (the adjoint's
  * x pass that reads the padded gradient),
  * "sort_keys", "sort_pass", "sort_permute", "tile_rk2_fwd",
- * "tile_rk2_bwd_gather", "tile_scatter", "interp". */
+ * "tile_rk2_bwd_gather", "tile_scatter", "tile_tv_stage1", "tile_tv_stage2",
+ * "interp". */
 pt_status pt_timing_enable(int on);
 pt_status pt_timing_read(const char *kernel, double *total_ms, int64_t *launches);
 

@@ -128,6 +128,27 @@ def rk2_step(grid, coeff, pos, dt, ids=None, sort=True, ws=None):
     return pos
 
 
+def rk2_stage1(grid, coeff_n, pos, ids=None, sort=True, u_n=None, ws=None):
+    """Stage 1 of a Heun step in a time-varying field: u_n = u^n(pos), after
+    an optional cell sort of pos (and ids) in place.  Returns (u_n, ws); pass
+    both to rk2_stage2."""
+    np_ = pos.shape[1]
+    if u_n is None:
+        u_n = torch.empty((3, np_), dtype=torch.float32, device=pos.device)
+    if ws is None:
+        ws = workspace(_b.PT_OP_RK2, grid, np_, coeff_n.dtype, pos.device)
+    _b.pt_rk2_stage1(grid, coeff_n, pos, ids, sort, u_n, ws)
+    return u_n, ws
+
+
+def rk2_stage2(grid, coeff_np1, pos, u_n, dt, sorted_=True, ws=None):
+    """Stage 2: pos <- pos + dt/2 (u_n + u^{n+1}(pos + dt u_n)) in place."""
+    if sorted_ and ws is None:
+        raise ValueError("rk2_stage2 with sorted_=True needs the workspace of rk2_stage1")
+    _b.pt_rk2_stage2(grid, coeff_np1, dt, pos, u_n, sorted_, ws)
+    return pos
+
+
 def rk2_step_bwd(grid, coeff, pos_n, dt, g_pos, g_coeff, sort=True, ws=None):
     """Adjoint of one step: g_pos (in: dL/dx_out) becomes dL/dpos_n in place;
     g_coeff accumulates."""

@@ -33,7 +33,8 @@ PT_OP_SPLINE_BWD = 3
 PT_OP_RK2_BWD = 4
 
 EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_sort_particles",
-           "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_interp_uvw_bwd",
+           "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_rk2_stage1", "pt_rk2_stage2",
+           "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
            "pt_status_string", "pt_timing_enable", "pt_timing_read")
 
@@ -66,6 +67,8 @@ def _load():
         "pt_interp_uvw": [g, vp, ctypes.c_int, i64, vp, vp, vp],
         "pt_interp_grad": [g, vp, ctypes.c_int, i64, vp, vp, vp],
         "pt_rk2_step": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
+        "pt_rk2_stage1": [g, vp, ctypes.c_int, i64, vp, vp, ctypes.c_int, vp, vp, sz, vp],
+        "pt_rk2_stage2": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
         "pt_interp_uvw_bwd": [g, vp, ctypes.c_int, i64, vp, vp, vp, vp, vp],
         "pt_spline_coeffs_bwd": [g, vp, vp, vp, sz, vp],
         "pt_rk2_step_bwd": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp, vp, vp, sz,
@@ -207,6 +210,31 @@ def pt_rk2_step(grid, coeff, dt, pos, ids, sort, ws, stream=None):
            LIB.pt_rk2_step(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
                            float(dt), _ptr(pos), _ptr(ids), int(bool(sort)), _ptr(ws),
                            ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pt_rk2_stage1(grid, coeff_n, pos, ids, sort, u_n, ws, stream=None):
+    np_ = pos.shape[1]
+    _need(coeff_n, None, grid.padded_shape, "coeff_n")
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(ids, torch.int32, (np_,), "ids")
+    _need(u_n, torch.float32, (3, np_), "u_n")
+    _check("pt_rk2_stage1",
+           LIB.pt_rk2_stage1(ctypes.byref(_grid(grid)), _ptr(coeff_n), _dtype_code(coeff_n), np_,
+                             _ptr(pos), _ptr(ids), int(bool(sort)), _ptr(u_n), _ptr(ws),
+                             0 if ws is None else ws.numel() * ws.element_size(),
+                             _stream(stream)))
+
+
+def pt_rk2_stage2(grid, coeff_np1, dt, pos, u_n, sorted_, ws, stream=None):
+    np_ = pos.shape[1]
+    _need(coeff_np1, None, grid.padded_shape, "coeff_np1")
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(u_n, torch.float32, (3, np_), "u_n")
+    _check("pt_rk2_stage2",
+           LIB.pt_rk2_stage2(ctypes.byref(_grid(grid)), _ptr(coeff_np1), _dtype_code(coeff_np1),
+                             np_, float(dt), _ptr(pos), _ptr(u_n), int(bool(sorted_)), _ptr(ws),
+                             0 if ws is None else ws.numel() * ws.element_size(),
+                             _stream(stream)))
 
 
 def pt_interp_uvw_bwd(grid, coeff, pos, g_out, g_pos, g_coeff, stream=None):

@@ -38,6 +38,8 @@ pt_status rk2_backward(const pt_grid* g, const void* coeff, pt_dtype dtype, int6
                        double* xbs, hipStream_t s);
 pt_status scatter_back(int64_t np, const double* in, const int32_t* perm, double* out,
                        hipStream_t s);
+pt_status rk2_correct(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
+                      const double* x, const float* u0, double* x_out, hipStream_t s);
 // tile.hip
 int64_t tile_nlayers(const pt_grid* g);
 pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
@@ -49,6 +51,12 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
                        float* u0, float* ub0, float* gcoeff, void* defer, void* items_ws,
                        hipStream_t s);
 size_t tile_defer_bytes(int64_t np);
+pt_status tile_tv_stage1(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
+                         int64_t np, const double* x, double* x_out, float* u_n, void* defer,
+                         void* items_ws, hipStream_t s);
+pt_status tile_tv_stage2(const pt_grid* g, const void* coeff, pt_dtype dtype, int32_t* ls,
+                         int64_t np, double dt, const double* x, const float* u_n, double* x_out,
+                         void* defer, void* items_ws, hipStream_t s);
 
 // One non-finite-position flag per device, in the library's static device
 // memory; kernels receive its device address.
@@ -307,6 +315,51 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
                         stream);
   }
   return rk2_advance(grid, coeff, dtype, np, dt, pos, pos, w.u0, stream);
+}
+
+pt_status pt_rk2_stage1(const pt_grid* grid, const void* coeff_n, pt_dtype dtype, int64_t np,
+                        double* pos, int32_t* ids, int sort, float* u_n, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (np == 0) return PT_OK;
+  if (!coeff_n || !pos || !u_n) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_RK2, grid, dtype, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  Rk2Ws w = carve_rk2(grid, np, ws);
+  if (sort) {
+    PT_TRY(sort_particles(grid, np, pos, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
+                          stream));
+    if (ids) {
+      PT_TRY(permute_ids(np, ids, w.perm, w.ids_tmp, stream));
+      PT_HIP_CHECK(hipMemcpyAsync(ids, w.ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
+    }
+    return tile_tv_stage1(grid, coeff_n, dtype, w.lstart, np, w.pos_sorted, pos, u_n, w.defer,
+                          w.items, stream);
+  }
+  return interp_fwd(grid, coeff_n, dtype, np, pos, u_n, 3, stream);
+}
+
+pt_status pt_rk2_stage2(const pt_grid* grid, const void* coeff_np1, pt_dtype dtype, int64_t np,
+                        double dt, double* pos, const float* u_n, int sorted, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (!isfinite(dt)) return PT_ERR_ARG;
+  if (np == 0) return PT_OK;
+  if (!coeff_np1 || !pos || !u_n) return PT_ERR_NULL;
+  PT_TRY(ready());
+  if (!sorted) return rk2_correct(grid, coeff_np1, dtype, np, dt, pos, u_n, pos, stream);
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_RK2, grid, dtype, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  Rk2Ws w = carve_rk2(grid, np, ws);
+  return tile_tv_stage2(grid, coeff_np1, dtype, w.lstart, np, dt, pos, u_n, pos, w.defer,
+                        w.items, stream);
 }
 
 pt_status pt_interp_uvw_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,

@@ -260,10 +260,10 @@ pt_status interp_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_
   return PT_OK;
 }
 
-pt_status rk2_advance(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
-                      const double* x, double* x_out, float* u0, hipStream_t s) {
-  pt_status st = interp_fwd(g, coeff, dtype, np, x, u0, 3, s);
-  if (st != PT_OK) return st;
+// Second Heun stage alone: x_out = x + dt/2 (u0 + u(x + dt u0)) with the
+// given coefficients (x_out may alias x).
+pt_status rk2_correct(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
+                      const double* x, const float* u0, double* x_out, hipStream_t s) {
   const GridDev gd = make_grid_dev(g);
   if (dtype == PT_F32)
     hipLaunchKernelGGL(rk2_stage2<float>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd,
@@ -273,6 +273,13 @@ pt_status rk2_advance(const pt_grid* g, const void* coeff, pt_dtype dtype, int64
                        (const uint16_t*)coeff, np, dt, x, u0, x_out, device_error_flag());
   PT_LAUNCH_CHECK();
   return PT_OK;
+}
+
+pt_status rk2_advance(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
+                      const double* x, double* x_out, float* u0, hipStream_t s) {
+  pt_status st = interp_fwd(g, coeff, dtype, np, x, u0, 3, s);
+  if (st != PT_OK) return st;
+  return rk2_correct(g, coeff, dtype, np, dt, x, u0, x_out, s);
 }
 
 pt_status interp_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,

@@ -33,6 +33,7 @@ constexpr int kScatterSeg = 256;  // layers per scatter work item
 // column layer (key >> 9 with 32 x 32 columns).
 constexpr int kHalfShift = 9;     // log2(kTileX * kTileY / 2)
 constexpr int kMaxSlots = 64;     // slots for the largest |ub| (see zero_int)
+constexpr int kTableBad = kMaxSlots + 1;  // defer header: particle table found invalid
 constexpr int kDeferHeader = 512; // bytes before the deferred list
 static_assert(kTileX * kTileY == (2 << kHalfShift), "half-layer shift");
 
@@ -163,7 +164,10 @@ constexpr int kGChunks = (kGComp + 63) / 64;   // 64-word chunks per component (
 constexpr int kGChunksPerLoader = (kGChunks + kLoaders - 1) / kLoaders;
 constexpr int kGGroups = kCompute / 4;
 
-enum { TILE_RK2_FWD = 0, TILE_RK2_BWD_GRAD = 1 };
+// Modes of the tiled gather: the fused Heun step, its adjoint's gathers, and
+// the two stages of a Heun step in a field that changes over the step
+// (stage 1 with the field at t_n, stage 2 with the field at t_n + dt).
+enum { TILE_RK2_FWD = 0, TILE_RK2_BWD_GRAD = 1, TILE_TV_STAGE1 = 2, TILE_TV_STAGE2 = 3 };
 
 __device__ __forceinline__ int gslot(int P) { return (P + kGRing) % kGRing; }
 
@@ -226,6 +230,7 @@ __device__ __forceinline__ void eval_ring(const uint32_t* ring, const GridDev& g
 struct PData {
   double x[3];
   double lam[3];
+  float un[3];  // stage 2: velocity of stage 1
   int p;
   bool ok;
 };
@@ -242,6 +247,10 @@ __device__ __forceinline__ void load_pdata(const TileArgs& a, int64_t p, bool ok
 #pragma unroll
     for (int c = 0; c < 3; ++c) d->lam[c] = a.lam[c * np + i];
   }
+  if (MODE == TILE_TV_STAGE2) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d->un[c] = a.u0[c * np + i];
+  }
 }
 
 __device__ __forceinline__ void defer_particle(int* count, int32_t* list, int64_t np, int p) {
@@ -249,9 +258,10 @@ __device__ __forceinline__ void defer_particle(int* count, int32_t* list, int64_
   if ((int64_t)i < np) list[i] = p;
 }
 
-// Both Heun stages (forward) or the whole step adjoint (backward) of one
-// particle from the ring.  A particle whose predictor point is not resident is
-// deferred to the cleanup kernel, which redoes it from global memory.
+// Both Heun stages (forward), the whole step adjoint (backward) or one stage
+// of the time-varying step of one particle from the ring.  A particle whose
+// predictor point is not resident is deferred to the cleanup kernel, which
+// redoes it from global memory.
 template <typename CT, int MODE>
 __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t* ring,
                                               const PData& d, int X0, int Y0, int zz, int lane,
@@ -265,7 +275,35 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
     if (lane == 0) defer_particle(a.defer_count, (int32_t*)a.defer, np, d.p);
     return;
   }
-  if (MODE == TILE_RK2_FWD) {
+  if (MODE == TILE_TV_STAGE1) {
+    // u^n at x; the positions are written back in the sorted order
+    float u0[12];
+    eval_ring<CT, false>(ring, g, qn, X0, Y0, lane, u0);
+    if (lane < 3) {
+      const int c = lane;
+      a.u0[c * np + p] = c == 0 ? u0[0] : c == 1 ? u0[1] : u0[2];
+      a.x_out[c * np + p] = c == 0 ? xn[0] : c == 1 ? xn[1] : xn[2];
+    }
+  } else if (MODE == TILE_TV_STAGE2) {
+    // x* = x + dt u^n (from stage 1), u^{n+1}(x*) from the ring
+    double xs[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)d.un[c];
+    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
+    if (!qs.in_ring) {
+      if (lane == 0) defer_particle(a.defer_count, (int32_t*)a.defer, np, d.p);
+      return;
+    }
+    float u1[12];
+    eval_ring<CT, false>(ring, g, qs, X0, Y0, lane, u1);
+    if (lane < 3) {
+      const double h = 0.5 * a.dt;
+      const double x0 = lane == 0 ? xn[0] : lane == 1 ? xn[1] : xn[2];
+      const float ua = lane == 0 ? d.un[0] : lane == 1 ? d.un[1] : d.un[2];
+      const float ub = lane == 0 ? u1[0] : lane == 1 ? u1[1] : u1[2];
+      a.x_out[lane * np + p] = x0 + h * ((double)ua + (double)ub);
+    }
+  } else if (MODE == TILE_RK2_FWD) {
     float u0[12], u1[12];
     eval_ring<CT, false>(ring, g, qn, X0, Y0, lane, u0);
     double xs[3];
@@ -485,18 +523,23 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
           const int64_t pb = lst[zs - z0];
           const int64_t pe = lst[min(zs + kSlab, z1) - z0];
           // passes of kGGroups particles; the data of pass k+1 is loaded
-          // (always, clamped) before pass k is processed
+          // before pass k is processed, into the register set not in use (a
+          // copy between sets would make the wave wait for the loads in
+          // flight)
           const int npass = (int)((pe - pb + kGGroups - 1) / kGGroups);
-          PData cur = pd[half];
-          for (int k = 0; k < npass; ++k) {
-            PData nxt;
-            const bool more = k + 1 < npass;  // uniform
-            if (more) {
+          PData sb;
+          for (int k = 0; k < npass; k += 2) {  // npass uniform
+            if (k + 1 < npass) {
               const int64_t pn = pb + (int64_t)(k + 1) * kGGroups + grp;
-              load_pdata<MODE>(a, pn, pn < pe, &nxt);
+              load_pdata<MODE>(a, pn, pn < pe, &sb);
             }
-            if (cur.ok) ring_particle<CT, MODE>(a, ring, cur, X0, Y0, zs, lane, &umax);
-            if (more) cur = nxt;
+            if (pd[half].ok) ring_particle<CT, MODE>(a, ring, pd[half], X0, Y0, zs, lane, &umax);
+            if (k + 1 >= npass) break;
+            if (k + 2 < npass) {
+              const int64_t pn = pb + (int64_t)(k + 2) * kGGroups + grp;
+              load_pdata<MODE>(a, pn, pn < pe, &pd[half]);
+            }
+            if (sb.ok) ring_particle<CT, MODE>(a, ring, sb, X0, Y0, zs, lane, &umax);
           }
           prefetch(half, s + 2);
         }
@@ -535,7 +578,26 @@ __global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
     if (p < 0 || p >= np) continue;
     double xn[3] = {a.x[p], a.x[np + p], a.x[2 * np + p]};
     const Pt qn = locate_pt<0>(g, xn, 0, 0, 0, -1, a.err);
-    if (MODE == TILE_RK2_FWD) {
+    if (MODE == TILE_TV_STAGE1) {
+      float u0[12];
+      eval_global<CT, false>(coeff, g, qn, u0);
+      for (int c = 0; c < 3; ++c) {
+        a.u0[c * np + p] = u0[c];
+        a.x_out[c * np + p] = xn[c];
+      }
+    } else if (MODE == TILE_TV_STAGE2) {
+      double xs[3];
+      float ua[3];
+      for (int c = 0; c < 3; ++c) {
+        ua[c] = a.u0[c * np + p];
+        xs[c] = xn[c] + a.dt * (double)ua[c];
+      }
+      const Pt qs = locate_pt<0>(g, xs, 0, 0, 0, -1, a.err);
+      float u1[12];
+      eval_global<CT, false>(coeff, g, qs, u1);
+      for (int c = 0; c < 3; ++c)
+        a.x_out[c * np + p] = xn[c] + 0.5 * a.dt * ((double)ua[c] + (double)u1[c]);
+    } else if (MODE == TILE_RK2_FWD) {
       float u0[12], u1[12];
       eval_global<CT, false>(coeff, g, qn, u0);
       double xs[3];
@@ -895,7 +957,33 @@ __global__ void zero_defer_count(int* p) { p[0] = 0; }
 // defer header: [0] deferred-list length, [1 .. kMaxSlots] largest |ub|
 // (float bits) per group of gather blocks
 __global__ void zero_int(int* p) {
-  if (threadIdx.x <= kMaxSlots) p[threadIdx.x] = 0;
+  if (threadIdx.x <= kTableBad) p[threadIdx.x] = 0;
+}
+
+// A particle table handed over from an earlier call: entries 0 .. nl must
+// rise from 0 to np.  Any other table raises the flag.
+__global__ __launch_bounds__(256) void check_table(const int32_t* __restrict__ ls, int64_t nl,
+                                                   int64_t np, int* bad) {
+  const int64_t h = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (h > nl) return;
+  const int64_t v = ls[h];
+  bool ok = v >= 0 && v <= np;
+  if (h == 0) ok = ok && v == 0;
+  if (h == nl) ok = ok && v == np;
+  else ok = ok && v <= (int64_t)ls[h + 1];
+  if (!ok) atomicOr(bad, 1);
+}
+
+// After a failed check: empty every layer and put every particle on the
+// deferred list, so that all of them are evaluated from global memory.
+__global__ __launch_bounds__(256) void table_fallback(int32_t* __restrict__ ls, int64_t nl,
+                                                      int64_t np, int* header,
+                                                      int32_t* __restrict__ list) {
+  if (header[kTableBad] == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i <= nl) ls[i] = 0;
+  if (i < np) list[i] = (int32_t)i;
+  if (i == 0) header[0] = (int)np;
 }
 
 // ------------------------------------------------------- layer table ---
@@ -1188,8 +1276,33 @@ static bool allow_lds(F* fn, size_t bytes) {
                              (int)bytes) == hipSuccess;
 }
 
+static const char* gather_name(int mode) {
+  switch (mode) {
+    case TILE_RK2_FWD: return "tile_rk2_fwd";
+    case TILE_RK2_BWD_GRAD: return "tile_rk2_bwd_gather";
+    case TILE_TV_STAGE1: return "tile_tv_stage1";
+    default: return "tile_tv_stage2";
+  }
+}
+
+// check: the particle table comes from an earlier call; verify it on the
+// device first (a table that fails sends every particle down the deferred
+// path, which needs no table).
 static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int mode,
-                               void* defer, void* items_ws, hipStream_t s) {
+                               void* defer, void* items_ws, bool check, hipStream_t s) {
+  a.defer_count = (int*)defer;
+  a.defer = (uint32_t*)((char*)defer + kDeferHeader);
+  hipLaunchKernelGGL(zero_int, dim3(1), dim3(128), 0, s, a.defer_count);
+  PT_LAUNCH_CHECK();
+  if (check) {
+    const int64_t nl = tile_nlayers(g);
+    const int64_t n = (nl + 1 > a.np ? nl + 1 : a.np);
+    hipLaunchKernelGGL(check_table, dim3(grid_1d(nl + 1, 256)), dim3(256), 0, s, a.lstart, nl,
+                       a.np, a.defer_count + kTableBad);
+    hipLaunchKernelGGL(table_fallback, dim3(grid_1d(n, 256)), dim3(256), 0, s,
+                       (int32_t*)a.lstart, nl, a.np, a.defer_count, (int32_t*)a.defer);
+    PT_LAUNCH_CHECK();
+  }
   ItemSet it;
   pt_status st = build_tile_items(g, a.np, a.lstart, false, items_ws, &it, s);
   if (st != PT_OK) return st;
@@ -1198,26 +1311,27 @@ static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int
   a.item_ctr = it.ctr;
   const unsigned blocks = item_blocks(it.bound);
   const size_t lds = sizeof(uint32_t) * ((size_t)kGRing * kGSlot + a.seg_len + 4 + kGTB / 64);
-  a.defer_count = (int*)defer;
-  a.defer = (uint32_t*)((char*)defer + kDeferHeader);
-  hipLaunchKernelGGL(zero_int, dim3(1), dim3(128), 0, s, a.defer_count);
-  PT_LAUNCH_CHECK();
 #define PT_TG(CT, MD)                                                                  \
   do {                                                                                 \
     if (!allow_lds(tile_gather<CT, MD>, lds)) return PT_ERR_HIP;                       \
     {                                                                                  \
-      TimedLaunch t(MD == TILE_RK2_FWD ? "tile_rk2_fwd" : "tile_rk2_bwd_gather", s);   \
+      TimedLaunch t(gather_name(MD), s);                                               \
       hipLaunchKernelGGL((tile_gather<CT, MD>), dim3(blocks), dim3(kGTB), lds, s, a);  \
     }                                                                                  \
     hipLaunchKernelGGL((gather_deferred<CT, MD>), dim3(256), dim3(256), 0, s, a);      \
   } while (0)
-  if (dtype == PT_F32) {
-    if (mode == TILE_RK2_FWD) PT_TG(float, TILE_RK2_FWD);
-    else PT_TG(float, TILE_RK2_BWD_GRAD);
-  } else {
-    if (mode == TILE_RK2_FWD) PT_TG(uint16_t, TILE_RK2_FWD);
-    else PT_TG(uint16_t, TILE_RK2_BWD_GRAD);
-  }
+#define PT_TG_MODES(CT)                                   \
+  do {                                                    \
+    switch (mode) {                                       \
+      case TILE_RK2_FWD: PT_TG(CT, TILE_RK2_FWD); break;  \
+      case TILE_RK2_BWD_GRAD: PT_TG(CT, TILE_RK2_BWD_GRAD); break; \
+      case TILE_TV_STAGE1: PT_TG(CT, TILE_TV_STAGE1); break; \
+      default: PT_TG(CT, TILE_TV_STAGE2); break;          \
+    }                                                     \
+  } while (0)
+  if (dtype == PT_F32) PT_TG_MODES(float);
+  else PT_TG_MODES(uint16_t);
+#undef PT_TG_MODES
 #undef PT_TG
   PT_LAUNCH_CHECK();
   return PT_OK;
@@ -1230,7 +1344,31 @@ pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
   a.x = x;
   a.x_out = x_out;
-  return launch_gather(g, a, dtype, TILE_RK2_FWD, defer, items_ws, s);
+  return launch_gather(g, a, dtype, TILE_RK2_FWD, defer, items_ws, false, s);
+}
+
+// Stage 1 of the time-varying step on sorted particles x (table ls):
+// u_n = u^n(x) and x_out = x (the sorted positions handed back).
+pt_status tile_tv_stage1(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
+                         int64_t np, const double* x, double* x_out, float* u_n, void* defer,
+                         void* items_ws, hipStream_t s) {
+  TileArgs a = tile_args(g, coeff, ls, np, 0.0, kGatherSeg);
+  a.x = x;
+  a.x_out = x_out;
+  a.u0 = u_n;
+  return launch_gather(g, a, dtype, TILE_TV_STAGE1, defer, items_ws, false, s);
+}
+
+// Stage 2: x_out = x + dt/2 (u_n + u^{n+1}(x + dt u_n)); x_out may alias x.
+// ls is the table of an earlier stage 1 and is checked on the device.
+pt_status tile_tv_stage2(const pt_grid* g, const void* coeff, pt_dtype dtype, int32_t* ls,
+                         int64_t np, double dt, const double* x, const float* u_n, double* x_out,
+                         void* defer, void* items_ws, hipStream_t s) {
+  TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
+  a.x = x;
+  a.x_out = x_out;
+  a.u0 = (float*)u_n;  // read only in this mode
+  return launch_gather(g, a, dtype, TILE_TV_STAGE2, defer, items_ws, true, s);
 }
 
 // defer: tile_defer_bytes(np) bytes; items_ws: tile_items_bytes(g, np, false)
@@ -1245,7 +1383,7 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   a.xbn = xbn;
   a.u0 = u0;
   a.ub0 = ub0;
-  pt_status st = launch_gather(g, a, dtype, TILE_RK2_BWD_GRAD, defer, items_ws, s);
+  pt_status st = launch_gather(g, a, dtype, TILE_RK2_BWD_GRAD, defer, items_ws, false, s);
   if (st != PT_OK || !gcoeff) return st;
   TileArgs b = tile_args(g, coeff, ls, np, dt, kScatterSeg);
   b.x = x;
