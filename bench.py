@@ -8,7 +8,14 @@ One step = one pass of the whole path on resident device data:
      coefficient gradient) -> adjoint of the spline solve.
 value = 2 * N_p particle interpolations of (u,v,w) per step / step time.
 
+With --workload tv a step is instead the forward step in a field that changes
+over the step (coefficients recomputed at each Runge-Kutta sub-step):
+  spline solve of the field at t_n -> sort + stage 1 (u^n at x)
+  spline solve of the field at t_n + dt -> stage 2 (u^{n+1} at x*),
+each solve on a second stream, overlapped with the gather stage before it.
+
     python bench.py [--steps K] [--warmup W] [--config c3] [--dtype f32|bf16]
+                    [--workload fwd_adjoint|tv] [--no-overlap]
 """
 import argparse
 import json
@@ -22,6 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("particle-interpolations/s (u,v,w) at 1024^3, 64M particles; "
           "fwd+adjoint step time")
+METRIC_TV = ("particle-interpolations/s (u,v,w) at 1024^3, 64M particles; "
+             "forward step with the coefficients recomputed at each RK sub-step")
 HBM_PEAK_GBS = 8000.0
 
 CONFIGS = {
@@ -39,7 +48,8 @@ def log(*a):
 
 
 KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold", "sort_keys",
-           "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter")
+           "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter",
+           "tile_tv_stage1", "tile_tv_stage2")
 
 
 def key_bytes(n):
@@ -67,6 +77,10 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step):
         # all colours of one step together: the FP32 gradient read and
         # written once, x, u0, lambda, ub0 read once
         "tile_scatter": (3 * p3 * 4 * 2 + np_ * 72) / launches_per_step,
+        # x in, x (sorted order) and u^n out; field once
+        "tile_tv_stage1": 3 * p3 * cb + np_ * 60,
+        # x and u^n in, x out; field once
+        "tile_tv_stage2": 3 * p3 * cb + np_ * 60,
     }
     return per_step[kernel]
 
@@ -150,6 +164,140 @@ def cpu_baseline(n_full, np_full, clustered):
             "ms_per_step_est": 1e3 * t_step}
 
 
+def cpu_baseline_tv(n_full, np_full, clustered):
+    """FP64 oracle on a bounded sample of the time-varying step: two spline
+    solves on a 512^3 grid, and sort + the two-field Heun step for 2^24
+    particles, each scaled linearly to the full grid and particle count."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    ns, nps = 512, 2 ** 24
+    fa = synth.spectral_field_torch(ns, ns // 3, seed=0, device="cuda:0").double().cpu().numpy()
+    fb = synth.spectral_field_torch(ns, ns // 3, seed=1, device="cuda:0").double().cpu().numpy()
+    pos = synth.clustered_particles_np(nps) if clustered else synth.uniform_particles_np(nps, seed=1)
+    g = oracle.Grid(ns)
+    dt = synth.cfl_dt(max(np.abs(fa).max(), np.abs(fb).max()), ns)
+    t0 = time.perf_counter()
+    ca = oracle.spline_coeffs(fa)
+    cb = oracle.spline_coeffs(fb)
+    t1 = time.perf_counter()
+    ps, _, _ = oracle.sort_particles(g, pos, 32, 32)
+    oracle.rk2_step_tv(g, ca, cb, ps, dt)
+    t2 = time.perf_counter()
+    t_step = (t1 - t0) * (n_full / ns) ** 3 + (t2 - t1) * (np_full / nps)
+    return {"value": 2.0 * np_full / t_step, "unit": "particle-interpolations/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle: two spline solves on a {ns}^3 grid "
+                       f"(x{(n_full / ns) ** 3:.0f} to {n_full}^3) and sort + two-field Heun "
+                       f"step for {nps} {'clustered' if clustered else 'uniform'} particles "
+                       f"(x{np_full / nps:.0f} to {np_full}); sample took {t2 - t0:.1f} s"),
+            "ms_per_step_est": 1e3 * t_step}
+
+
+def kernel_stats(B, steps):
+    out = {}
+    for k in KERNELS:
+        ms, nl = B.pt_timing_read(k)
+        if nl:
+            out[k] = {"ms_per_step": ms / steps, "launches_per_step": nl / steps,
+                      "avg_launch_ms": ms / nl}
+    return out
+
+
+def roofline(kstats, n, np_, cb, config, dtype, clustered):
+    dom = max(kstats, key=lambda k: kstats[k]["ms_per_step"])
+    bpl = launch_bytes(dom, n, np_, cb, kstats[dom]["launches_per_step"])
+    achieved = bpl / (kstats[dom]["avg_launch_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(dom, config, dtype, clustered),
+            "algorithmic_bytes_per_launch": bpl}
+
+
+def run_tv(args, torch, pt, B, synth, n, np_, kmax, clustered, desc, cdt, cb):
+    """Forward steps in a field that changes over the step: per step two
+    spline solves (fields at t_n and t_n + dt) and the two gather stages; each
+    solve runs on a second stream while the gather stage before it runs."""
+    dev = torch.device("cuda:0")
+    g = pt.Grid(n)
+    fa = synth.spectral_field_torch(n, kmax, seed=0, device=dev)
+    fb = synth.spectral_field_torch(n, kmax, seed=1, device=dev)
+    dt = synth.cfl_dt(max(float(fa.abs().max()), float(fb.abs().max())), n)
+    pos = (synth.clustered_particles_torch(np_, sigma=0.1, device=dev) if clustered
+           else synth.uniform_particles_torch(np_, seed=1, device=dev))
+    ids = torch.arange(np_, dtype=torch.int32, device=dev)
+    ca = torch.empty(g.padded_shape, dtype=cdt, device=dev)
+    cbuf = torch.empty(g.padded_shape, dtype=cdt, device=dev)
+    u_n = torch.empty((3, np_), dtype=torch.float32, device=dev)
+    ws_sp = pt.workspace(B.PT_OP_SPLINE, g, 0, cdt, dev)
+    ws = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
+    main_s = torch.cuda.current_stream()
+    side = torch.cuda.Stream() if not args.no_overlap else main_s
+    torch.cuda.synchronize()
+    log(f"[bench] tv inputs ready: dt={dt:.3e}, mem={torch.cuda.memory_allocated() / 2**30:.1f} GiB")
+    # the field at t_n of the first step
+    B.pt_spline_coeffs(g, fa, ca, ws_sp)
+    ev_a, ev_b, ev_s1, ev_s2 = (torch.cuda.Event() for _ in range(4))
+    ev_a.record(main_s)   # ca holds the coefficients at t_n
+    ev_s2.record(main_s)  # cbuf is free
+
+    def step():
+        # side: coefficients of the field at t_n + dt, while stage 1 runs
+        side.wait_event(ev_s2)
+        B.pt_spline_coeffs(g, fb, cbuf, ws_sp, stream=side)
+        ev_b.record(side)
+        main_s.wait_event(ev_a)
+        B.pt_rk2_stage1(g, ca, pos, ids, True, u_n, ws)
+        ev_s1.record(main_s)
+        main_s.wait_event(ev_b)
+        B.pt_rk2_stage2(g, cbuf, dt, pos, u_n, True, ws)
+        ev_s2.record(main_s)
+        # side: the next step's field at t_n, once stage 1 no longer reads ca
+        side.wait_event(ev_s1)
+        B.pt_spline_coeffs(g, fa, ca, ws_sp, stream=side)
+        ev_a.record(side)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+    for k in KERNELS:
+        B.pt_timing_read(k)
+    B.pt_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log(f"[bench] timed step {i + 1}/{args.steps} issued")
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    status = B.pt_last_device_error()
+    if status != 0:
+        raise RuntimeError(f"device error flag set: {B.status_string(status)}")
+    kstats = kernel_stats(B, args.steps)
+    B.pt_timing_enable(False)
+    out = {
+        "metric": METRIC_TV, "value": 2.0 * np_ / (ms_step * 1e-3),
+        "unit": "particle-interpolations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": desc + f", {args.dtype} coefficients, FP64 positions, Heun step "
+                   "with the coefficients of the field at t_n (predictor) and t_n+dt "
+                   "(corrector) recomputed every step, cell sort every step"
+                   + ("" if args.no_overlap else ", solves overlapped on a second stream"),
+                   "grid": n, "particles": np_, "kmax": kmax, "dt": dt,
+                   "coeff_dtype": args.dtype, "overlap": not args.no_overlap},
+        "kernels": kstats,
+        "roofline": roofline(kstats, n, np_, cb, args.config + "_tv", args.dtype, clustered),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline_tv(n, np_, clustered)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +306,9 @@ def main():
     ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="fwd_adjoint", choices=["fwd_adjoint", "tv"])
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="tv: run the solves on the main stream (no overlap)")
     ap.add_argument("--uniform", action="store_true",
                     help="uniform particles instead of the configuration's distribution")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -197,6 +348,9 @@ def main():
     g = pt.Grid(n)
 
     log(f"[bench] config {args.config}: {desc}; coefficients {args.dtype}")
+    if args.workload == "tv":
+        run_tv(args, torch, pt, B, synth, n, np_, kmax, clustered, desc, cdt, cb)
+        return
     field = synth.spectral_field_torch(n, kmax, seed=0, device=dev)
     umax = float(field.abs().max())
     dt = synth.cfl_dt(umax, n)
@@ -268,17 +422,8 @@ def main():
     per = {k: acc[k] / args.steps for k in names}
     value = 2.0 * np_ / (ms_step * 1e-3)
 
-    kstats = {}
-    for k in KERNELS:
-        ms, nl = B.pt_timing_read(k)
-        if nl:
-            kstats[k] = {"ms_per_step": ms / args.steps, "launches_per_step": nl / args.steps,
-                         "avg_launch_ms": ms / nl}
+    kstats = kernel_stats(B, args.steps)
     B.pt_timing_enable(False)
-    dom = max(kstats, key=lambda k: kstats[k]["ms_per_step"])
-    bpl = launch_bytes(dom, n, np_, cb, kstats[dom]["launches_per_step"])
-    achieved = bpl / (kstats[dom]["avg_launch_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(dom, args.config, args.dtype, clustered)
     out = {
         "metric": METRIC, "value": value, "unit": "particle-interpolations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -289,9 +434,7 @@ def main():
                    "kmax": kmax, "dt": dt, "coeff_dtype": args.dtype},
         "breakdown_ms": per,
         "kernels": kstats,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes_per_launch": bpl},
+        "roofline": roofline(kstats, n, np_, cb, args.config, args.dtype, clustered),
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")

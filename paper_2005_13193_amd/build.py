@@ -24,6 +24,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wno-unused-command-line-argument",
+    # keep single-lane counter draws as plain atomics: the wave-wide rewrite
+    # needs the returned value at once, which stalls the wave on every memory
+    # operation it has in flight
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

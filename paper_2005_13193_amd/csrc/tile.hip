@@ -253,45 +253,98 @@ __device__ __forceinline__ void load_pdata(const TileArgs& a, int64_t p, bool ok
   }
 }
 
-__device__ __forceinline__ void defer_particle(int* count, int32_t* list, int64_t np, int p) {
-  const int i = atomicAdd(count, 1);
-  if ((int64_t)i < np) list[i] = p;
+// Outputs of one particle, held in registers until the wave's next flush.
+// Stores are issued only right after the wave has waited for all its
+// memory operations: a store still in flight makes every later wait for a
+// load a wait for everything, including the loads just issued for the next
+// pass, so stores must not sit between the loads and their use.
+struct Pend {
+  int64_t off;  // c * np + p for lane c < 3 of the quad, or -1
+  double d;     // x_out (forward modes) or dL/dx_n (backward)
+  float f0, f1; // stage 1: u_n; backward: u0, ub0
+  int defer;    // quad lane 0: particle to redo from global memory, or -1
+};
+
+// Deferred particles of one flush get list slots from one counter draw per
+// wave; the returned base is used at the next flush, after the wave's next
+// full wait, so the draw never stalls the wave.
+struct DeferBatch {
+  uint64_t mask;  // lanes with a particle to defer
+  int leader;     // lane that drew the slots
+  int base;       // first slot (valid in the leader lane)
+  int part;       // this lane's particle
+};
+
+template <int MODE>
+__device__ __forceinline__ void flush_pend(const TileArgs& a, Pend* o, DeferBatch* db, int* lerr) {
+  const int64_t np = a.np;
+  const int lane64 = threadIdx.x & 63;
+  if (db->mask) {
+    const int base = __shfl(db->base, db->leader, 64);
+    const int rank = __popcll(db->mask & ((1ull << lane64) - 1ull));
+    if (db->part >= 0 && (int64_t)(base + rank) < np) ((int32_t*)a.defer)[base + rank] = db->part;
+  }
+  if (o->off >= 0) {
+    if (MODE == TILE_RK2_BWD_GRAD) {
+      a.xbn[o->off] = o->d;
+      a.u0[o->off] = o->f0;
+      a.ub0[o->off] = o->f1;
+    } else {
+      if (MODE == TILE_TV_STAGE1) a.u0[o->off] = o->f0;
+      a.x_out[o->off] = o->d;
+    }
+  }
+  if (*lerr) {
+    *a.err = 1;
+    *lerr = 0;
+  }
+  const uint64_t m = __ballot(o->defer >= 0);
+  db->mask = m;
+  db->part = o->defer;
+  if (m) {
+    db->leader = __ffsll((unsigned long long)m) - 1;
+    if (lane64 == db->leader) db->base = atomicAdd(a.defer_count, __popcll(m));
+  }
+  o->off = -1;
+  o->defer = -1;
 }
 
 // Both Heun stages (forward), the whole step adjoint (backward) or one stage
-// of the time-varying step of one particle from the ring.  A particle whose
-// predictor point is not resident is deferred to the cleanup kernel, which
-// redoes it from global memory.
+// of the time-varying step of one particle from the ring, into o.  A particle
+// whose predictor point is not resident is deferred to the cleanup kernel,
+// which redoes it from global memory.
 template <typename CT, int MODE>
 __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t* ring,
                                               const PData& d, int X0, int Y0, int zz, int lane,
-                                              float* umax) {
+                                              float* umax, Pend* o, int* lerr) {
   const GridDev& g = a.g;
   const int64_t np = a.np, p = d.p;
   const double* xn = d.x;
   // resident cells: layers zz-1 .. zz+kSlab (planes zz-1 .. zz+5)
-  const Pt qn = locate_pt<0>(g, xn, X0, Y0, zz - 1, zz + kSlab, a.err);
+  const Pt qn = locate_pt<0>(g, xn, X0, Y0, zz - 1, zz + kSlab, lerr);
   if (!qn.in_ring) {  // cannot happen for a correctly sorted particle; kept safe
-    if (lane == 0) defer_particle(a.defer_count, (int32_t*)a.defer, np, d.p);
+    if (lane == 0) o->defer = d.p;
     return;
   }
+  // lane c < 3 keeps component c (selects, not indexing: register arrays
+  // indexed by a lane-dependent value would live in scratch memory)
   if (MODE == TILE_TV_STAGE1) {
     // u^n at x; the positions are written back in the sorted order
     float u0[12];
     eval_ring<CT, false>(ring, g, qn, X0, Y0, lane, u0);
     if (lane < 3) {
-      const int c = lane;
-      a.u0[c * np + p] = c == 0 ? u0[0] : c == 1 ? u0[1] : u0[2];
-      a.x_out[c * np + p] = c == 0 ? xn[0] : c == 1 ? xn[1] : xn[2];
+      o->off = lane * np + p;
+      o->f0 = lane == 0 ? u0[0] : lane == 1 ? u0[1] : u0[2];
+      o->d = lane == 0 ? xn[0] : lane == 1 ? xn[1] : xn[2];
     }
   } else if (MODE == TILE_TV_STAGE2) {
     // x* = x + dt u^n (from stage 1), u^{n+1}(x*) from the ring
     double xs[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)d.un[c];
-    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
+    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
     if (!qs.in_ring) {
-      if (lane == 0) defer_particle(a.defer_count, (int32_t*)a.defer, np, d.p);
+      if (lane == 0) o->defer = d.p;
       return;
     }
     float u1[12];
@@ -301,7 +354,8 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
       const double x0 = lane == 0 ? xn[0] : lane == 1 ? xn[1] : xn[2];
       const float ua = lane == 0 ? d.un[0] : lane == 1 ? d.un[1] : d.un[2];
       const float ub = lane == 0 ? u1[0] : lane == 1 ? u1[1] : u1[2];
-      a.x_out[lane * np + p] = x0 + h * ((double)ua + (double)ub);
+      o->off = lane * np + p;
+      o->d = x0 + h * ((double)ua + (double)ub);
     }
   } else if (MODE == TILE_RK2_FWD) {
     float u0[12], u1[12];
@@ -309,9 +363,9 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
     double xs[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)u0[c];
-    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
+    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
     if (!qs.in_ring) {
-      if (lane == 0) defer_particle(a.defer_count, (int32_t*)a.defer, np, d.p);
+      if (lane == 0) o->defer = d.p;
       return;
     }
     eval_ring<CT, false>(ring, g, qs, X0, Y0, lane, u1);
@@ -320,7 +374,8 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
       const double x0 = lane == 0 ? xn[0] : lane == 1 ? xn[1] : xn[2];
       const float ua = lane == 0 ? u0[0] : lane == 1 ? u0[1] : u0[2];
       const float ub = lane == 0 ? u1[0] : lane == 1 ? u1[1] : u1[2];
-      a.x_out[lane * np + p] = x0 + h * ((double)ua + (double)ub);
+      o->off = lane * np + p;
+      o->d = x0 + h * ((double)ua + (double)ub);
     }
   } else {
     float on[12], os[12];
@@ -328,9 +383,9 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
     double xs[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)on[c];
-    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
+    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
     if (!qs.in_ring) {
-      if (lane == 0) defer_particle(a.defer_count, (int32_t*)a.defer, np, d.p);
+      if (lane == 0) o->defer = d.p;
       return;
     }
     eval_ring<CT, true>(ring, g, qs, X0, Y0, lane, os);
@@ -351,13 +406,11 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
               (double)(ub0[0] * on[3 + c] + ub0[1] * on[6 + c] + ub0[2] * on[9 + c]);
       *umax = fmaxf(*umax, fmaxf(fabsf(ub0[c]), fabsf(ub1[c])));
     }
-    // lane c < 3 writes component c (selects, not indexing: register arrays
-    // indexed by a lane-dependent value would live in scratch memory)
     if (lane < 3) {
-      const int c = lane;
-      a.xbn[c * np + p] = c == 0 ? xb[0] : c == 1 ? xb[1] : xb[2];
-      a.u0[c * np + p] = c == 0 ? on[0] : c == 1 ? on[1] : on[2];
-      a.ub0[c * np + p] = c == 0 ? ub0[0] : c == 1 ? ub0[1] : ub0[2];
+      o->off = lane * np + p;
+      o->d = lane == 0 ? xb[0] : lane == 1 ? xb[1] : xb[2];
+      o->f0 = lane == 0 ? on[0] : lane == 1 ? on[1] : on[2];
+      o->f1 = lane == 0 ? ub0[0] : lane == 1 ? ub0[1] : ub0[2];
     }
   }
 }
@@ -473,6 +526,12 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
   const int wave = threadIdx.x >> 6;
   const bool loader = wave >= kCompute / 64;
   float umax = 0.0f;  // largest |ub| of this thread's particles (adjoint)
+  Pend pend;
+  pend.off = -1;
+  pend.defer = -1;
+  DeferBatch db;
+  db.mask = 0;
+  int lerr = 0;  // a non-finite position was met
   int col, half_unused, z0, z1, range_k = 0;
   while (next_item(a, &range_k, &col, &half_unused, &z0, &z1)) {
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
@@ -522,24 +581,31 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
         } else {
           const int64_t pb = lst[zs - z0];
           const int64_t pe = lst[min(zs + kSlab, z1) - z0];
-          // passes of kGGroups particles; the data of pass k+1 is loaded
-          // before pass k is processed, into the register set not in use (a
-          // copy between sets would make the wave wait for the loads in
-          // flight)
+          // passes of kGGroups particles.  Each pass starts with a full wait
+          // (the data of this pass was loaded during the previous one), then
+          // stores the previous pass's outputs, then loads the next pass into
+          // the register set not in use (a copy between sets would also make
+          // the wave wait for loads in flight).
           const int npass = (int)((pe - pb + kGGroups - 1) / kGGroups);
           PData sb;
           for (int k = 0; k < npass; k += 2) {  // npass uniform
+            PT_WAIT_VMCNT0();
+            flush_pend<MODE>(a, &pend, &db, &lerr);
             if (k + 1 < npass) {
               const int64_t pn = pb + (int64_t)(k + 1) * kGGroups + grp;
               load_pdata<MODE>(a, pn, pn < pe, &sb);
             }
-            if (pd[half].ok) ring_particle<CT, MODE>(a, ring, pd[half], X0, Y0, zs, lane, &umax);
+            if (pd[half].ok)
+              ring_particle<CT, MODE>(a, ring, pd[half], X0, Y0, zs, lane, &umax, &pend, &lerr);
             if (k + 1 >= npass) break;
+            PT_WAIT_VMCNT0();
+            flush_pend<MODE>(a, &pend, &db, &lerr);
             if (k + 2 < npass) {
               const int64_t pn = pb + (int64_t)(k + 2) * kGGroups + grp;
               load_pdata<MODE>(a, pn, pn < pe, &pd[half]);
             }
-            if (sb.ok) ring_particle<CT, MODE>(a, ring, sb, X0, Y0, zs, lane, &umax);
+            if (sb.ok)
+              ring_particle<CT, MODE>(a, ring, sb, X0, Y0, zs, lane, &umax, &pend, &lerr);
           }
           prefetch(half, s + 2);
         }
@@ -549,6 +615,13 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
   }
   if (loader) PT_WAIT_VMCNT0();  // no copy into the ring outlives the item
   }  // items
+  if (!loader) {
+    // the last outputs, then the list slots of the last deferred batch
+    PT_WAIT_VMCNT0();
+    flush_pend<MODE>(a, &pend, &db, &lerr);
+    PT_WAIT_VMCNT0();
+    flush_pend<MODE>(a, &pend, &db, &lerr);
+  }
   if (MODE == TILE_RK2_BWD_GRAD) {
     // block maximum of |ub| for the fixed-point scale of the scatter
     float* smax = (float*)(lst + a.seg_len + 4);
