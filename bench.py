@@ -166,14 +166,14 @@ def cpu_baseline(n_full, np_full, clustered):
 
 def cpu_baseline_tv(n_full, np_full, clustered):
     """FP64 oracle on a bounded sample of the time-varying step: two spline
-    solves on a 512^3 grid, and sort + the two-field Heun step for 2^24
+    solves on a 512^3 grid, and sort + the two-field Heun step for 2^25
     particles, each scaled linearly to the full grid and particle count."""
     import numpy as np
 
     import oracle
     import synth
 
-    ns, nps = 512, 2 ** 24
+    ns, nps = 512, 2 ** 25
     fa = synth.spectral_field_torch(ns, ns // 3, seed=0, device="cuda:0").double().cpu().numpy()
     fb = synth.spectral_field_torch(ns, ns // 3, seed=1, device="cuda:0").double().cpu().numpy()
     pos = synth.clustered_particles_np(nps) if clustered else synth.uniform_particles_np(nps, seed=1)

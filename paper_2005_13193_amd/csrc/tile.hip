@@ -805,13 +805,46 @@ __device__ __forceinline__ void load_sdata(const TileArgs& a, int64_t p, bool ok
   }
 }
 
-__device__ __forceinline__ void defer_stencil(const TileArgs& a, int64_t p, int stage) {
-  const int i = atomicAdd(a.defer_count, 1);
-  if ((int64_t)i < 2 * a.np) a.defer[i] = (uint32_t)(2 * p + stage);
+// Deferred stencils (2 p + stage) collect in a small LDS list that the
+// workgroup copies to the global list at slab ends (see dump_deferred): a
+// global counter draw or store here would make the wave's next waits for its
+// particle loads wait for everything in flight.  Past the LDS capacity an
+// entry goes straight to the global list.
+constexpr int kSDefCap = 512;
+
+__device__ __forceinline__ void defer_stencil(const TileArgs& a, int* sdef_n, uint32_t* sdef,
+                                              int64_t p, int stage) {
+  const uint32_t e = (uint32_t)(2 * p + stage);
+  const int k = atomicAdd(sdef_n, 1);
+  if (k < kSDefCap) {
+    sdef[k] = e;
+  } else {
+    const int i = atomicAdd(a.defer_count, 1);
+    if ((int64_t)i < 2 * a.np) a.defer[i] = e;
+    PT_WAIT_VMCNT0();  // leave no store in flight on this rare path
+  }
+}
+
+// Copies the LDS list to the global list when it is at least half full (or
+// always, with force) and empties it.  Called by the whole workgroup after a
+// barrier; ends with one.
+__device__ __forceinline__ void dump_deferred(const TileArgs& a, int* sdef_n, uint32_t* sdef,
+                                              int* s_base, bool force) {
+  const int n = min(*sdef_n, kSDefCap);
+  if (n == 0 || (!force && n < kSDefCap / 2)) return;  // uniform
+  if (threadIdx.x == 0) *s_base = atomicAdd(a.defer_count, n);
+  __syncthreads();
+  const int64_t base = *s_base;
+  for (int i = threadIdx.x; i < n; i += kSTB)
+    if (base + i < 2 * a.np) a.defer[base + i] = sdef[i];
+  __syncthreads();
+  if (threadIdx.x == 0) *sdef_n = 0;
+  __syncthreads();
 }
 
 __device__ __forceinline__ void scatter_one(const TileArgs& a, long long* ring, const SData& d,
-                                            int X0, int Y0, int zz, int lane, float scale) {
+                                            int X0, int Y0, int zz, int lane, float scale,
+                                            int* sdef_n, uint32_t* sdef, int* lerr) {
   const GridDev& g = a.g;
   double xs[3];
   float s0[3], s1[3];
@@ -823,22 +856,22 @@ __device__ __forceinline__ void scatter_one(const TileArgs& a, long long* ring, 
   }
   // cells with tile-local index in [0, kTileX + 2) x [0, kTileY/2 + 2) and
   // layers zz-1 .. zz+2 have their stencils inside the tile and the ring
-  Pt qn = locate_pt<0>(g, d.x, X0, Y0, zz - 1, zz + kSlab, a.err);
+  Pt qn = locate_pt<0>(g, d.x, X0, Y0, zz - 1, zz + kSlab, lerr);
   {
     const int lx = qn.a - X0, ly = qn.b - Y0;
     qn.in_ring = lx >= 0 && lx < kTileX + 2 && ly >= 0 && ly < kTileY / 2 + 2 &&
                  qn.c >= zz - 1 && qn.c <= zz + kSlab;
   }
   if (qn.in_ring) scatter_ring(ring, qn, X0, Y0, lane, s0);
-  else if (lane == 0) defer_stencil(a, d.p, 0);
-  Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, a.err);
+  else if (lane == 0) defer_stencil(a, sdef_n, sdef, d.p, 0);
+  Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
   {
     const int lx = qs.a - X0, ly = qs.b - Y0;
     qs.in_ring = lx >= 0 && lx < kTileX + 2 && ly >= 0 && ly < kTileY / 2 + 2 &&
                  qs.c >= zz - 1 && qs.c <= zz + kSlab;
   }
   if (qs.in_ring) scatter_ring(ring, qs, X0, Y0, lane, s1);
-  else if (lane == 0) defer_stencil(a, d.p, 1);
+  else if (lane == 0) defer_stencil(a, sdef_n, sdef, d.p, 1);
 }
 
 __device__ __forceinline__ float scatter_scale(const TileArgs& a) {
@@ -887,8 +920,13 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   extern __shared__ long long ssm[];
   long long* ring = ssm;
   int* lst = (int*)(ssm + kSRing * kSSlot);  // [2 (nl + 1)] half-layer starts
+  int* sdef_n = lst + 2 * (kScatterSeg + 2);  // LDS deferred list: length, base, entries
+  int* s_base = sdef_n + 1;
+  uint32_t* sdef = (uint32_t*)(sdef_n + 4);
   const GridDev& g = a.g;
   const float scale = scatter_scale(a), inv_scale = 1.0f / scale;
+  int lerr = 0;  // a non-finite position was met
+  if (threadIdx.x == 0) *sdef_n = 0;  // published by the barrier in next_item
   int col, half, z0, z1, range_k = 0;
   while (next_item(a, &range_k, &col, &half, &z0, &z1)) {
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
@@ -955,16 +993,21 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
         for (int64_t k = 0; k < npass; k += 2) {
           const int64_t v = grp * npass + k;
           if (k + 1 < npass) load_sdata(a, vidx(v + 1, r0, n0, r1), v + 1 < n, &sb);
-          if (sd[hf].ok) scatter_one(a, ring, sd[hf], X0, Y0, zs, lane, scale);
+          if (sd[hf].ok) scatter_one(a, ring, sd[hf], X0, Y0, zs, lane, scale, sdef_n, sdef, &lerr);
           if (k + 1 >= npass) break;
           if (k + 2 < npass) load_sdata(a, vidx(v + 2, r0, n0, r1), v + 2 < n, &sd[hf]);
-          if (sb.ok) scatter_one(a, ring, sb, X0, Y0, zs, lane, scale);
+          if (sb.ok) scatter_one(a, ring, sb, X0, Y0, zs, lane, scale, sdef_n, sdef, &lerr);
         }
         __syncthreads();
+        // Slab end: the only place with global stores.  Wait for everything
+        // first (the loads for the next slab were issued a slab ago), so that
+        // afterwards only these stores and the new prefetch are in flight.
+        PT_WAIT_VMCNT0();
         // planes zs-1 and zs are complete: later particles sit in layers
         // >= zs+2 and their predictor points in layers >= zs+1
         flush_splane(a, ring, X0, Y0, zs - 1, gv[hf][0], inv_scale);
         flush_splane(a, ring, X0, Y0, zs, gv[hf][1], inv_scale);
+        dump_deferred(a, sdef_n, sdef, s_base, false);
         prefetch(hf, s + 2);
         __syncthreads();
       }
@@ -980,6 +1023,9 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
     __syncthreads();
   }
   }  // items
+  __syncthreads();
+  dump_deferred(a, sdef_n, sdef, s_base, true);
+  if (lerr) *a.err = 1;
 }
 
 // Stencils that did not fit their column's tile, added with atomics once all
@@ -1473,7 +1519,8 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   hipLaunchKernelGGL(zero_defer_count, dim3(1), dim3(1), 0, s, b.defer_count);
   PT_LAUNCH_CHECK();
   const size_t lds =
-      sizeof(long long) * (size_t)kSRing * kSSlot + sizeof(int) * 2 * (b.seg_len + 2);
+      sizeof(long long) * (size_t)kSRing * kSSlot + sizeof(int) * 2 * (kScatterSeg + 2) +
+      sizeof(int) * (4 + (size_t)kSDefCap);
   if (!allow_lds(tile_scatter, lds)) return PT_ERR_HIP;
   const unsigned blocks = item_blocks(it.bound);
   for (int color = 0; color < 8; ++color) {
