@@ -14,8 +14,12 @@ over the step (coefficients recomputed at each Runge-Kutta sub-step):
   spline solve of the field at t_n + dt -> stage 2 (u^{n+1} at x*),
 each solve on a second stream, overlapped with the gather stage before it.
 
+With --workload slab a step is the spline solve of one device's z-slab of a
+2048^3 grid split 8 ways (256 planes, z lines solved with open ends over 16
+halo planes per side).
+
     python bench.py [--steps K] [--warmup W] [--config c3] [--dtype f32|bf16]
-                    [--workload fwd_adjoint|tv] [--no-overlap]
+                    [--workload fwd_adjoint|tv|slab] [--no-overlap]
 """
 import argparse
 import json
@@ -29,6 +33,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("particle-interpolations/s (u,v,w) at 1024^3, 64M particles; "
           "fwd+adjoint step time")
+METRIC_SLAB = ("spline coefficient points/s, one 256-plane z-slab (halo 16) of a "
+               "2048^3 grid")
 METRIC_TV = ("particle-interpolations/s (u,v,w) at 1024^3, 64M particles; "
              "forward step with the coefficients recomputed at each RK sub-step")
 HBM_PEAK_GBS = 8000.0
@@ -216,6 +222,81 @@ def roofline(kstats, n, np_, cb, config, dtype, clustered):
             "algorithmic_bytes_per_launch": bpl}
 
 
+def cpu_baseline_slab(points_full):
+    """FP64 oracle spline solve of an 896^3 periodic grid, scaled linearly to
+    the slab's coefficient points."""
+    import oracle
+    import synth
+
+    ns = 896
+    f = synth.spectral_field_torch(ns, ns // 3, seed=0, device="cuda:0").double().cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.spline_coeffs(f)
+    t = time.perf_counter() - t0
+    pts = 3 * (ns + 3) ** 3
+    return {"value": pts / t, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle periodic solve of a {ns}^3 grid ({t:.1f} s), per point",
+            "ms_per_step_est": 1e3 * t * points_full / pts}
+
+
+def run_slab(args, torch, pt, B, synth, cdt, cb):
+    """The spline solve of one device's z-slab: 256 planes of a 2048^3 grid
+    (one of 8), z lines with open ends over 16 halo planes per side."""
+    dev = torch.device("cuda:0")
+    n, nzl, halo = 2048, 256, 16
+    nzi = nzl + 3 + 2 * halo
+    g = pt.Grid(n)
+    # planes -1-halo .. nzl+1+halo (mod n) of the 2048^3 synthetic field
+    full = synth.spectral_field_torch_chunked(n, n // 3, seed=0, device=dev)
+    planes = torch.tensor([(-1 - halo + i) % n for i in range(nzi)], device=dev)
+    field = full.index_select(1, planes).contiguous()
+    del full
+    torch.cuda.empty_cache()
+    out = torch.empty((3, nzl + 3, n + 3, n + 3), dtype=cdt, device=dev)
+    ws = pt.workspace(B.PT_OP_SPLINE_SLAB, g, nzi, cdt, dev)
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        B.pt_spline_coeffs_slab(g, nzl, halo, field, out, ws)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+    for k in KERNELS:
+        B.pt_timing_read(k)
+    B.pt_timing_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        B.pt_spline_coeffs_slab(g, nzl, halo, field, out, ws)
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    kstats = kernel_stats(B, args.steps)
+    B.pt_timing_enable(False)
+    points = 3 * (nzl + 3) * (n + 3) ** 2
+    # algorithmic bytes per launch: z pass reads and writes nzi planes, y
+    # pass nzl + 3 planes in place, x pass reads nzl + 3 planes and writes the
+    # padded output
+    plane = n * n
+    per = {"spline_z": 8 * plane * nzi, "spline_y": 8 * plane * (nzl + 3),
+           "spline_x_pad": 4 * plane * (nzl + 3) + cb * (nzl + 3) * (n + 3) ** 2}
+    dom = max(kstats, key=lambda k: kstats[k]["ms_per_step"])
+    achieved = per[dom] / (kstats[dom]["avg_launch_ms"] * 1e-3) / 1e9
+    out_line = {
+        "metric": METRIC_SLAB, "value": points / (ms_step * 1e-3), "unit": "points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"z-slab of a 2048^3 grid: {nzl} planes + 2 x {halo} halo planes, "
+                   f"{args.dtype} coefficients", "grid": n, "slab_planes": nzl, "halo": halo},
+        "kernels": kstats,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, "slab", args.dtype, False),
+                     "algorithmic_bytes_per_launch": per[dom]},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a bounded sample")
+        out_line["cpu_baseline"] = cpu_baseline_slab(points)
+    print(json.dumps(out_line), flush=True)
+
+
 def run_tv(args, torch, pt, B, synth, n, np_, kmax, clustered, desc, cdt, cb):
     """Forward steps in a field that changes over the step: per step two
     spline solves (fields at t_n and t_n + dt) and the two gather stages; each
@@ -306,7 +387,7 @@ def main():
     ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="fwd_adjoint", choices=["fwd_adjoint", "tv"])
+    ap.add_argument("--workload", default="fwd_adjoint", choices=["fwd_adjoint", "tv", "slab"])
     ap.add_argument("--no-overlap", action="store_true",
                     help="tv: run the solves on the main stream (no overlap)")
     ap.add_argument("--uniform", action="store_true",
@@ -350,6 +431,9 @@ def main():
     log(f"[bench] config {args.config}: {desc}; coefficients {args.dtype}")
     if args.workload == "tv":
         run_tv(args, torch, pt, B, synth, n, np_, kmax, clustered, desc, cdt, cb)
+        return
+    if args.workload == "slab":
+        run_slab(args, torch, pt, B, synth, cdt, cb)
         return
     field = synth.spectral_field_torch(n, kmax, seed=0, device=dev)
     umax = float(field.abs().max())

@@ -81,11 +81,13 @@ enum {
   PT_OP_SORT = 1,       /* pt_sort_particles */
   PT_OP_RK2 = 2,        /* pt_rk2_step (with or without sort) */
   PT_OP_SPLINE_BWD = 3, /* pt_spline_coeffs_bwd */
-  PT_OP_RK2_BWD = 4     /* pt_rk2_step_bwd (with or without sort) */
+  PT_OP_RK2_BWD = 4,    /* pt_rk2_step_bwd (with or without sort) */
+  PT_OP_SPLINE_SLAB = 5 /* pt_spline_coeffs_slab; np = input planes nzl + 3 + 2 halo */
 };
 
 /* Bytes of workspace the operation needs for this grid, coefficient dtype
- * and particle count (np ignored for the spline operations).  The result is a
+ * and particle count (np ignored for PT_OP_SPLINE and PT_OP_SPLINE_BWD; for
+ * PT_OP_SPLINE_SLAB it is the slab's input plane count).  The result is a
  * multiple of 256.  Returns PT_ERR_ARG for an unknown op. */
 pt_status pt_workspace_bytes(int op, const pt_grid *grid, pt_dtype dtype, int64_t np,
                              size_t *bytes);
@@ -112,6 +114,27 @@ pt_status pt_key_layout(const pt_grid *grid, int32_t *tile_x, int32_t *tile_y,
 pt_status pt_spline_coeffs(const pt_grid *grid, const float *field, void *coeff,
                            pt_dtype dtype, void *ws, size_t ws_bytes,
                            hipStream_t stream);
+
+/* Operation 1 for one z-slab of a periodic grid: the share of one device
+ * when the grid is split in z, as the paper's domain decomposition splits it
+ * across processes (Sec. 3).  The z lines are solved with open ends over the
+ * slab plus `halo` field planes on each side: the inverse of the periodic
+ * 1-4-1 system decays like |z1|^d (z1 = sqrt(3) - 2, |z1| = 0.268) with the
+ * distance d, so the result differs from the periodic solve by a relative
+ * amount of order |z1|^halo (halo >= 14 puts it below FP32 rounding).  The x
+ * and y lines are whole and solved periodically, as by pt_spline_coeffs.
+ *   grid   the whole grid (nx, ny as stored here; nz = all planes)
+ *   nzl    planes of the slab, 1 <= nzl <= nz;  halo 1 .. 64
+ *   field  in   float [3][nzl + 3 + 2 halo][ny][nx]: the periodic field's
+ *               planes z0-1-halo .. z0+nzl+1+halo (indices mod nz), for a
+ *               slab starting at plane z0
+ *   coeff  out  [3][nzl+3][ny+3][nx+3] of `dtype`, x and y padded as by
+ *               pt_spline_coeffs; padded plane P holds plane z0-1+P
+ *   ws          >= pt_workspace_bytes(PT_OP_SPLINE_SLAB, grid, dtype,
+ *               nzl + 3 + 2 halo) bytes */
+pt_status pt_spline_coeffs_slab(const pt_grid *grid, int32_t nzl, int32_t halo,
+                                const float *field, void *coeff, pt_dtype dtype, void *ws,
+                                size_t ws_bytes, hipStream_t stream);
 
 /* Sec. 2.2 and Sec. 3: map each position to its cell and order particles by
  * cell.  Per axis, in double precision with no fused operations,

@@ -75,6 +75,20 @@ def spline_coeffs(grid, field, dtype=torch.float32, out=None, ws=None):
     return out
 
 
+def spline_coeffs_slab(grid, field_halo, nzl, halo, dtype=torch.float32, out=None, ws=None):
+    """Coefficients of planes z0-1 .. z0+nzl+1 of the periodic field from its
+    planes z0-1-halo .. z0+nzl+1+halo (field_halo [3][nzl+3+2 halo][ny][nx])."""
+    field_halo = field_halo.contiguous()
+    if out is None:
+        out = torch.empty((3, nzl + 3, grid.ny + 3, grid.nx + 3), dtype=dtype,
+                          device=field_halo.device)
+    if ws is None:
+        ws = workspace(_b.PT_OP_SPLINE_SLAB, grid, nzl + 3 + 2 * halo, out.dtype,
+                       field_halo.device)
+    _b.pt_spline_coeffs_slab(grid, nzl, halo, field_halo, out, ws)
+    return out
+
+
 def spline_coeffs_bwd(grid, g_coeff, out=None, ws=None):
     g_coeff = g_coeff.contiguous()
     if out is None:

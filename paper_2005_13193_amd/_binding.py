@@ -31,8 +31,10 @@ PT_OP_SORT = 1
 PT_OP_RK2 = 2
 PT_OP_SPLINE_BWD = 3
 PT_OP_RK2_BWD = 4
+PT_OP_SPLINE_SLAB = 5
 
-EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_sort_particles",
+EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_spline_coeffs_slab",
+           "pt_sort_particles",
            "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_rk2_stage1", "pt_rk2_stage2",
            "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
@@ -63,6 +65,8 @@ def _load():
         "pt_workspace_bytes": [ctypes.c_int, g, ctypes.c_int, i64, ctypes.POINTER(sz)],
         "pt_key_layout": [g, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "pt_spline_coeffs": [g, vp, vp, ctypes.c_int, vp, sz, vp],
+        "pt_spline_coeffs_slab": [g, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int, vp,
+                                  sz, vp],
         "pt_sort_particles": [g, i64, vp, vp, vp, vp, vp, sz, vp],
         "pt_interp_uvw": [g, vp, ctypes.c_int, i64, vp, vp, vp],
         "pt_interp_grad": [g, vp, ctypes.c_int, i64, vp, vp, vp],
@@ -159,6 +163,16 @@ def pt_spline_coeffs(grid, field, coeff, ws, stream=None):
            LIB.pt_spline_coeffs(ctypes.byref(_grid(grid)), _ptr(field), _ptr(coeff),
                                 _dtype_code(coeff), _ptr(ws), ws.numel() * ws.element_size(),
                                 _stream(stream)))
+
+
+def pt_spline_coeffs_slab(grid, nzl, halo, field, coeff, ws, stream=None):
+    nzi = nzl + 3 + 2 * halo
+    _need(field, torch.float32, (3, nzi, grid.ny, grid.nx), "field")
+    _need(coeff, None, (3, nzl + 3, grid.ny + 3, grid.nx + 3), "coeff")
+    _check("pt_spline_coeffs_slab",
+           LIB.pt_spline_coeffs_slab(ctypes.byref(_grid(grid)), int(nzl), int(halo), _ptr(field),
+                                     _ptr(coeff), _dtype_code(coeff), _ptr(ws),
+                                     ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def pt_spline_coeffs_bwd(grid, g_coeff, g_field, ws, stream=None):

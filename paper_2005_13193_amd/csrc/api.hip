@@ -13,6 +13,9 @@ namespace pt {
 
 // solve.hip
 size_t spline_ws_floats(const pt_grid* g, pt_dtype dtype);
+size_t spline_slab_ws_floats(const pt_grid* g, int nzl, int W);
+pt_status spline_slab_fwd(const pt_grid* g, int nzl, int W, const float* field, void* coeff,
+                          pt_dtype dtype, float* ws, hipStream_t s);
 pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype dtype, float* ws,
                      hipStream_t s);
 pt_status spline_bwd(const pt_grid* g, const float* gcoeff, float* gfield, float* ws,
@@ -210,6 +213,7 @@ pt_status pt_workspace_bytes(int op, const pt_grid* grid, pt_dtype dtype, int64_
   PT_TRY(check_grid(grid));
   PT_TRY(check_dtype(dtype));
   if (op != PT_OP_SPLINE && op != PT_OP_SPLINE_BWD) PT_TRY(check_np(np));
+  if (op == PT_OP_SPLINE_SLAB && (np < 6 || np > 8192)) return PT_ERR_SIZE;
   const size_t n3 = (size_t)grid->nx * grid->ny * grid->nz;
   switch (op) {
     case PT_OP_SPLINE: *bytes = a256(4 * spline_ws_floats(grid, dtype)); break;
@@ -217,6 +221,8 @@ pt_status pt_workspace_bytes(int op, const pt_grid* grid, pt_dtype dtype, int64_
     case PT_OP_SORT: *bytes = a256(sort_ws_bytes(grid, np)); break;
     case PT_OP_RK2: *bytes = a256(rk2_ws_bytes(grid, np)); break;
     case PT_OP_RK2_BWD: *bytes = a256(rk2_bwd_ws_bytes(grid, np)); break;
+    // np = input planes of the slab, nzl + 3 + 2 W
+    case PT_OP_SPLINE_SLAB: *bytes = a256(4 * spline_slab_ws_floats(grid, (int)np - 3, 0)); break;
     default: return PT_ERR_ARG;
   }
   return PT_OK;
@@ -241,6 +247,22 @@ pt_status pt_spline_coeffs(const pt_grid* grid, const float* field, void* coeff,
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
   PT_TRY(ready());
   return spline_fwd(grid, field, coeff, dtype, (float*)ws, stream);
+}
+
+pt_status pt_spline_coeffs_slab(const pt_grid* grid, int32_t nzl, int32_t halo,
+                                const float* field, void* coeff, pt_dtype dtype, void* ws,
+                                size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  if (nzl < 1 || nzl > grid->nz || halo < 1 || halo > 64) return PT_ERR_SIZE;
+  const int64_t nzi = (int64_t)nzl + 3 + 2 * (int64_t)halo;
+  if (nzi > 8192) return PT_ERR_UNSUPPORTED;
+  if (!field || !coeff) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_SPLINE_SLAB, grid, dtype, nzi, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  return spline_slab_fwd(grid, nzl, halo, field, coeff, dtype, (float*)ws, stream);
 }
 
 pt_status pt_spline_coeffs_bwd(const pt_grid* grid, const float* g_coeff, float* g_field, void* ws,

@@ -33,6 +33,13 @@
 //    holds a contiguous chunk and the chunk maps are combined by a wave scan.
 //    Variants write all padded copies of the row (last forward pass) or sum
 //    the padded copies of the row (first adjoint pass).
+//
+// Slab form.  When the grid is split in z (one device's share), the z lines
+// of a slab are solved with open ends over the slab plus W field planes on
+// each side: the periodic inverse decays like |z1|^d, so the recursions
+// started from zero W planes away reach the slab with a relative error of
+// order |z1|^W, below FP32 rounding for W >= 14.  The x and y solves are
+// whole lines and stay periodic.
 #include <math.h>
 
 #include <type_traits>
@@ -126,6 +133,8 @@ struct RowArgs {
   int q;       // points per lane chunk, ceil(nx / 64)
   int nrows;   // ny * nz
   int pitch;   // LDS floats per wave
+  int zpad;    // PAD_*: 1 = rows are grid planes (write z + 1 and its wrapped
+               // copy); 0 = rows are already padded planes (write z only)
 };
 
 // LDS slot of row element p: one pad word per 16 keeps the chunk view
@@ -285,8 +294,8 @@ __global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
   }
   if (pad_out) {
     using T = typename std::conditional<MODE == ROW_PAD_F32, float, uint16_t>::type;
-    const int ye = pad_extra(y, a.ny), ze = pad_extra(z, a.nz);
-    const int Ys[2] = {y + 1, ye}, Zs[2] = {z + 1, ze};
+    const int ye = pad_extra(y, a.ny), ze = a.zpad ? pad_extra(z, a.nz) : -1;
+    const int Ys[2] = {y + 1, ye}, Zs[2] = {a.zpad ? z + 1 : z, ze};
     for (int zc = 0; zc < 2; ++zc) {
       if (Zs[zc] < 0) continue;
       for (int yc = 0; yc < 2; ++yc) {
@@ -322,7 +331,9 @@ struct LineArgs {
   int L;          // chunk length
   float a_full;   // z1^L
   float a_last;   // z1^(length of the last, shorter chunk)
-  float closure;  // 1 / (1 - z1^na)
+  float closure;  // 1 / (1 - z1^na); 1 for open lines
+  int open;       // 1: lines with open ends (recursions start from zero at
+                  // the ends), 0: periodic lines
   int bx0;        // first x-block of the launch
 };
 
@@ -362,7 +373,8 @@ __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
   __syncthreads();
   {
     float cin = 0.0f, P = 1.0f;
-    for (int j = 1; j <= a.K && P != 0.0f; ++j) {
+    const int jn = a.open ? k : a.K;  // chunks before this one (open: no wrap)
+    for (int j = 1; j <= jn && P != 0.0f; ++j) {
       int kk = k - j;
       if (kk < 0) kk += a.K;
       cin += P * s_e[kk * a.G + xg];
@@ -374,7 +386,8 @@ __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
   __syncthreads();
   {
     float din = 0.0f, R = 1.0f;
-    for (int j = 1; j <= a.K && R != 0.0f; ++j) {
+    const int jn = a.open ? a.K - 1 - k : a.K;
+    for (int j = 1; j <= jn && R != 0.0f; ++j) {
       int kk = k + j;
       if (kk >= a.K) kk -= a.K;
       din += R * s_f[kk * a.G + xg];
@@ -394,11 +407,12 @@ __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
 // ------------------------------------------------------------ launchers ---
 
 static pt_status pass_rows(const float* in, void* out, int nx, int ny, int nz, int mode,
-                           hipStream_t s) {
+                           hipStream_t s, int zpad = 1) {
   RowArgs a;
   a.in = in;
   a.out = out;
   a.nx = nx; a.ny = ny; a.nz = nz;
+  a.zpad = zpad;
   a.q = (nx + 63) / 64;
   a.nrows = ny * nz;
   const int px = nx + 3;
@@ -457,11 +471,12 @@ static bool line_shape(int na, int* Q, int* G, int* waves) {
 
 // axis 1 = y, axis 2 = z; plain layout in and out.
 static pt_status pass_lines(const float* in, float* out, int nx, int ny, int nz, int axis,
-                            hipStream_t s) {
+                            hipStream_t s, int open = 0) {
   LineArgs a;
   a.in = in;
   a.out = out;
   a.nx = nx;
+  a.open = open;
   int nb;
   if (axis == 1) {
     a.na = ny; nb = nz;
@@ -477,7 +492,7 @@ static pt_status pass_lines(const float* in, float* out, int nx, int ny, int nz,
   a.L = (a.na + a.K - 1) / a.K;
   a.a_full = z1_pow(a.L);
   a.a_last = z1_pow(a.na - (a.na / a.L) * a.L);
-  a.closure = (float)(1.0 / (1.0 - (double)z1_pow(a.na)));
+  a.closure = open ? 1.0f : (float)(1.0 / (1.0 - (double)z1_pow(a.na)));
   // Whole chunks everywhere except possibly a last, partial x-block: the
   // FULL kernel takes the whole x-blocks, the general one the rest.
   const int xblocks = (nx + G - 1) / G;
@@ -529,6 +544,37 @@ pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype
     void* o = dtype == PT_F32 ? (void*)((float*)coeff + c * p3)
                               : (void*)((uint16_t*)coeff + c * p3);
     st = pass_rows(t2, o, nx, ny, nz, dtype == PT_F32 ? ROW_PAD_F32 : ROW_PAD_BF16, s);
+    if (st != PT_OK) return st;
+  }
+  return PT_OK;
+}
+
+size_t spline_slab_ws_floats(const pt_grid* g, int nzl, int W) {
+  return (size_t)g->nx * g->ny * (size_t)(nzl + 3 + 2 * W);
+}
+
+// field: planes z0-1-W .. z0+nzl+1+W of the periodic field (nzl + 3 + 2W),
+// coeff: [3][nzl+3][ny+3][nx+3], padded plane P = global plane z0-1+P.
+pt_status spline_slab_fwd(const pt_grid* g, int nzl, int W, const float* field, void* coeff,
+                          pt_dtype dtype, float* ws, hipStream_t s) {
+  const int nx = g->nx, ny = g->ny;
+  const int nzo = nzl + 3, nzi = nzo + 2 * W;
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t pb = (int64_t)(nx + 3) * (ny + 3) * nzo;  // output block per component
+  for (int c = 0; c < 3; ++c) {
+    // z with open ends over all nzi planes into the workspace, y in place on
+    // the nzo central planes (a line pass reads all of its lines before it
+    // writes any, and workgroups own disjoint lines), then the x pass writes
+    // padded rows (y padding only: the planes are padded z planes already).
+    float* t = ws;
+    pt_status st = pass_lines(field + c * plane * nzi, t, nx, ny, nzi, 2, s, 1);
+    if (st != PT_OK) return st;
+    float* mid = t + plane * W;
+    st = pass_lines(mid, mid, nx, ny, nzo, 1, s);
+    if (st != PT_OK) return st;
+    void* o = dtype == PT_F32 ? (void*)((float*)coeff + c * pb)
+                              : (void*)((uint16_t*)coeff + c * pb);
+    st = pass_rows(mid, o, nx, ny, nzo, dtype == PT_F32 ? ROW_PAD_F32 : ROW_PAD_BF16, s, 0);
     if (st != PT_OK) return st;
   }
   return PT_OK;

@@ -114,3 +114,25 @@ def test_timing_registry_without_launches(b):
     b.pt_timing_enable(False)
     ms, n = ctypes.c_double(), ctypes.c_int64()
     assert b.LIB.pt_timing_read(None, ctypes.byref(ms), ctypes.byref(n)) == b.PT_ERR_NULL
+
+
+def test_slab_solve_arguments_and_workspace(b):
+    L = b.LIB
+    g = _g(b, (64, 48, 96))
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)  # never dereferenced: validation fails first
+    sp = ctypes.c_size_t()
+    nzi = 16 + 3 + 2 * 16
+    assert L.pt_workspace_bytes(b.PT_OP_SPLINE_SLAB, ctypes.byref(g), b.PT_F32, nzi,
+                                ctypes.byref(sp)) == 0
+    assert sp.value >= 4 * 64 * 48 * nzi and sp.value % 256 == 0
+    assert L.pt_workspace_bytes(b.PT_OP_SPLINE_SLAB, ctypes.byref(g), b.PT_F32, 3,
+                                ctypes.byref(sp)) == b.PT_ERR_SIZE
+    big = 1 << 40
+    assert L.pt_spline_coeffs_slab(ctypes.byref(g), 16, 0, fake, fake, 0, fake, big, None) == b.PT_ERR_SIZE
+    assert L.pt_spline_coeffs_slab(ctypes.byref(g), 16, 65, fake, fake, 0, fake, big, None) == b.PT_ERR_SIZE
+    assert L.pt_spline_coeffs_slab(ctypes.byref(g), 0, 16, fake, fake, 0, fake, big, None) == b.PT_ERR_SIZE
+    assert L.pt_spline_coeffs_slab(ctypes.byref(g), 97, 16, fake, fake, 0, fake, big, None) == b.PT_ERR_SIZE
+    assert L.pt_spline_coeffs_slab(ctypes.byref(g), 16, 16, None, fake, 0, fake, big, None) == b.PT_ERR_NULL
+    assert L.pt_spline_coeffs_slab(ctypes.byref(g), 16, 16, fake, fake, 5, fake, big, None) == b.PT_ERR_DTYPE
+    assert L.pt_spline_coeffs_slab(ctypes.byref(g), 16, 16, fake, fake, 0, fake, 256, None) == b.PT_ERR_WORKSPACE
