@@ -141,15 +141,15 @@ struct TimedLaunch {
       return;
     }
     if (hipEventCreate(&e1) != hipSuccess) {
-      hipEventDestroy(e0);
+      (void)hipEventDestroy(e0);
       e0 = e1 = nullptr;
       return;
     }
-    hipEventRecord(e0, stream);
+    (void)hipEventRecord(e0, stream);  // diagnostics: a failed record only loses the sample
   }
   ~TimedLaunch() {
     if (e0 && e1) {
-      hipEventRecord(e1, stream);
+      (void)hipEventRecord(e1, stream);
       timing_record(name, e0, e1);
     }
   }

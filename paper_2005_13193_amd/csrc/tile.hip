@@ -716,10 +716,10 @@ __global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
 // Each workgroup takes a 32 x 16 half of a column over a segment of layers and
 // sums the contributions in an LDS ring of planes of its tile (one-cell
 // margin, so predictor points that moved one cell out still land in it).  A
-// plane is added to g_coeff with a plain read-modify-write once nothing more
-// can reach it.  Launches run one colour (parities of cx, the half-row and the
-// segment) at a time, so no two concurrent workgroups touch the same
-// coefficient.  Stencils that do not fit the tile (periodic wrap, or a move of
+// plane is added to g_coeff once nothing more can reach it.  Launches run one
+// colour (parities of cx, the half-row and the segment) at a time, so no two
+// concurrent workgroups touch the same coefficient and the order of the
+// additions to each coefficient is fixed.  Stencils that do not fit the tile (periodic wrap, or a move of
 // more than one cell) go to a list that scatter_deferred adds with atomics
 // after all colours.
 //
@@ -883,21 +883,12 @@ __device__ __forceinline__ float scatter_scale(const TileArgs& a) {
   return ldexpf(1.0f, 30 - e);
 }
 
-__device__ __forceinline__ void load_gv(const TileArgs& a, int X0, int Y0, int P, float* v) {
-  const GridDev& g = a.g;
-  const int Pc = min(max(P, 0), g.nz + 2);
-#pragma unroll
-  for (int q = 0; q < kSPer; ++q) {
-    const int e = min((int)threadIdx.x + q * kSTB, kSPlane - 1);
-    int c, y, x;
-    selem(e, &c, &y, &x);
-    const int X = min(max(X0 + x, 0), g.px - 1), Y = min(max(Y0 + y, 0), g.py - 1);
-    v[q] = a.gcoeff[c * g.comp + (int64_t)Pc * g.plane + (int64_t)Y * g.px + X];
-  }
-}
-
+// Adds a finished plane of the ring to the gradient with one FP32 atomic add
+// per point (a single instruction instead of a load and a store; the colours
+// keep every other workgroup of the launch off these points, so the sums are
+// the same as a read-modify-write) and clears it for reuse.
 __device__ __forceinline__ void flush_splane(const TileArgs& a, long long* ring, int X0, int Y0,
-                                             int P, const float* v, float inv_scale) {
+                                             int P, float inv_scale) {
   const GridDev& g = a.g;
   if (P < 0 || P >= g.nz + 3) return;
   long long* sl = ring + sslot(P) * kSSlot;
@@ -911,8 +902,8 @@ __device__ __forceinline__ void flush_splane(const TileArgs& a, long long* ring,
     const long long acc = sl[e];
     sl[e] = 0;
     if (acc == 0 || X < 0 || X >= g.px || Y < 0 || Y >= g.py) continue;
-    a.gcoeff[c * g.comp + (int64_t)P * g.plane + (int64_t)Y * g.px + X] =
-        v[q] + (float)((double)acc * (double)inv_scale);
+    atomicAdd(a.gcoeff + (c * g.comp + (int64_t)P * g.plane + (int64_t)Y * g.px + X),
+              (float)((double)acc * (double)inv_scale));
   }
 }
 
@@ -961,7 +952,6 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
     return v < n0 ? r0 + v : r1 + (v - n0);
   };
   SData sd[2];
-  float gv[2][2][kSPer];
   auto prefetch = [&](int set, int s) {
     const int zs = z0 + s * kSlab;
     int64_t r0, n0, r1, n1;
@@ -970,9 +960,6 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
     const int64_t npass = (n + kSGroups - 1) / kSGroups;
     const int64_t v = grp * npass;
     load_sdata(a, vidx(v, r0, n0, r1), v < n, &sd[set]);
-    // planes zs-1 and zs are flushed at the end of slab s
-    load_gv(a, X0, Y0, zs - 1, gv[set][0]);
-    load_gv(a, X0, Y0, zs, gv[set][1]);
   };
   prefetch(0, 0);
   prefetch(1, 1);
@@ -1005,8 +992,8 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
         PT_WAIT_VMCNT0();
         // planes zs-1 and zs are complete: later particles sit in layers
         // >= zs+2 and their predictor points in layers >= zs+1
-        flush_splane(a, ring, X0, Y0, zs - 1, gv[hf][0], inv_scale);
-        flush_splane(a, ring, X0, Y0, zs, gv[hf][1], inv_scale);
+        flush_splane(a, ring, X0, Y0, zs - 1, inv_scale);
+        flush_splane(a, ring, X0, Y0, zs, inv_scale);
         dump_deferred(a, sdef_n, sdef, s_base, false);
         prefetch(hf, s + 2);
         __syncthreads();
@@ -1017,9 +1004,7 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   // predictor point of layer z1 - 1 reaches)
   const int last_zs = z0 + ((nl - 1) / kSlab) * kSlab;
   for (int P = last_zs + 1; P <= z1 + 3; ++P) {
-    float v[kSPer];
-    load_gv(a, X0, Y0, P, v);
-    flush_splane(a, ring, X0, Y0, P, v, inv_scale);
+    flush_splane(a, ring, X0, Y0, P, inv_scale);
     __syncthreads();
   }
   }  // items
