@@ -27,8 +27,8 @@
 namespace pt {
 
 constexpr int kSlab = 2;          // layers per iteration
-constexpr int kGatherSeg = 128;   // layers per gather work item
-constexpr int kScatterSeg = 256;  // layers per scatter work item
+constexpr int kGatherSeg = 128;   // most layers per gather work item
+constexpr int kScatterSeg = 256;  // most layers per scatter work item
 // The particle table indexes half-layers: the rows 0..15 and 16..31 of a
 // column layer (key >> 9 with 32 x 32 columns).
 constexpr int kHalfShift = 9;     // log2(kTileX * kTileY / 2)
@@ -1293,6 +1293,19 @@ static int64_t item_bound(int64_t nunits, int nz, int64_t np, int lmax) {
   return nunits * ((nz + lmax - 1) / lmax + 1) + 2 * ((np + kItemPmax - 1) / kItemPmax) + 8;
 }
 
+// Most layers per work item.  The longest runs are the cheapest per layer
+// (each item flushes or loads a few planes beyond its own), but a launch
+// needs about two items per compute unit (eight colours for the scatter):
+// small grids get shorter runs.
+static int item_lmax(const pt_grid* g, bool scatter) {
+  const int64_t ncol = (int64_t)((g->nx + kTileX - 1) / kTileX) * ((g->ny + kTileY - 1) / kTileY);
+  const int64_t want = scatter ? 8 * 2 * 256 : 2 * 256;  // items per launch, all colours
+  const int64_t units = scatter ? 2 * ncol : ncol;
+  const int64_t l = (int64_t)g->nz * units / want;
+  const int lo = scatter ? 8 : 16, hi = scatter ? kScatterSeg : kGatherSeg;
+  return (int)(l < lo ? lo : (l > hi ? hi : l));
+}
+
 // Units of the item builder: half-columns (scatter) or (z-block, column)
 // slots of the grouped column order (gather).
 static int64_t item_units(const pt_grid* g, bool scatter, ItemCfg* cfg) {
@@ -1303,7 +1316,8 @@ static int64_t item_units(const pt_grid* g, bool scatter, ItemCfg* cfg) {
     cfg->ngy = (ncy + kGroupH - 1) / kGroupH;
   }
   if (scatter) return 2 * (int64_t)ncx * ncy;
-  const int64_t nzb = (g->nz + kGatherSeg - 1) / kGatherSeg;
+  const int lmax = item_lmax(g, false);
+  const int64_t nzb = (g->nz + lmax - 1) / lmax;
   return nzb * ((ncx + kGroupW - 1) / kGroupW) * ((ncy + kGroupH - 1) / kGroupH) * kGroupW *
          kGroupH;
 }
@@ -1312,7 +1326,7 @@ static int64_t item_units(const pt_grid* g, bool scatter, ItemCfg* cfg) {
 size_t tile_items_bytes(const pt_grid* g, int64_t np, bool scatter) {
   const int64_t nunits = item_units(g, scatter, nullptr);
   // a gather unit spans one z-block: at most 1 + (splits by particle count)
-  const int64_t bound = scatter ? item_bound(nunits, g->nz, np, kScatterSeg)
+  const int64_t bound = scatter ? item_bound(nunits, g->nz, np, item_lmax(g, true))
                                 : nunits + 2 * ((np + kItemPmax - 1) / kItemPmax) + 8;
   return kItemsHeader + 4 * (size_t)(8 * nunits) + 16 * (size_t)bound;
 }
@@ -1331,7 +1345,7 @@ __global__ void zero_ctr(int* p) {
 static pt_status build_tile_items(const pt_grid* g, int64_t np, const int32_t* hs, bool scatter,
                                   void* ws, ItemSet* out, hipStream_t s) {
   const int ncx = (g->nx + kTileX - 1) / kTileX;
-  const int lmax = scatter ? kScatterSeg : kGatherSeg;
+  const int lmax = item_lmax(g, scatter);
   ItemCfg cfg{kItemPmax, scatter ? 6 : 2, lmax, scatter ? 1 : 0, 0, 0, 0};
   const int64_t nunits64 = item_units(g, scatter, &cfg);
   const int ncolors = scatter ? 8 : 1;
