@@ -136,3 +136,15 @@ def test_slab_solve_arguments_and_workspace(b):
     assert L.pt_spline_coeffs_slab(ctypes.byref(g), 16, 16, None, fake, 0, fake, big, None) == b.PT_ERR_NULL
     assert L.pt_spline_coeffs_slab(ctypes.byref(g), 16, 16, fake, fake, 5, fake, big, None) == b.PT_ERR_DTYPE
     assert L.pt_spline_coeffs_slab(ctypes.byref(g), 16, 16, fake, fake, 0, fake, 256, None) == b.PT_ERR_WORKSPACE
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it says so and exits before
+    touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
