@@ -168,11 +168,27 @@ pt_status pt_interp_uvw(const pt_grid *grid, const void *coeff, pt_dtype dtype,
 pt_status pt_interp_grad(const pt_grid *grid, const void *coeff, pt_dtype dtype,
                          int64_t np, const double *pos, float *out, hipStream_t stream);
 
+/* The sort argument of pt_rk2_step and pt_rk2_step_bwd. */
+enum {
+  PT_UNSORTED = 0, /* particles in any order, left in it; one thread per particle
+                      reads its coefficients from global memory */
+  PT_SORT = 1,     /* sort first (as pt_sort_particles); the column-tiled kernels */
+  PT_SORTED = 2    /* the particles are already in cell order (as pt_sort_particles
+                      leaves them, positions unchanged since) and stay in it; the
+                      column-tiled kernels without the sort.  Particles out of order
+                      give the same result more slowly: a particle outside its
+                      column's tile is evaluated from global memory, and a cell
+                      table that is not a partition of the particles (checked on
+                      the device) sends every particle that way. */
+};
+
 /* One RK2 step of dx/dt = u(x) (eq. (dxdt)), Heun's form:
  *   u0 = u(x);  x* = x + dt u0;  u1 = u(x*);  x <- x + dt/2 (u0 + u1),
  * velocities from the spline (FP32), positions in FP64, stored unwrapped.
- * If sort != 0 the particles are first re-ordered as by pt_sort_particles and
- * pos (and ids, if not NULL) come back in the new order.
+ * With sort = PT_SORT the particles are first re-ordered as by
+ * pt_sort_particles and pos (and ids, if not NULL) come back in the new
+ * order; with PT_UNSORTED or PT_SORTED the order is kept.  Other values of
+ * sort return PT_ERR_ARG.
  *   pos  in/out double [3][np];  ids  in/out int32 [np] or NULL
  *   ws          >= pt_workspace_bytes(PT_OP_RK2, ...) bytes */
 pt_status pt_rk2_step(const pt_grid *grid, const void *coeff, pt_dtype dtype,
@@ -236,7 +252,8 @@ pt_status pt_spline_coeffs_bwd(const pt_grid *grid, const float *g_coeff, float 
                                void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Adjoint of one pt_rk2_step.  pos_n: the positions the step started from
- * (in the step's input order); sort: as given to the forward step.
+ * (in the step's input order); sort: as given to the forward step (with
+ * PT_SORTED, pos_n in cell order and g_pos in that order).
  * g_pos: on entry dL/d(output positions) in the step's output order, on exit
  * dL/d(pos_n) in the input order.  g_coeff (may be NULL) accumulates dL/dS.
  *   x*b = J(x*)^T (dt/2) lam;  u0b = dt/2 lam + dt x*b;

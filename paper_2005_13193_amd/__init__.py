@@ -17,7 +17,7 @@ import math
 import torch
 
 from . import _binding as _b
-from ._binding import PtError  # noqa: F401
+from ._binding import PT_SORT, PT_SORTED, PT_UNSORTED, PtError  # noqa: F401
 
 __all__ = ["Grid", "PtError", "spline_coeffs", "spline_coeffs_bwd", "sort_particles",
            "interp_uvw", "interp_grad", "interp_uvw_bwd", "rk2_step", "rk2_step_bwd",
@@ -135,7 +135,9 @@ def interp_uvw_bwd(grid, coeff, pos, g_out, g_pos=None, g_coeff=None):
 
 
 def rk2_step(grid, coeff, pos, dt, ids=None, sort=True, ws=None):
-    """One Heun step in place on pos (and ids); returns pos."""
+    """One Heun step in place on pos (and ids); returns pos.  sort:
+    PT_SORT (or True) sorts first, PT_SORTED takes pos as already in cell
+    order, PT_UNSORTED (or False) keeps any order."""
     if ws is None:
         ws = workspace(_b.PT_OP_RK2, grid, pos.shape[1], coeff.dtype, pos.device)
     _b.pt_rk2_step(grid, coeff, dt, pos, ids, sort, ws)
@@ -165,7 +167,7 @@ def rk2_stage2(grid, coeff_np1, pos, u_n, dt, sorted_=True, ws=None):
 
 def rk2_step_bwd(grid, coeff, pos_n, dt, g_pos, g_coeff, sort=True, ws=None):
     """Adjoint of one step: g_pos (in: dL/dx_out) becomes dL/dpos_n in place;
-    g_coeff accumulates."""
+    g_coeff accumulates.  sort: as given to the forward step."""
     if ws is None:
         ws = workspace(_b.PT_OP_RK2_BWD, grid, pos_n.shape[1], coeff.dtype, pos_n.device)
     _b.pt_rk2_step_bwd(grid, coeff, dt, pos_n.contiguous(), sort, g_pos, g_coeff, ws)

@@ -32,6 +32,7 @@ PT_OP_RK2 = 2
 PT_OP_SPLINE_BWD = 3
 PT_OP_RK2_BWD = 4
 PT_OP_SPLINE_SLAB = 5
+PT_UNSORTED, PT_SORT, PT_SORTED = 0, 1, 2  # sort argument of the RK2 steps
 
 EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_spline_coeffs_slab",
            "pt_sort_particles",
@@ -222,7 +223,7 @@ def pt_rk2_step(grid, coeff, dt, pos, ids, sort, ws, stream=None):
     _need(ids, torch.int32, (np_,), "ids")
     _check("pt_rk2_step",
            LIB.pt_rk2_step(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
-                           float(dt), _ptr(pos), _ptr(ids), int(bool(sort)), _ptr(ws),
+                           float(dt), _ptr(pos), _ptr(ids), int(sort), _ptr(ws),
                            ws.numel() * ws.element_size(), _stream(stream)))
 
 
@@ -272,7 +273,7 @@ def pt_rk2_step_bwd(grid, coeff, dt, pos_n, sort, g_pos, g_coeff, ws, stream=Non
     _need(g_coeff, torch.float32, grid.padded_shape, "g_coeff")
     _check("pt_rk2_step_bwd",
            LIB.pt_rk2_step_bwd(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
-                               float(dt), _ptr(pos_n), int(bool(sort)), _ptr(g_pos),
+                               float(dt), _ptr(pos_n), int(sort), _ptr(g_pos),
                                _ptr(g_coeff), _ptr(ws), ws.numel() * ws.element_size(),
                                _stream(stream)))
 

@@ -23,6 +23,8 @@ pt_status spline_bwd(const pt_grid* g, const float* gcoeff, float* gfield, float
 // sort.hip
 int key_bits(const pt_grid* g);
 size_t sort_ws_bytes(const pt_grid* g, int64_t np);
+pt_status presorted_table(const pt_grid* g, int64_t np, const double* pos, int32_t* lstart,
+                          void* ws, hipStream_t s);
 pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double* pos_sorted,
                          int32_t* perm, uint64_t* keys_out, int32_t* lstart, void* ws,
                          hipStream_t s);
@@ -47,12 +49,12 @@ pt_status rk2_correct(const pt_grid* g, const void* coeff, pt_dtype dtype, int64
 int64_t tile_nlayers(const pt_grid* g);
 pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, double* x_out, void* defer,
-                       void* items_ws, hipStream_t s);
+                       void* items_ws, bool check, hipStream_t s);
 size_t tile_items_bytes(const pt_grid* g, int64_t np, bool scatter);
 pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, const double* lam, double* xbn,
                        float* u0, float* ub0, float* gcoeff, void* defer, void* items_ws,
-                       hipStream_t s);
+                       bool check, hipStream_t s);
 size_t tile_defer_bytes(int64_t np);
 pt_status tile_tv_stage1(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                          int64_t np, const double* x, double* x_out, float* u_n, void* defer,
@@ -319,6 +321,7 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
   PT_TRY(check_dtype(dtype));
   PT_TRY(check_np(np));
   if (!isfinite(dt)) return PT_ERR_ARG;
+  if (sort != PT_UNSORTED && sort != PT_SORT && sort != PT_SORTED) return PT_ERR_ARG;
   if (np == 0) return PT_OK;
   if (!coeff || !pos) return PT_ERR_NULL;
   size_t need = 0;
@@ -326,7 +329,7 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
   PT_TRY(ready());
   Rk2Ws w = carve_rk2(grid, np, ws);
-  if (sort) {
+  if (sort == PT_SORT) {
     PT_TRY(sort_particles(grid, np, pos, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
                           stream));
     if (ids) {
@@ -334,6 +337,11 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
       PT_HIP_CHECK(hipMemcpyAsync(ids, w.ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
     }
     return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, pos, w.defer, w.items,
+                        false, stream);
+  }
+  if (sort == PT_SORTED) {
+    PT_TRY(presorted_table(grid, np, pos, w.lstart, w.sort, stream));
+    return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, pos, pos, w.defer, w.items, true,
                         stream);
   }
   return rk2_advance(grid, coeff, dtype, np, dt, pos, pos, w.u0, stream);
@@ -403,6 +411,7 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
   PT_TRY(check_dtype(dtype));
   PT_TRY(check_np(np));
   if (!isfinite(dt)) return PT_ERR_ARG;
+  if (sort != PT_UNSORTED && sort != PT_SORT && sort != PT_SORTED) return PT_ERR_ARG;
   if (np == 0) return PT_OK;
   if (!coeff || !pos_n || !g_pos) return PT_ERR_NULL;
   size_t need = 0;
@@ -410,12 +419,19 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
   PT_TRY(ready());
   Rk2BwdWs w = carve_rk2_bwd(grid, np, ws);
-  if (sort) {
+  if (sort == PT_SORT) {
     PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
                           stream));
     PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, g_pos, w.xbn, w.u0,
-                        w.ub0, g_coeff, w.defer, w.items, stream));
+                        w.ub0, g_coeff, w.defer, w.items, false, stream));
     return scatter_back(np, w.xbn, w.perm, g_pos, stream);
+  }
+  if (sort == PT_SORTED) {
+    PT_TRY(presorted_table(grid, np, pos_n, w.lstart, w.sort, stream));
+    PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, pos_n, g_pos, w.xbn, w.u0, w.ub0,
+                        g_coeff, w.defer, w.items, true, stream));
+    PT_HIP_CHECK(hipMemcpyAsync(g_pos, w.xbn, 24 * (size_t)np, hipMemcpyDeviceToDevice, stream));
+    return PT_OK;
   }
   return rk2_backward(grid, coeff, dtype, np, dt, pos_n, g_pos, g_pos, g_coeff, w.u0, w.xbs,
                       stream);

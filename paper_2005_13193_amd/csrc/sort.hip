@@ -376,6 +376,30 @@ static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int3
   return PT_OK;
 }
 
+// The particle table of positions that should already be in cell order:
+// their keys, then the table built from them as if sorted.  For positions
+// that are not in order the table is garbage; its users check it on the
+// device before trusting it.
+template <typename K>
+static pt_status table_impl(const pt_grid* g, int64_t np, const double* pos, int32_t* lstart,
+                            void* ws, hipStream_t s) {
+  const GridDev gd = make_grid_dev(g);
+  SortWs w = carve_sort_ws(g, np, ws);
+  {
+    TimedLaunch t("sort_keys", s);
+    hipLaunchKernelGGL(cell_key_kernel<K>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd, np, pos,
+                       (K*)w.keys[0], w.vals0, device_error_flag());
+  }
+  PT_LAUNCH_CHECK();
+  return build_layer_table(g, np, w.keys[0], (int)sizeof(K), lstart, s);
+}
+
+pt_status presorted_table(const pt_grid* g, int64_t np, const double* pos, int32_t* lstart,
+                          void* ws, hipStream_t s) {
+  return key_bits(g) > 32 ? table_impl<uint64_t>(g, np, pos, lstart, ws, s)
+                          : table_impl<uint32_t>(g, np, pos, lstart, ws, s);
+}
+
 pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double* pos_sorted,
                          int32_t* perm, uint64_t* keys_out, int32_t* lstart, void* ws,
                          hipStream_t s) {

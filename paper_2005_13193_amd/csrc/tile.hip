@@ -1078,6 +1078,16 @@ __global__ __launch_bounds__(256) void check_table(const int32_t* __restrict__ l
   if (!ok) atomicOr(bad, 1);
 }
 
+// The scatter's counterpart: after a failed check every stencil (2 p + stage)
+// is deferred.
+__global__ __launch_bounds__(256) void scatter_fallback(int* header, uint32_t* __restrict__ list,
+                                                        int64_t np) {
+  if (header[kTableBad] == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < 2 * np) list[i] = (uint32_t)i;
+  if (i == 0) header[0] = (int)(2 * np < 0x7fffffff ? 2 * np : 0x7fffffff);
+}
+
 // After a failed check: empty every layer and put every particle on the
 // deferred list, so that all of them are evaluated from global memory.
 __global__ __launch_bounds__(256) void table_fallback(int32_t* __restrict__ ls, int64_t nl,
@@ -1456,13 +1466,15 @@ static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int
 }
 
 // defer: tile_defer_bytes(np) bytes; items_ws: tile_items_bytes(g, np, false)
+// check: ls was built from positions that may not be in cell order (see
+// launch_gather); x_out may then alias x.
 pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, double* x_out, void* defer,
-                       void* items_ws, hipStream_t s) {
+                       void* items_ws, bool check, hipStream_t s) {
   TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
   a.x = x;
   a.x_out = x_out;
-  return launch_gather(g, a, dtype, TILE_RK2_FWD, defer, items_ws, false, s);
+  return launch_gather(g, a, dtype, TILE_RK2_FWD, defer, items_ws, check, s);
 }
 
 // Stage 1 of the time-varying step on sorted particles x (table ls):
@@ -1494,14 +1506,14 @@ pt_status tile_tv_stage2(const pt_grid* g, const void* coeff, pt_dtype dtype, in
 pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, const double* lam, double* xbn,
                        float* u0, float* ub0, float* gcoeff, void* defer, void* items_ws,
-                       hipStream_t s) {
+                       bool check, hipStream_t s) {
   TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
   a.x = x;
   a.lam = lam;
   a.xbn = xbn;
   a.u0 = u0;
   a.ub0 = ub0;
-  pt_status st = launch_gather(g, a, dtype, TILE_RK2_BWD_GRAD, defer, items_ws, false, s);
+  pt_status st = launch_gather(g, a, dtype, TILE_RK2_BWD_GRAD, defer, items_ws, check, s);
   if (st != PT_OK || !gcoeff) return st;
   TileArgs b = tile_args(g, coeff, ls, np, dt, kScatterSeg);
   b.x = x;
@@ -1517,6 +1529,13 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   b.items = it.items;
   hipLaunchKernelGGL(zero_defer_count, dim3(1), dim3(1), 0, s, b.defer_count);
   PT_LAUNCH_CHECK();
+  if (check) {
+    // a table the gather found invalid was emptied: every stencil goes to
+    // the deferred list
+    hipLaunchKernelGGL(scatter_fallback, dim3(grid_1d(2 * np, 256)), dim3(256), 0, s,
+                       b.defer_count, b.defer, np);
+    PT_LAUNCH_CHECK();
+  }
   const size_t lds =
       sizeof(long long) * (size_t)kSRing * kSSlot + sizeof(int) * 2 * (kScatterSeg + 2) +
       sizeof(int) * (4 + (size_t)kSDefCap);

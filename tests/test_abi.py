@@ -97,6 +97,10 @@ def test_invalid_arguments_rejected_before_launch(b):
     nan = float("nan")
     assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, nan, fake, None, 1, fake, 1 << 40, None) == b.PT_ERR_ARG
     assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, 0.1, fake, None, 1, fake, 8, None) == b.PT_ERR_WORKSPACE
+    for bad_sort in (-1, 3):  # only PT_UNSORTED, PT_SORT and PT_SORTED
+        assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, 0.1, fake, None, bad_sort, fake, 1 << 40, None) == b.PT_ERR_ARG
+        assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, 10, 0.1, fake, bad_sort, fake, None, fake, 1 << 40, None) == b.PT_ERR_ARG
+    assert (b.PT_UNSORTED, b.PT_SORT, b.PT_SORTED) == (0, 1, 2)
     assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, 10, 0.1, fake, 1, None, None, fake, 1 << 40, None) == b.PT_ERR_NULL
     assert L.pt_interp_uvw_bwd(ctypes.byref(g), fake, 0, 10, fake, None, fake, None, None) == b.PT_ERR_NULL
     assert L.pt_interp_uvw_bwd(ctypes.byref(g), fake, 0, 10, fake, fake, None, None, None) == b.PT_OK
