@@ -2,10 +2,11 @@
 
 One step = one pass of the whole path on resident device data:
   spline coefficients of the field (3 axis solves per component)
-  -> cell keys + stable radix sort + permutation
-  -> Heun RK2 step (two 64-point gathers of (u,v,w) per particle)
-  -> adjoint of that RK2 step (re-sort, derivative gathers, scatter-add of the
-     coefficient gradient) -> adjoint of the spline solve.
+  -> cell keys + stable radix sort + permutation of x_n (and the labels)
+  -> Heun RK2 step on the sorted particles (two 64-point gathers of (u,v,w)
+     per particle)
+  -> adjoint of that RK2 step on the same order (derivative gathers,
+     scatter-add of the coefficient gradient) -> adjoint of the spline solve.
 value = 2 * N_p particle interpolations of (u,v,w) per step / step time.
 
 With --workload tv a step is instead the forward step in a field that changes
@@ -127,7 +128,7 @@ def measured_traffic(kernel, config, dtype, clustered):
 def cpu_baseline(n_full, np_full, clustered):
     """FP64 oracle, timed on this host, on a bounded sample of the same step:
     the spline solve and its adjoint on a 512^3 grid and the fwd+adjoint
-    particle work (sort, Heun step, re-sort, step adjoint) for 2^24 particles
+    particle work (sort, Heun step, step adjoint) for 2^24 particles
     of the workload's distribution, each scaled linearly to the full grid and
     particle count."""
     import numpy as np
@@ -150,9 +151,8 @@ def cpu_baseline(n_full, np_full, clustered):
     t1 = time.perf_counter()
     ps, _, _ = oracle.sort_particles(g, pos, 32, 32)
     p1 = oracle.rk2_step(g, coeff, ps, dt)
-    ps2, _, _ = oracle.sort_particles(g, pos, 32, 32)  # the adjoint re-sorts the step input
     gc = np.zeros_like(coeff)
-    oracle.rk2_step_bwd(g, coeff, ps2, dt, 2.0 * p1, gc)
+    oracle.rk2_step_bwd(g, coeff, ps, dt, 2.0 * p1, gc)
     t2 = time.perf_counter()
     gfield = oracle.spline_coeffs_bwd(gc)
     t3 = time.perf_counter()
@@ -447,17 +447,19 @@ def main():
     coeff = torch.empty(g.padded_shape, dtype=cdt, device=dev)
     g_coeff = torch.zeros(g.padded_shape, dtype=torch.float32, device=dev)
     g_field = torch.empty(g.field_shape, dtype=torch.float32, device=dev)
-    pos_prev = torch.empty_like(pos)
+    pos_n = torch.empty_like(pos)
+    perm = torch.empty(np_, dtype=torch.int32, device=dev)
     g_pos = torch.empty_like(pos)
     ws_sp = pt.workspace(B.PT_OP_SPLINE, g, 0, cdt, dev)
     ws_spb = pt.workspace(B.PT_OP_SPLINE_BWD, g, 0, torch.float32, dev)
+    ws_s = pt.workspace(B.PT_OP_SORT, g, np_, cdt, dev)
     ws_f = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
     ws_b = pt.workspace(B.PT_OP_RK2_BWD, g, np_, cdt, dev)
     torch.cuda.synchronize()
     log(f"[bench] inputs ready: dt={dt:.3e}, |u|max={umax:.3f}, "
         f"mem={torch.cuda.memory_allocated() / 2**30:.1f} GiB")
 
-    names = ["spline", "rk2_fwd", "rk2_bwd", "spline_bwd"]
+    names = ["spline", "sort", "rk2_fwd", "rk2_bwd", "spline_bwd"]
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for k in names}
     acc = {k: 0.0 for k in names}
@@ -469,13 +471,18 @@ def main():
         mark("spline", 0)
         B.pt_spline_coeffs(g, field, coeff, ws_sp)
         mark("spline", 1)
-        pos_prev.copy_(pos)
+        # one cell sort per step: x_n (and the labels) into cell order, kept
+        # for the adjoint; the step and its adjoint then skip their own sort
+        mark("sort", 0)
+        B.pt_sort_particles(g, pos, pos_n, perm, ids, None, ws_s)
+        mark("sort", 1)
+        pos.copy_(pos_n)
         mark("rk2_fwd", 0)
-        B.pt_rk2_step(g, coeff, dt, pos, ids, True, ws_f)
+        B.pt_rk2_step(g, coeff, dt, pos, None, B.PT_SORTED, ws_f)
         mark("rk2_fwd", 1)
         torch.mul(pos, 2.0, out=g_pos)  # dL/dx for L = sum |x|^2
         mark("rk2_bwd", 0)
-        B.pt_rk2_step_bwd(g, coeff, dt, pos_prev, True, g_pos, g_coeff, ws_b)
+        B.pt_rk2_step_bwd(g, coeff, dt, pos_n, B.PT_SORTED, g_pos, g_coeff, ws_b)
         mark("rk2_bwd", 1)
         mark("spline_bwd", 0)
         B.pt_spline_coeffs_bwd(g, g_coeff, g_field, ws_spb)

@@ -147,11 +147,14 @@ pt_status pt_spline_coeffs_slab(const pt_grid *grid, int32_t nzl, int32_t halo,
  *   pos_sorted  out  double [3][np], pos_sorted[d][i] = pos[d][perm[i]]
  *                    (may be NULL); must not overlap pos
  *   perm        out  int32 [np], original index of sorted particle i
+ *   ids      in/out  int32 [np] particle labels, re-ordered with the positions:
+ *                    ids[i] <- ids[perm[i]] (may be NULL)
  *   keys_out    out  uint64 [np] sorted keys (may be NULL)
  *   ws               >= pt_workspace_bytes(PT_OP_SORT, ...) bytes */
 pt_status pt_sort_particles(const pt_grid *grid, int64_t np, const double *pos,
-                            double *pos_sorted, int32_t *perm, uint64_t *keys_out,
-                            void *ws, size_t ws_bytes, hipStream_t stream);
+                            double *pos_sorted, int32_t *perm, int32_t *ids,
+                            uint64_t *keys_out, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
 
 /* Operations 2 and 3 of Sec. 2.2, eq. (spline): at every particle
  *   g+ = sum_{k,j,i=1..4} b_i(x') c_j(y') d_k(z') S[gamma+k-2][beta+j-2][alpha+i-2]

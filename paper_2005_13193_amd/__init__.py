@@ -99,8 +99,9 @@ def spline_coeffs_bwd(grid, g_coeff, out=None, ws=None):
     return out
 
 
-def sort_particles(grid, pos, want_keys=True, ws=None):
-    """Returns (pos_sorted, perm, keys) with pos_sorted = pos[:, perm]."""
+def sort_particles(grid, pos, want_keys=True, ids=None, ws=None):
+    """Returns (pos_sorted, perm, keys) with pos_sorted = pos[:, perm]; ids,
+    if given, is re-ordered in place the same way."""
     pos = pos.contiguous()
     np_ = pos.shape[1]
     dev = pos.device
@@ -109,7 +110,7 @@ def sort_particles(grid, pos, want_keys=True, ws=None):
     keys = torch.empty(np_, dtype=torch.int64, device=dev) if want_keys else None
     if ws is None:
         ws = workspace(_b.PT_OP_SORT, grid, np_, torch.float32, dev)
-    _b.pt_sort_particles(grid, pos, pos_sorted, perm, keys, ws)
+    _b.pt_sort_particles(grid, pos, pos_sorted, perm, ids, keys, ws)
     return pos_sorted, perm, keys
 
 

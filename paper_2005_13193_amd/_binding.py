@@ -68,7 +68,7 @@ def _load():
         "pt_spline_coeffs": [g, vp, vp, ctypes.c_int, vp, sz, vp],
         "pt_spline_coeffs_slab": [g, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int, vp,
                                   sz, vp],
-        "pt_sort_particles": [g, i64, vp, vp, vp, vp, vp, sz, vp],
+        "pt_sort_particles": [g, i64, vp, vp, vp, vp, vp, vp, sz, vp],
         "pt_interp_uvw": [g, vp, ctypes.c_int, i64, vp, vp, vp],
         "pt_interp_grad": [g, vp, ctypes.c_int, i64, vp, vp, vp],
         "pt_rk2_step": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
@@ -184,15 +184,16 @@ def pt_spline_coeffs_bwd(grid, g_coeff, g_field, ws, stream=None):
                                     _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
 
-def pt_sort_particles(grid, pos, pos_sorted, perm, keys_out, ws, stream=None):
+def pt_sort_particles(grid, pos, pos_sorted, perm, ids, keys_out, ws, stream=None):
     np_ = pos.shape[1]
     _need(pos, torch.float64, (3, np_), "pos")
     _need(pos_sorted, torch.float64, (3, np_), "pos_sorted")
     _need(perm, torch.int32, (np_,), "perm")
+    _need(ids, torch.int32, (np_,), "ids")
     _need(keys_out, torch.int64, (np_,), "keys_out")
     _check("pt_sort_particles",
            LIB.pt_sort_particles(ctypes.byref(_grid(grid)), np_, _ptr(pos), _ptr(pos_sorted),
-                                 _ptr(perm), _ptr(keys_out), _ptr(ws),
+                                 _ptr(perm), _ptr(ids), _ptr(keys_out), _ptr(ws),
                                  ws.numel() * ws.element_size(), _stream(stream)))
 
 

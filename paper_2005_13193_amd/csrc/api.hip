@@ -220,7 +220,7 @@ pt_status pt_workspace_bytes(int op, const pt_grid* grid, pt_dtype dtype, int64_
   switch (op) {
     case PT_OP_SPLINE: *bytes = a256(4 * spline_ws_floats(grid, dtype)); break;
     case PT_OP_SPLINE_BWD: *bytes = a256(4 * n3); break;
-    case PT_OP_SORT: *bytes = a256(sort_ws_bytes(grid, np)); break;
+    case PT_OP_SORT: *bytes = a256(sort_ws_bytes(grid, np)) + a256(4 * (size_t)np); break;
     case PT_OP_RK2: *bytes = a256(rk2_ws_bytes(grid, np)); break;
     case PT_OP_RK2_BWD: *bytes = a256(rk2_bwd_ws_bytes(grid, np)); break;
     // np = input planes of the slab, nzl + 3 + 2 W
@@ -279,8 +279,8 @@ pt_status pt_spline_coeffs_bwd(const pt_grid* grid, const float* g_coeff, float*
 }
 
 pt_status pt_sort_particles(const pt_grid* grid, int64_t np, const double* pos, double* pos_sorted,
-                            int32_t* perm, uint64_t* keys_out, void* ws, size_t ws_bytes,
-                            hipStream_t stream) {
+                            int32_t* perm, int32_t* ids, uint64_t* keys_out, void* ws,
+                            size_t ws_bytes, hipStream_t stream) {
   PT_TRY(check_grid(grid));
   PT_TRY(check_np(np));
   if (np == 0) return PT_OK;
@@ -289,7 +289,13 @@ pt_status pt_sort_particles(const pt_grid* grid, int64_t np, const double* pos, 
   PT_TRY(pt_workspace_bytes(PT_OP_SORT, grid, PT_F32, np, &need));
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
   PT_TRY(ready());
-  return sort_particles(grid, np, pos, pos_sorted, perm, keys_out, nullptr, ws, stream);
+  PT_TRY(sort_particles(grid, np, pos, pos_sorted, perm, keys_out, nullptr, ws, stream));
+  if (!ids) return PT_OK;
+  // the labels' staging buffer sits after the sort's own workspace
+  int32_t* ids_tmp = (int32_t*)((char*)ws + a256(sort_ws_bytes(grid, np)));
+  PT_TRY(permute_ids(np, ids, perm, ids_tmp, stream));
+  PT_HIP_CHECK(hipMemcpyAsync(ids, ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
+  return PT_OK;
 }
 
 pt_status pt_interp_uvw(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,

@@ -85,11 +85,11 @@ def test_invalid_arguments_rejected_before_launch(b):
     assert L.pt_spline_coeffs(ctypes.byref(g), fake, fake, 0, fake, 16, None) == b.PT_ERR_WORKSPACE
     assert L.pt_spline_coeffs(ctypes.byref(g), fake, fake, 0, None, 1 << 30, None) == b.PT_ERR_WORKSPACE
     assert L.pt_spline_coeffs_bwd(ctypes.byref(g), fake, None, fake, 1 << 30, None) == b.PT_ERR_NULL
-    assert L.pt_sort_particles(ctypes.byref(g), -1, fake, fake, fake, None, fake, 1 << 30, None) == b.PT_ERR_SIZE
-    assert L.pt_sort_particles(ctypes.byref(g), 1 << 31, fake, fake, fake, None, fake, 1 << 40, None) == b.PT_ERR_SIZE
-    assert L.pt_sort_particles(ctypes.byref(g), 10, fake, fake, None, None, fake, 1 << 30, None) == b.PT_ERR_NULL
-    assert L.pt_sort_particles(ctypes.byref(g), 10, fake, fake, fake, None, fake, 8, None) == b.PT_ERR_WORKSPACE
-    assert L.pt_sort_particles(ctypes.byref(g), 0, None, None, None, None, None, 0, None) == b.PT_OK
+    assert L.pt_sort_particles(ctypes.byref(g), -1, fake, fake, fake, None, None, fake, 1 << 30, None) == b.PT_ERR_SIZE
+    assert L.pt_sort_particles(ctypes.byref(g), 1 << 31, fake, fake, fake, None, None, fake, 1 << 40, None) == b.PT_ERR_SIZE
+    assert L.pt_sort_particles(ctypes.byref(g), 10, fake, fake, None, None, None, fake, 1 << 30, None) == b.PT_ERR_NULL
+    assert L.pt_sort_particles(ctypes.byref(g), 10, fake, fake, fake, None, None, fake, 8, None) == b.PT_ERR_WORKSPACE
+    assert L.pt_sort_particles(ctypes.byref(g), 0, None, None, None, None, None, None, 0, None) == b.PT_OK
     assert L.pt_interp_uvw(ctypes.byref(g), None, 0, 10, fake, fake, None) == b.PT_ERR_NULL
     assert L.pt_interp_uvw(ctypes.byref(g), fake, 2, 10, fake, fake, None) == b.PT_ERR_DTYPE
     assert L.pt_interp_uvw(ctypes.byref(g), None, 0, 0, None, None, None) == b.PT_OK

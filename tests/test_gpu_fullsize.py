@@ -11,7 +11,10 @@ full with the plain oracle.
     gradients at 256 sampled particles, and the displacement after 20 Heun
     steps with the cell sort every step (FP32 and BF16-stored coefficients)
     of a 1M-particle subsample, against the full FP64 oracle (its spline solve
-    of the whole 1024^3 field on the host);
+    of the whole 1024^3 field on the host), each step launched as the
+    benchmark launches it (one sort, then the step on the sorted particles);
+    for FP32, the adjoint of the last step at 256 sampled particles and 64
+    sampled coefficient points;
   2048^3, 256M uniform particles (64-bit sort keys): sort, the 12-output
     gather on the sorted particles and one sorted Heun step, sampled;
   256^3, 1M particles: L = sum |x(8)|^2 through TrackParticles (checkpoints
@@ -102,8 +105,8 @@ def test_c3_1024_sampled(pt, dtype):
     import torch
     from paper_2005_13193_amd import _binding as B
     n, np_, kmax, steps = 1024, 64 * 2 ** 20, 341, 20
-    if free_bytes() < 40 * 2 ** 30:
-        pytest.skip("needs 40 GiB of free device memory")
+    if free_bytes() < 64 * 2 ** 30:
+        pytest.skip("needs 64 GiB of free device memory")
     dev = torch.device("cuda:0")
     cdt = torch.float32 if dtype == "f32" else torch.bfloat16
     g, og = pt.Grid(n), oracle.Grid(n)
@@ -136,14 +139,25 @@ def test_c3_1024_sampled(pt, dtype):
     assert normwise(out12[:3], ref12[:3]) < (F32_TOL if dtype == "f32" else BF16_TOL)
     assert normwise(out12[3:], ref12[3:]) < (F32_TOL if dtype == "f32" else GRAD_BF16_TOL)
     log("sampled gather ok")
+    # the step as the benchmark launches it: one sort of x_n and the labels,
+    # then the Heun step on the sorted particles (PT_SORTED)
     ids = torch.arange(np_, dtype=torch.int32, device=dev)
+    pos_n = torch.empty_like(pos)
+    perm = torch.empty(np_, dtype=torch.int32, device=dev)
+    ws_s = pt.workspace(B.PT_OP_SORT, g, np_, cdt, dev)
     ws = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
     for s in range(steps):
-        pt.rk2_step(g, coeff, pos, dt, ids=ids, sort=True, ws=ws)
+        B.pt_sort_particles(g, pos, pos_n, perm, ids, None, ws_s)
+        pos.copy_(pos_n)
+        B.pt_rk2_step(g, coeff, dt, pos, None, B.PT_SORTED, ws)
     assert pt.last_device_error() == 0
     fin = pos[:, slots_of(ids, sample)].cpu().numpy()
     finb = pos[:, slots_of(ids, big)].cpu().numpy()
-    del pos, ids, ws, coeff
+    del ws_s, ws, perm, ids
+    torch.cuda.empty_cache()
+    if dtype == "f32":
+        adj = _c3_adjoint_of_last_step(pt, B, g, coeff, pos_n, pos, dt)
+    del pos, pos_n, coeff
     torch.cuda.empty_cache()
     log("20 steps done; oracle trajectories")
     ref = oracle.rk2_window(og, fh, pos0, dt, steps)
@@ -157,6 +171,69 @@ def test_c3_1024_sampled(pt, dtype):
     errb = normwise(finb - big0, refb - big0)
     log(f"c3 {dtype}: displacement error (1M particles, FP64 oracle) {errb:.3e}")
     assert errb < (F32_TOL if dtype == "f32" else BF16_TOL)
+    if dtype == "f32":
+        _check_c3_adjoint(og, rc, dt, adj)
+
+
+def _c3_adjoint_of_last_step(pt, B, g, coeff, pos_n, pos, dt):
+    """The adjoint of the last step as the benchmark launches it (PT_SORTED on
+    the sorted x_n, lambda = dL/dx for L = sum |x|^2), and host copies of what
+    the sampled checks need: 256 particles' x_n, lambda and dL/dx_n, and, for
+    64 padded coefficient points (half of them at particles' cells), the
+    gradient there and every particle whose cell lies within 5 cells of one
+    of them on each axis (a stencil reaches 2 cells, the predictor < 1)."""
+    import torch
+    dev = pos.device
+    n, np_ = g.nx, pos.shape[1]
+    lam = 2.0 * pos
+    g_pos = lam.clone()
+    gco = torch.zeros(g.padded_shape, dtype=torch.float32, device=dev)
+    ws_b = pt.workspace(B.PT_OP_RK2_BWD, g, np_, torch.float32, dev)
+    B.pt_rk2_step_bwd(g, coeff, dt, pos_n, B.PT_SORTED, g_pos, gco, ws_b)
+    assert pt.last_device_error() == 0
+    del ws_b
+    rng = np.random.default_rng(21)
+    part = torch.from_numpy(rng.choice(np_, 256, replace=False)).to(dev)
+    out = {"x": pos_n[:, part].cpu().numpy(), "lam": lam[:, part].cpu().numpy(),
+           "gx": g_pos[:, part].cpu().numpy()}
+    del g_pos
+    h = 2 * np.pi / n
+    cell = torch.floor(torch.remainder(pos_n, 2 * np.pi) / h).long().clamp_(0, n - 1)
+    at = cell[:, torch.from_numpy(rng.choice(np_, 32, replace=False)).to(dev)].cpu().numpy() + 1
+    pts = np.concatenate([at, rng.integers(0, n + 3, size=(3, 32))], axis=1)
+    near = torch.zeros(np_, dtype=torch.bool, device=dev)
+    for j in range(pts.shape[1]):
+        m = torch.ones(np_, dtype=torch.bool, device=dev)
+        for d in range(3):
+            r = torch.remainder(cell[d] - int(pts[d, j] - 1), n)
+            m &= torch.minimum(r, n - r) <= 5
+        near |= m
+    idx = near.nonzero().flatten()
+    out["near_x"] = pos_n[:, idx].cpu().numpy()
+    out["near_lam"] = lam[:, idx].cpu().numpy()
+    out["pts"] = pts
+    out["gco"] = gco[:, torch.from_numpy(pts[2]).to(dev), torch.from_numpy(pts[1]).to(dev),
+                     torch.from_numpy(pts[0]).to(dev)].double().cpu().numpy()
+    del lam, gco, cell, near
+    torch.cuda.empty_cache()
+    log(f"c3 f32: adjoint done; {idx.numel()} particles near the sampled coefficients")
+    return out
+
+
+def _check_c3_adjoint(og, rc, dt, adj):
+    gx, _ = oracle.rk2_step_bwd(og, rc, adj["x"], dt, adj["lam"], None)
+    err = normwise(adj["gx"], gx)
+    log(f"c3 f32: adjoint dL/dx_n error (256 particles) {err:.3e}")
+    assert err < F32_TOL
+    gfull = np.zeros_like(rc)
+    oracle.rk2_step_bwd(og, rc, adj["near_x"], dt, adj["near_lam"], gfull)
+    pts = adj["pts"]
+    ref = gfull[:, pts[2], pts[1], pts[0]]
+    del gfull
+    assert np.abs(ref).max() > 0
+    err = normwise(adj["gco"], ref)
+    log(f"c3 f32: adjoint dL/dS error (64 sampled coefficients) {err:.3e}")
+    assert err < F32_TOL
 
 
 def test_c5_2048_sampled(pt):

@@ -114,10 +114,13 @@ def test_sort_bit_exact(pt, shape, np_):
     tx, ty, _ = pt.key_layout(g)
     _, _, key_ref = oracle.cell_keys(og, pos, tx, ty)
     perm_ref = oracle.stable_sort(key_ref)
-    ps, perm, keys = pt.sort_particles(g, dev(pos))
+    labels = rng.integers(-2**31, 2**31 - 1, size=np_).astype(np.int32)
+    ids = dev(labels)
+    ps, perm, keys = pt.sort_particles(g, dev(pos), ids=ids)
     assert np.array_equal(host(perm), perm_ref)
     assert np.array_equal(host(keys).astype(np.uint64), key_ref[perm_ref])
     assert np.array_equal(host(ps), pos[:, perm_ref])
+    assert np.array_equal(host(ids), labels[perm_ref])
 
 
 def test_sort_empty(pt):
