@@ -883,27 +883,41 @@ __device__ __forceinline__ float scatter_scale(const TileArgs& a) {
   return ldexpf(1.0f, 30 - e);
 }
 
+// Offsets in g_coeff, less the plane term, of the plane words this thread
+// flushes for the current tile (-1: outside the padded grid).  They depend on
+// the tile only, so they are formed once per work item.
+__device__ __forceinline__ void flush_offsets(const GridDev& g, int X0, int Y0,
+                                              int64_t off[kSPer]) {
+#pragma unroll
+  for (int q = 0; q < kSPer; ++q) {
+    const int e = threadIdx.x + q * kSTB;
+    int c, y, x;
+    selem(e, &c, &y, &x);
+    const int X = X0 + x, Y = Y0 + y;
+    off[q] = (e < kSPlane && X >= 0 && X < g.px && Y >= 0 && Y < g.py)
+                 ? c * g.comp + (int64_t)Y * g.px + X
+                 : -1;
+  }
+}
+
 // Adds a finished plane of the ring to the gradient with one FP32 atomic add
 // per point (a single instruction instead of a load and a store; the colours
 // keep every other workgroup of the launch off these points, so the sums are
 // the same as a read-modify-write) and clears it for reuse.
-__device__ __forceinline__ void flush_splane(const TileArgs& a, long long* ring, int X0, int Y0,
-                                             int P, float inv_scale) {
+__device__ __forceinline__ void flush_splane(const TileArgs& a, long long* ring,
+                                             const int64_t off[kSPer], int P, float inv_scale) {
   const GridDev& g = a.g;
   if (P < 0 || P >= g.nz + 3) return;
   long long* sl = ring + sslot(P) * kSSlot;
+  float* gp = a.gcoeff + (int64_t)P * g.plane;
 #pragma unroll
   for (int q = 0; q < kSPer; ++q) {
     const int e = threadIdx.x + q * kSTB;
     if (e >= kSPlane) continue;
-    int c, y, x;
-    selem(e, &c, &y, &x);
-    const int X = X0 + x, Y = Y0 + y;
     const long long acc = sl[e];
     sl[e] = 0;
-    if (acc == 0 || X < 0 || X >= g.px || Y < 0 || Y >= g.py) continue;
-    atomicAdd(a.gcoeff + (c * g.comp + (int64_t)P * g.plane + (int64_t)Y * g.px + X),
-              (float)((double)acc * (double)inv_scale));
+    if (acc == 0 || off[q] < 0) continue;
+    atomicAdd(gp + off[q], (float)((double)acc * (double)inv_scale));
   }
 }
 
@@ -922,6 +936,8 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   while (next_item(a, &range_k, &col, &half, &z0, &z1)) {
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
   const int X0 = cx * kTileX - 1, Y0 = cy * kTileY + half * (kTileY / 2) - 1;
+  int64_t foff[kSPer];
+  flush_offsets(g, X0, Y0, foff);
   const int lane = threadIdx.x & (kSLanes - 1), grp = threadIdx.x / kSLanes;
   const int nl = z1 - z0;
   // starts of this half and of the next half-layer, for layers z0 .. z1
@@ -992,8 +1008,8 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
         PT_WAIT_VMCNT0();
         // planes zs-1 and zs are complete: later particles sit in layers
         // >= zs+2 and their predictor points in layers >= zs+1
-        flush_splane(a, ring, X0, Y0, zs - 1, inv_scale);
-        flush_splane(a, ring, X0, Y0, zs, inv_scale);
+        flush_splane(a, ring, foff, zs - 1, inv_scale);
+        flush_splane(a, ring, foff, zs, inv_scale);
         dump_deferred(a, sdef_n, sdef, s_base, false);
         prefetch(hf, s + 2);
         __syncthreads();
@@ -1004,7 +1020,7 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   // predictor point of layer z1 - 1 reaches)
   const int last_zs = z0 + ((nl - 1) / kSlab) * kSlab;
   for (int P = last_zs + 1; P <= z1 + 3; ++P) {
-    flush_splane(a, ring, X0, Y0, P, inv_scale);
+    flush_splane(a, ring, foff, P, inv_scale);
     __syncthreads();
   }
   }  // items
