@@ -54,7 +54,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold", "sort_keys",
+KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold",
+           "spline_y_carry", "spline_yx_pad", "sort_keys",
            "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter",
            "tile_tv_stage1", "tile_tv_stage2")
 
@@ -74,6 +75,10 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step):
         "spline_x": 8 * n3, "spline_y": 8 * n3, "spline_z": 8 * n3,
         "spline_x_pad": 4 * n3 + cb * p3,
         "spline_x_fold": 4 * p3 + 4 * n3,
+        # fused y + x: the y lines' chunk carries (2 floats per 32 rows) are
+        # written by the first pass and read by the second
+        "spline_y_carry": 4 * n3 + 8 * n3 // 32,
+        "spline_yx_pad": 4 * n3 + 8 * n3 // 32 + cb * p3,
         "sort_keys": np_ * (24 + kb + 4),
         "sort_pass": np_ * 2 * (kb + 4),
         "sort_permute": np_ * (4 + 24 + 24),

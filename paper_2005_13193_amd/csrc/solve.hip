@@ -33,6 +33,11 @@
 //    holds a contiguous chunk and the chunk maps are combined by a wave scan.
 //    Variants write all padded copies of the row (last forward pass) or sum
 //    the padded copies of the row (first adjoint pass).
+//  * solve_yx    - the forward y and x passes fused, for rows of 256, 512 or
+//    1024 points: a y pass that stores only its chunk carries, then one
+//    workgroup per chunk of rows solves along y in registers and along x
+//    through LDS and writes the padded rows (one read and one write of the
+//    field instead of two of each).
 //
 // Slab form.  When the grid is split in z (one device's share), the z lines
 // of a slab are solved with open ends over the slab plus W field planes on
@@ -335,6 +340,9 @@ struct LineArgs {
   int open;       // 1: lines with open ends (recursions start from zero at
                   // the ends), 0: periodic lines
   int bx0;        // first x-block of the launch
+  float* carry;   // non-null: write only the carries entering each run of
+                  // 16 points, [b][na / 16][2][nx] (causal, anti-causal),
+                  // for solve_yx (whole chunks of a multiple of 16 points)
 };
 
 __device__ __forceinline__ float chunk_gain(const LineArgs& a, int k) {
@@ -344,7 +352,8 @@ __device__ __forceinline__ float chunk_gain(const LineArgs& a, int k) {
 
 // FULL: every thread of the launch holds a whole chunk of Q = L points
 // (launched only on x-blocks inside nx, with K * L = na).
-template <int Q, bool FULL>
+// CARRY: write only the run carries to a.carry (FULL launches only).
+template <int Q, bool FULL, bool CARRY = false>
 __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
   __shared__ float s_e[1024];
   __shared__ float s_f[1024];
@@ -371,6 +380,7 @@ __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
 
   s_e[k * a.G + xg] = causal_local<Q, FULL>(v, len);
   __syncthreads();
+  float s_c;  // the causal carry entering this chunk
   {
     float cin = 0.0f, P = 1.0f;
     const int jn = a.open ? k : a.K;  // chunks before this one (open: no wrap)
@@ -381,6 +391,12 @@ __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
       P *= chunk_gain(a, kk);
     }
     causal_carry<Q, FULL>(v, len, cin * a.closure);
+    s_c = cin * a.closure;
+  }
+  float cv[Q / 16 > 1 ? Q / 16 - 1 : 1];  // causal values ending runs of 16
+  if constexpr (CARRY) {
+#pragma unroll
+    for (int r = 0; r + 1 < Q / 16; ++r) cv[r] = v[16 * r + 15];
   }
   s_f[k * a.G + xg] = anticausal_local<Q>(v);
   __syncthreads();
@@ -393,6 +409,25 @@ __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
       din += R * s_f[kk * a.G + xg];
       R *= chunk_gain(a, kk);
     }
+    if constexpr (CARRY) {
+      // the state entering each run of 16 points from the left (the causal
+      // value before it) and from the right (the anti-causal value after it)
+      constexpr int R = Q / 16;
+      float cl[R];
+      cl[0] = s_c;
+#pragma unroll
+      for (int r = 1; r < R; ++r) cl[r] = cv[r - 1];
+      anticausal_carry<Q, FULL>(v, len, din * a.closure);
+      if (len > 0) {
+        float* cr = a.carry + ((int64_t)b * a.na + m0) / 16 * 2 * a.nx + x;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          cr[2 * r * a.nx] = cl[r];
+          cr[(2 * r + 1) * a.nx] = r + 1 < R ? v[16 * (r + 1)] : din * a.closure;
+        }
+      }
+      return;
+    }
     anticausal_carry<Q, FULL>(v, len, din * a.closure);
   }
 
@@ -401,6 +436,133 @@ __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
   for (int i = 0; i < Q; ++i) {
     if (FULL || i < len) *o = kGain * v[i];
     o += a.sa;
+  }
+}
+
+// ------------------------------------------------ fused y + x lines ---
+// The y pass and the padded x pass of the forward solve in one read and one
+// write of the field.  A carries-only y pass (solve_lines with a.carry) has
+// stored the states entering every run of QY rows from either side; a
+// workgroup of nx = 64 W threads then takes one run of one plane: thread x
+// solves its column of the run along y in registers (the recursions of the
+// y pass, started from the stored states), and the rows go through LDS W at
+// a time, one wave per row, for the periodic x solve of solve_rows and the
+// padded stores.  The arithmetic is that of the two separate passes, with
+// the y recursions restarted at every
+// run of QY rows from the carries stored there.
+struct YXArgs {
+  const float* in;     // plain [planes][ny][nx] (z-solved field)
+  const float* carry;  // [planes][K][2][nx] from the carries-only y pass
+  void* out;           // padded coefficients
+  int nx, ny, nz;      // nz: grid planes (for the wrapped z copies with zpad)
+  int K;               // chunks per y line (QY rows each)
+  int pitch;           // LDS floats per row slot
+  int zpad;            // as RowArgs::zpad
+};
+
+template <int W, int QY, typename T>
+__global__ __launch_bounds__(1024) void solve_yx(YXArgs a) {
+  extern __shared__ float lds[];
+  constexpr int QX = W;  // x points per lane: nx = 64 W
+  constexpr int J = QX + 1;
+  const int x = threadIdx.x, lane = x & 63, wid = x >> 6;
+  const int k = blockIdx.x, z = blockIdx.y;
+  const int nx = a.nx, px = nx + 3;
+  const int64_t py = a.ny + 3;
+
+  float v[QY];
+  {
+    const float* src = a.in + ((int64_t)z * a.ny + (int64_t)k * QY) * nx + x;
+#pragma unroll
+    for (int i = 0; i < QY; ++i) v[i] = src[(int64_t)i * nx];
+    const float* cr = a.carry + ((int64_t)z * a.K + k) * 2 * nx + x;
+    const float cin = cr[0], din = cr[nx];
+    causal_local<QY, true>(v, QY);
+    causal_carry<QY, true>(v, QY, cin);
+    anticausal_local<QY>(v);
+    anticausal_carry<QY, true>(v, QY, din);
+  }
+
+  float* L = lds + wid * a.pitch;
+  const int m0 = lane * QX;
+#pragma unroll
+  for (int bt = 0; bt < QY / W; ++bt) {
+#pragma unroll
+    for (int r = 0; r < W; ++r) lds[r * a.pitch + lds_ix(x)] = kGain * v[bt * W + r];
+    __syncthreads();
+    const int y = k * QY + bt * W + wid;
+
+    // the periodic x solve of row (y, z), as in solve_rows
+    float u[QX];
+#pragma unroll
+    for (int i = 0; i < QX; ++i) u[i] = L[lds_ix(m0 + i)];
+    float a_len = 1.0f;
+#pragma unroll
+    for (int i = 0; i < QX; ++i) a_len *= kZ1;
+    const float e = causal_local<QX, false>(u, QX);
+    float sa = a_len, se = e;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const float pa = __shfl_up(sa, d), pe = __shfl_up(se, d);
+      if (lane >= d) {
+        se = sa * pe + se;
+        sa = sa * pa;
+      }
+    }
+    {
+      const float A = __shfl(sa, 63), B = __shfl(se, 63);
+      const float C0 = B / (1.0f - A);
+      const float pa = __shfl_up(sa, 1), pe = __shfl_up(se, 1);
+      causal_carry<QX, false>(u, QX, lane == 0 ? C0 : pa * C0 + pe);
+    }
+    const float f = anticausal_local<QX>(u);
+    sa = a_len;
+    float sf = f;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const float pa = __shfl_down(sa, d), pf = __shfl_down(sf, d);
+      if (lane + d < 64) {
+        sf = sa * pf + sf;
+        sa = sa * pa;
+      }
+    }
+    {
+      const float A = __shfl(sa, 0), B = __shfl(sf, 0);
+      const float D0 = B / (1.0f - A);
+      const float pa = __shfl_down(sa, 1), pf = __shfl_down(sf, 1);
+      anticausal_carry<QX, false>(u, QX, lane == 63 ? D0 : pa * D0 + pf);
+    }
+    __syncthreads();  // every lane's reads of the row before the padded writes
+#pragma unroll
+    for (int i = 0; i < QX; ++i) {
+      const int xx = m0 + i;
+      const float sv = kGain * u[i];
+      L[lds_ix(xx + 1)] = sv;
+      const int xe = pad_extra(xx, nx);
+      if (xe >= 0) L[lds_ix(xe)] = sv;
+    }
+    __syncthreads();
+    float w[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int p = lane + 64 * j;
+      w[j] = p < px ? L[lds_ix(p)] : 0.0f;
+    }
+    const int ye = pad_extra(y, a.ny), ze = a.zpad ? pad_extra(z, a.nz) : -1;
+    const int Ys[2] = {y + 1, ye}, Zs[2] = {a.zpad ? z + 1 : z, ze};
+    for (int zc = 0; zc < 2; ++zc) {
+      if (Zs[zc] < 0) continue;
+      for (int yc = 0; yc < 2; ++yc) {
+        if (Ys[yc] < 0) continue;
+        const int64_t row = ((int64_t)Zs[zc] * py + Ys[yc]) * px;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const int p = lane + 64 * j;
+          if (p < px) put<T>(a.out, row + p, w[j]);
+        }
+      }
+    }
+    __syncthreads();  // the slots are refilled by the next batch
   }
 }
 
@@ -471,12 +633,13 @@ static bool line_shape(int na, int* Q, int* G, int* waves) {
 
 // axis 1 = y, axis 2 = z; plain layout in and out.
 static pt_status pass_lines(const float* in, float* out, int nx, int ny, int nz, int axis,
-                            hipStream_t s, int open = 0) {
+                            hipStream_t s, int open = 0, float* carry = nullptr) {
   LineArgs a;
   a.in = in;
   a.out = out;
   a.nx = nx;
   a.open = open;
+  a.carry = carry;
   int nb;
   if (axis == 1) {
     a.na = ny; nb = nz;
@@ -498,7 +661,17 @@ static pt_status pass_lines(const float* in, float* out, int nx, int ny, int nz,
   const int xblocks = (nx + G - 1) / G;
   const int full_x = (a.L == Q && a.K * a.L == a.na) ? nx / G : 0;
   const dim3 block(64 * waves);
-  TimedLaunch t(axis == 2 ? "spline_z" : "spline_y", s);
+  TimedLaunch t(carry ? "spline_y_carry" : (axis == 2 ? "spline_z" : "spline_y"), s);
+  if (carry) {
+    if (full_x != xblocks) return PT_ERR_UNSUPPORTED;
+    a.bx0 = 0;
+    if (Q == 32)
+      hipLaunchKernelGGL((solve_lines<32, true, true>), dim3(full_x, nb), block, 0, s, a);
+    else
+      hipLaunchKernelGGL((solve_lines<64, true, true>), dim3(full_x, nb), block, 0, s, a);
+    PT_LAUNCH_CHECK();
+    return PT_OK;
+  }
   if (full_x > 0) {
     a.bx0 = 0;
     if (Q == 32) hipLaunchKernelGGL((solve_lines<32, true>), dim3(full_x, nb), block, 0, s, a);
@@ -518,8 +691,79 @@ static float* align256f(float* p) {
   return (float*)(((uintptr_t)p + 255) & ~(uintptr_t)255);
 }
 
+// The fused y + x pass applies to rows of 256, 512 or 1024 points (one
+// thread per point) and y lines that line_shape cuts into whole chunks of 32
+// or 64 points; solve_yx takes runs of 16 rows (few enough registers for two
+// workgroups per compute unit).  *K, *QY: runs per line and rows per run.
+static bool yx_shape(int nx, int ny, int* K, int* QY) {
+  if (nx != 256 && nx != 512 && nx != 1024) return false;
+  int Q = 0, G = 0, waves = 0;
+  if (!line_shape(ny, &Q, &G, &waves)) return false;
+  const int k = waves * (64 / G), L = (ny + k - 1) / k;
+  if (L != Q || k * L != ny || Q % 16 != 0) return false;
+  *K = ny / 16;
+  *QY = 16;
+  return true;
+}
+
+// Carry floats of the fused pass over `planes` planes (0 if it does not apply).
+static size_t yx_carry_floats(const pt_grid* g, int planes) {
+  int K = 0, QY = 0;
+  if (!yx_shape(g->nx, g->ny, &K, &QY)) return 0;
+  return 2 * (size_t)K * g->nx * planes;
+}
+
+template <typename F>
+static bool allow_lds(F* fn, size_t bytes) {
+  return hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes) == hipSuccess;
+}
+
+// y then x of `planes` planes of in (plain, z-solved) into the padded out:
+// the carries-only y pass into carry, then solve_yx.
+static pt_status pass_yx(const float* in, float* carry, void* out, bool bf16, int nx, int ny,
+                         int planes, int nz, int zpad, hipStream_t s) {
+  int K = 0, QY = 0;
+  if (!yx_shape(nx, ny, &K, &QY)) return PT_ERR_UNSUPPORTED;
+  pt_status st = pass_lines(in, nullptr, nx, ny, planes, 1, s, 0, carry);
+  if (st != PT_OK) return st;
+  YXArgs a;
+  a.in = in;
+  a.carry = carry;
+  a.out = out;
+  a.nx = nx; a.ny = ny; a.nz = nz;
+  a.K = K;
+  a.zpad = zpad;
+  const int px = nx + 3;
+  a.pitch = px + (px >> 4) + 1;
+  const int W = nx / 64;
+  const size_t lds = (size_t)W * a.pitch * 4;
+  const dim3 grid(K, planes);
+  TimedLaunch t("spline_yx_pad", s);
+#define PT_YX(WW, QQ, TT)                                                             \
+  do {                                                                                \
+    if (!allow_lds(solve_yx<WW, QQ, TT>, lds)) return PT_ERR_HIP;                     \
+    hipLaunchKernelGGL((solve_yx<WW, QQ, TT>), grid, dim3(nx), lds, s, a);            \
+  } while (0)
+#define PT_YX_W(QQ, TT)                  \
+  do {                                   \
+    if (W == 4) PT_YX(4, QQ, TT);        \
+    else if (W == 8) PT_YX(8, QQ, TT);   \
+    else PT_YX(16, QQ, TT);              \
+  } while (0)
+  if (QY != 16) return PT_ERR_UNSUPPORTED;
+  if (bf16) PT_YX_W(16, uint16_t);
+  else PT_YX_W(16, float);
+#undef PT_YX_W
+#undef PT_YX
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
 size_t spline_ws_floats(const pt_grid* g, pt_dtype dtype) {
   const size_t n3 = (size_t)g->nx * g->ny * g->nz;
+  const size_t cf = yx_carry_floats(g, g->nz);
+  if (cf) return n3 + 64 + cf;  // z-solved field, then the y carries
   return dtype == PT_BF16 ? 2 * n3 : n3;
 }
 
@@ -528,8 +772,19 @@ pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype
   const int nx = g->nx, ny = g->ny, nz = g->nz;
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int64_t p3 = (int64_t)(nx + 3) * (ny + 3) * (nz + 3);
+  const bool fused = yx_carry_floats(g, nz) > 0;
   for (int c = 0; c < 3; ++c) {
     const float* f = field + c * n3;
+    void* o = dtype == PT_F32 ? (void*)((float*)coeff + c * p3)
+                              : (void*)((uint16_t*)coeff + c * p3);
+    if (fused) {
+      // z pass into the workspace, then y and x in one pass into the output
+      pt_status st = pass_lines(f, ws, nx, ny, nz, 2, s);
+      if (st != PT_OK) return st;
+      st = pass_yx(ws, align256f(ws + n3), o, dtype == PT_BF16, nx, ny, nz, nz, 1, s);
+      if (st != PT_OK) return st;
+      continue;
+    }
     // z pass into a scratch array, y pass, then the x pass writes the padded
     // coefficients.  For FP32 output the component's own output block (read
     // by the y pass before the x pass overwrites it) is the first scratch,
@@ -541,8 +796,6 @@ pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype
     if (st != PT_OK) return st;
     st = pass_lines(t1, t2, nx, ny, nz, 1, s);
     if (st != PT_OK) return st;
-    void* o = dtype == PT_F32 ? (void*)((float*)coeff + c * p3)
-                              : (void*)((uint16_t*)coeff + c * p3);
     st = pass_rows(t2, o, nx, ny, nz, dtype == PT_F32 ? ROW_PAD_F32 : ROW_PAD_BF16, s);
     if (st != PT_OK) return st;
   }
@@ -550,7 +803,9 @@ pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype
 }
 
 size_t spline_slab_ws_floats(const pt_grid* g, int nzl, int W) {
-  return (size_t)g->nx * g->ny * (size_t)(nzl + 3 + 2 * W);
+  const size_t planes = (size_t)(nzl + 3 + 2 * W);
+  const size_t cf = yx_carry_floats(g, (int)planes);
+  return (size_t)g->nx * g->ny * planes + (cf ? 64 + cf : 0);
 }
 
 // field: planes z0-1-W .. z0+nzl+1+W of the periodic field (nzl + 3 + 2W),
@@ -562,18 +817,25 @@ pt_status spline_slab_fwd(const pt_grid* g, int nzl, int W, const float* field, 
   const int64_t plane = (int64_t)nx * ny;
   const int64_t pb = (int64_t)(nx + 3) * (ny + 3) * nzo;  // output block per component
   for (int c = 0; c < 3; ++c) {
-    // z with open ends over all nzi planes into the workspace, y in place on
-    // the nzo central planes (a line pass reads all of its lines before it
-    // writes any, and workgroups own disjoint lines), then the x pass writes
-    // padded rows (y padding only: the planes are padded z planes already).
+    // z with open ends over all nzi planes into the workspace, then y and x
+    // of the nzo central planes: fused where solve_yx applies, else y in
+    // place (a line pass reads all of its lines before it writes any, and
+    // workgroups own disjoint lines) and the x pass; the padded rows get y
+    // padding only (the planes are padded z planes already).
     float* t = ws;
     pt_status st = pass_lines(field + c * plane * nzi, t, nx, ny, nzi, 2, s, 1);
     if (st != PT_OK) return st;
     float* mid = t + plane * W;
-    st = pass_lines(mid, mid, nx, ny, nzo, 1, s);
-    if (st != PT_OK) return st;
     void* o = dtype == PT_F32 ? (void*)((float*)coeff + c * pb)
                               : (void*)((uint16_t*)coeff + c * pb);
+    if (yx_carry_floats(g, nzi) > 0) {
+      st = pass_yx(mid, align256f(t + plane * nzi), o, dtype == PT_BF16, nx, ny, nzo, nzo, 0,
+                   s);
+      if (st != PT_OK) return st;
+      continue;
+    }
+    st = pass_lines(mid, mid, nx, ny, nzo, 1, s);
+    if (st != PT_OK) return st;
     st = pass_rows(mid, o, nx, ny, nzo, dtype == PT_F32 ? ROW_PAD_F32 : ROW_PAD_BF16, s, 0);
     if (st != PT_OK) return st;
   }

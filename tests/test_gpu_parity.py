@@ -78,9 +78,12 @@ SHAPES = [(32, 32, 32), (45, 37, 20), (4, 4, 4), (64, 64, 64), (100, 6, 33)]
 # per lane; y/z lines split over lane groups of 32, 16 and 8 x-points)
 LONG_SHAPES = [(7, 1100, 5), (5, 6, 2500), (4100, 4, 5), (2049, 4, 4), (4, 4, 8192),
                (65, 1025, 4)]
+# rows of 256, 512 and 1024 points with y lines of whole 32-row chunks: the
+# fused y + x pass (one to 64 chunks per line, lane groups of 64 to 16)
+FUSED_SHAPES = [(256, 96, 9), (512, 32, 5), (1024, 64, 4), (1024, 1024, 4), (256, 2048, 4)]
 
 
-@pytest.mark.parametrize("shape", SHAPES + LONG_SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + LONG_SHAPES + FUSED_SHAPES)
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_spline_coeffs_parity(pt, shape, dtype):
     import torch

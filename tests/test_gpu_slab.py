@@ -14,7 +14,9 @@ pytestmark = pytest.mark.gpu
 # (grid, first plane z0, planes nzl, halo): slabs at the start, inside and
 # wrapping around the end of z, a halo longer than the grid, ragged sizes
 SLABS = [((64, 48, 96), 0, 16, 16), ((64, 48, 96), 40, 32, 16), ((64, 48, 96), 90, 20, 16),
-         ((100, 70, 300), 250, 64, 16), ((33, 40, 37), 30, 5, 40), ((4, 5, 6), 2, 3, 14)]
+         ((100, 70, 300), 250, 64, 16), ((33, 40, 37), 30, 5, 40), ((4, 5, 6), 2, 3, 14),
+         # fused y + x pass (rows of 256 and 1024 points)
+         ((256, 64, 40), 10, 8, 14), ((1024, 32, 30), 25, 6, 14)]
 
 
 def _slab_inputs(f, z0, nzl, halo):
