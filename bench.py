@@ -75,10 +75,10 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step):
         "spline_x": 8 * n3, "spline_y": 8 * n3, "spline_z": 8 * n3,
         "spline_x_pad": 4 * n3 + cb * p3,
         "spline_x_fold": 4 * p3 + 4 * n3,
-        # fused y + x: the y lines' chunk carries (2 floats per 32 rows) are
+        # fused y + x: the y lines' run carries (2 floats per 16 rows) are
         # written by the first pass and read by the second
-        "spline_y_carry": 4 * n3 + 8 * n3 // 32,
-        "spline_yx_pad": 4 * n3 + 8 * n3 // 32 + cb * p3,
+        "spline_y_carry": 4 * n3 + 8 * n3 // 16,
+        "spline_yx_pad": 4 * n3 + 8 * n3 // 16 + cb * p3,
         "sort_keys": np_ * (24 + kb + 4),
         "sort_pass": np_ * 2 * (kb + 4),
         "sort_permute": np_ * (4 + 24 + 24),
