@@ -11,7 +11,7 @@
 // planes at item ends).
 //
 // tile_gather: both Heun stages (forward) or the step adjoint's gather half
-// (backward) per particle.  Two loader waves fill the ring with direct
+// (backward) per particle.  Four loader waves fill the ring with direct
 // global-to-LDS loads several planes ahead; eight compute waves evaluate the
 // particles of the current slab of layers, four lanes per point.  Points
 // whose stencil is not in the ring (the predictor left the column or moved
@@ -147,8 +147,8 @@ __device__ __forceinline__ void eval_global(const CT* __restrict__ coeff, const 
 
 // ------------------------------------------------------- gather kernels ---
 // The gather ring holds kGRing dense planes [3][kTileY+3][kTileX+3] of 32-bit
-// words (FP32 values, or BF16 bits in the low half).  Two loader waves fill it
-// with direct global-to-LDS loads; eight compute waves only read it.  The
+// words (FP32 values, or BF16 bits in the low half).  Four loader waves fill
+// it with direct global-to-LDS loads; eight compute waves only read it.  The
 // load queue of a wave retires in order, so keeping the plane loads in waves
 // of their own means the compute waves never wait on them, and the loaders
 // wait for exactly their own loads before the barrier that publishes them.
@@ -158,7 +158,11 @@ constexpr int kGComp = kGTW * kGTH;            // 1225 words per component
 constexpr int kGSlot = 3 * kGComp + 13;        // slot pitch (words), 40 mod 64
 static_assert(kGSlot % 64 == 40, "planes of one stencil in distinct LDS banks");
 constexpr int kCompute = 512;                  // compute threads (8 waves)
-constexpr int kLoaders = 2;                    // loader waves
+// Loader waves: a wave has at most 63 memory operations in flight, so the
+// plane loads in flight per compute unit grow with the loader count; 4 (one
+// per SIMD) measured best (2 and 3 slower or equal; 5 and more leave the
+// compute waves too few registers).
+constexpr int kLoaders = 4;
 constexpr int kGTB = kCompute + 64 * kLoaders;
 constexpr int kGChunks = (kGComp + 63) / 64;   // 64-word chunks per component (20)
 constexpr int kGChunksPerLoader = (kGChunks + kLoaders - 1) / kLoaders;
