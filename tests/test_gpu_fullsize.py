@@ -14,7 +14,8 @@ full with the plain oracle.
     of the whole 1024^3 field on the host), each step launched as the
     benchmark launches it (one sort, then the step on the sorted particles);
     for FP32, the adjoint of the last step at 256 sampled particles and 64
-    sampled coefficient points;
+    sampled coefficient points, and the adjoint of the solve at 200 sampled
+    grid points;
   2048^3, 256M uniform particles (64-bit sort keys): sort, the 12-output
     gather on the sorted particles and one sorted Heun step, sampled;
   256^3, 1M particles: L = sum |x(8)|^2 through TrackParticles (checkpoints
@@ -233,6 +234,51 @@ def _check_c3_adjoint(og, rc, dt, adj):
     assert np.abs(ref).max() > 0
     err = normwise(adj["gco"], ref)
     log(f"c3 f32: adjoint dL/dS error (64 sampled coefficients) {err:.3e}")
+    assert err < F32_TOL
+
+
+def _fold_axis(t, dim, n):
+    """Sum of the padded copies along one axis: padded index P holds grid
+    point (P - 1) mod n (P = 0 -> n - 1, P = n + 1 -> 0, P = n + 2 -> 1)."""
+    core = t.narrow(dim, 1, n).clone()
+    core.narrow(dim, n - 1, 1).add_(t.narrow(dim, 0, 1))
+    core.narrow(dim, 0, 1).add_(t.narrow(dim, n + 1, 1))
+    core.narrow(dim, 1, 1).add_(t.narrow(dim, n + 2, 1))
+    return core
+
+
+def test_c3_1024_spline_adjoint_sampled(pt):
+    """The adjoint of the 1024^3 solve as the benchmark runs it: with A
+    symmetric it is the periodic inverse applied to the folded gradient, so
+    the windowed closed-form oracle of the solve, applied to the fold of the
+    same gradient, gives it at sampled grid points."""
+    import torch
+    n = 1024
+    if free_bytes() < 64 * 2 ** 30:
+        pytest.skip("needs 64 GiB of free device memory")
+    dev = torch.device("cuda:0")
+    g = pt.Grid(n)
+    gen = torch.Generator(device=dev).manual_seed(17)
+    G = torch.randn(g.padded_shape, generator=gen, dtype=torch.float32, device=dev)
+    gf = pt.spline_coeffs_bwd(g, G)
+    torch.cuda.synchronize()
+    F = _fold_axis(_fold_axis(_fold_axis(G, 1, n), 2, n), 3, n)
+    del G
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(23)
+    pts = rng.integers(0, n, size=(3, 200))
+    pts[:, :8] = [[0, 1, n - 1, 0, n - 1, 1, 2, n - 2]] * 3  # points with padded copies
+    got = gf[:, torch.from_numpy(pts[2]).to(dev), torch.from_numpy(pts[1]).to(dev),
+             torch.from_numpy(pts[0]).to(dev)].double().cpu().numpy()
+    del gf
+    torch.cuda.empty_cache()
+    log("c3: spline adjoint done; host copy of the folded gradient")
+    Fh = field_to_host(F)
+    del F
+    torch.cuda.empty_cache()
+    ref = oracle.coeffs_at(Fh, pts)
+    err = normwise(got, ref)
+    log(f"c3: spline adjoint error (200 sampled points) {err:.3e}")
     assert err < F32_TOL
 
 
