@@ -55,7 +55,7 @@ def log(*a):
 
 
 KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold",
-           "spline_y_carry", "spline_yx_pad", "sort_keys",
+           "spline_y_carry", "spline_yx_pad", "sorted_table", "sort_keys",
            "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter",
            "tile_tv_stage1", "tile_tv_stage2")
 
@@ -82,6 +82,8 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step):
         "sort_keys": np_ * (24 + kb + 4),
         "sort_pass": np_ * 2 * (kb + 4),
         "sort_permute": np_ * (4 + 24 + 24),
+        # the particle table of positions already in cell order
+        "sorted_table": np_ * 24,
         # x in, x_out out; field once
         "tile_rk2_fwd": 3 * p3 * cb + np_ * 48,
         # x, lambda in; dL/dx_n, stage-1 velocity and its adjoint out

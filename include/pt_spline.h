@@ -280,8 +280,10 @@ const char *pt_status_string(pt_status status);
  * of `kernel`, returns their summed elapsed time and count, and forgets them.
  * Kernel names: "spline_x", "spline_y", "spline_z", "spline_x_pad" (the x
  * pass that writes the padded coefficients), "spline_x_fold" (the adjoint's
- * x pass that reads the padded gradient),
- * "sort_keys", "sort_pass", "sort_permute", "tile_rk2_fwd",
+ * x pass that reads the padded gradient), "spline_y_carry" and
+ * "spline_yx_pad" (the forward's fused y + x pass and the y pass that feeds
+ * it its carries), "sort_keys", "sort_pass", "sort_permute",
+ * "sorted_table" (the particle table of PT_SORTED), "tile_rk2_fwd",
  * "tile_rk2_bwd_gather", "tile_scatter", "tile_tv_stage1", "tile_tv_stage2",
  * "interp". */
 pt_status pt_timing_enable(int on);

@@ -24,7 +24,7 @@ pt_status spline_bwd(const pt_grid* g, const float* gcoeff, float* gfield, float
 int key_bits(const pt_grid* g);
 size_t sort_ws_bytes(const pt_grid* g, int64_t np);
 pt_status presorted_table(const pt_grid* g, int64_t np, const double* pos, int32_t* lstart,
-                          void* ws, hipStream_t s);
+                          hipStream_t s);
 pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double* pos_sorted,
                          int32_t* perm, uint64_t* keys_out, int32_t* lstart, void* ws,
                          hipStream_t s);
@@ -346,7 +346,7 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
                         false, stream);
   }
   if (sort == PT_SORTED) {
-    PT_TRY(presorted_table(grid, np, pos, w.lstart, w.sort, stream));
+    PT_TRY(presorted_table(grid, np, pos, w.lstart, stream));
     return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, pos, pos, w.defer, w.items, true,
                         stream);
   }
@@ -433,7 +433,7 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
     return scatter_back(np, w.xbn, w.perm, g_pos, stream);
   }
   if (sort == PT_SORTED) {
-    PT_TRY(presorted_table(grid, np, pos_n, w.lstart, w.sort, stream));
+    PT_TRY(presorted_table(grid, np, pos_n, w.lstart, stream));
     PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, pos_n, g_pos, w.xbn, w.u0, w.ub0,
                         g_coeff, w.defer, w.items, true, stream));
     PT_HIP_CHECK(hipMemcpyAsync(g_pos, w.xbn, 24 * (size_t)np, hipMemcpyDeviceToDevice, stream));

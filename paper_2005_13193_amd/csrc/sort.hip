@@ -25,6 +25,20 @@ constexpr int kSortTile = kSortThreads * kSortRounds;   // elements per tile
 constexpr int kScanItems = 8;             // per thread in the scan kernels
 constexpr int kScanBlock = 256 * kScanItems;
 
+// Cell key of particle i (see pt_key_layout): column, layer, row, column
+// offset; *bad is set for a non-finite coordinate.
+template <typename K>
+__device__ __forceinline__ K cell_key(const GridDev& g, int64_t np,
+                                      const double* __restrict__ pos, int64_t i, bool* bad) {
+  double t;
+  const int a = cell_1d(pos[i], g.cs[0], g.nx, &t, bad);
+  const int b = cell_1d(pos[np + i], g.cs[1], g.ny, &t, bad);
+  const int c = cell_1d(pos[2 * np + i], g.cs[2], g.nz, &t, bad);
+  const K ncx = (K)((g.nx + kTileX - 1) / kTileX);
+  return ((((K)(b / kTileY) * ncx + (K)(a / kTileX)) * (K)g.nz + (K)c) * (K)kTileY +
+          (K)(b % kTileY)) * (K)kTileX + (K)(a % kTileX);
+}
+
 template <typename K>
 __global__ __launch_bounds__(256) void cell_key_kernel(GridDev g, int64_t np,
                                                        const double* __restrict__ pos,
@@ -33,16 +47,42 @@ __global__ __launch_bounds__(256) void cell_key_kernel(GridDev g, int64_t np,
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= np) return;
   bool bad = false;
-  double t;
-  const int a = cell_1d(pos[i], g.cs[0], g.nx, &t, &bad);
-  const int b = cell_1d(pos[np + i], g.cs[1], g.ny, &t, &bad);
-  const int c = cell_1d(pos[2 * np + i], g.cs[2], g.nz, &t, &bad);
-  if (bad) *err = 1;
-  const K ncx = (K)((g.nx + kTileX - 1) / kTileX);
-  const K key = ((((K)(b / kTileY) * ncx + (K)(a / kTileX)) * (K)g.nz + (K)c) * (K)kTileY +
-                 (K)(b % kTileY)) * (K)kTileX + (K)(a % kTileX);
-  keys[i] = key;
+  keys[i] = cell_key<K>(g, np, pos, i, &bad);
   vals[i] = (uint32_t)i;
+  if (bad) *err = 1;
+}
+
+// The half-layer (column, layer, upper or lower 16 rows) of a key: the
+// particle table's index.
+constexpr int kHalfLayerShift = 9;  // log2(kTileX * kTileY / 2)
+static_assert(kTileX * kTileY == (2 << kHalfLayerShift), "half-layer shift");
+
+// Particle table straight from positions taken to be in cell order: entry
+// L is the first particle of half-layer L or later (np past the last one).
+// Thread i compares the half-layers of particles i - 1 and i (each thread
+// forms one, the neighbour's comes through LDS; the first thread of a block
+// forms its predecessor's itself).  For positions not in order some entries
+// are left as they were; the table's users check it before trusting it.
+template <typename K>
+__global__ __launch_bounds__(256) void sorted_layer_table(GridDev g, int64_t np,
+                                                          const double* __restrict__ pos,
+                                                          int64_t nlayers,
+                                                          int32_t* __restrict__ ls, int* err) {
+  __shared__ int64_t s_half[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool bad = false;
+  const int64_t lcur =
+      i < np ? (int64_t)(cell_key<K>(g, np, pos, i, &bad) >> kHalfLayerShift) : nlayers;
+  s_half[threadIdx.x] = lcur;
+  __syncthreads();
+  if (i > np) return;
+  int64_t lprev = -1;
+  if (i > 0) {
+    lprev = threadIdx.x > 0 ? s_half[threadIdx.x - 1]
+                            : (int64_t)(cell_key<K>(g, np, pos, i - 1, &bad) >> kHalfLayerShift);
+  }
+  if (bad) *err = 1;
+  for (int64_t L = lprev + 1; L <= lcur && L <= nlayers; ++L) ls[L] = (int32_t)i;
 }
 
 // Lanes holding the same 8-bit digit: AND of the ballots of each bit (or of
@@ -297,6 +337,8 @@ int key_bits(const pt_grid* g) {
 
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+int64_t tile_nlayers(const pt_grid* g);  // tile.hip: half-layers of the particle table
+
 struct SortWs {
   void* keys[2];
   uint32_t* vals0;
@@ -376,28 +418,23 @@ static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int3
   return PT_OK;
 }
 
-// The particle table of positions that should already be in cell order:
-// their keys, then the table built from them as if sorted.  For positions
-// that are not in order the table is garbage; its users check it on the
-// device before trusting it.
-template <typename K>
-static pt_status table_impl(const pt_grid* g, int64_t np, const double* pos, int32_t* lstart,
-                            void* ws, hipStream_t s) {
-  const GridDev gd = make_grid_dev(g);
-  SortWs w = carve_sort_ws(g, np, ws);
-  {
-    TimedLaunch t("sort_keys", s);
-    hipLaunchKernelGGL(cell_key_kernel<K>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd, np, pos,
-                       (K*)w.keys[0], w.vals0, device_error_flag());
-  }
-  PT_LAUNCH_CHECK();
-  return build_layer_table(g, np, w.keys[0], (int)sizeof(K), lstart, s);
-}
-
+// The particle table of positions that should already be in cell order,
+// built from the positions in one pass.  For positions that are not in order
+// the table is not a partition; its users check it on the device before
+// trusting it.
 pt_status presorted_table(const pt_grid* g, int64_t np, const double* pos, int32_t* lstart,
-                          void* ws, hipStream_t s) {
-  return key_bits(g) > 32 ? table_impl<uint64_t>(g, np, pos, lstart, ws, s)
-                          : table_impl<uint32_t>(g, np, pos, lstart, ws, s);
+                          hipStream_t s) {
+  const GridDev gd = make_grid_dev(g);
+  const int64_t nl = tile_nlayers(g);
+  TimedLaunch t("sorted_table", s);
+  if (key_bits(g) > 32)
+    hipLaunchKernelGGL(sorted_layer_table<uint64_t>, dim3(grid_1d(np + 1, 256)), dim3(256), 0, s,
+                       gd, np, pos, nl, lstart, device_error_flag());
+  else
+    hipLaunchKernelGGL(sorted_layer_table<uint32_t>, dim3(grid_1d(np + 1, 256)), dim3(256), 0, s,
+                       gd, np, pos, nl, lstart, device_error_flag());
+  PT_LAUNCH_CHECK();
+  return PT_OK;
 }
 
 pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double* pos_sorted,

@@ -1100,12 +1100,18 @@ __global__ __launch_bounds__(256) void check_table(const int32_t* __restrict__ l
 
 // The scatter's counterpart: after a failed check every stencil (2 p + stage)
 // is deferred.
+// Both fallbacks run on a fixed grid (grid-stride loops): they are launched
+// on every call and almost always find the flag clear.
+constexpr int kFallbackBlocks = 1024;
+
 __global__ __launch_bounds__(256) void scatter_fallback(int* header, uint32_t* __restrict__ list,
                                                         int64_t np) {
   if (header[kTableBad] == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < 2 * np) list[i] = (uint32_t)i;
-  if (i == 0) header[0] = (int)(2 * np < 0x7fffffff ? 2 * np : 0x7fffffff);
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 2 * np; i += stride)
+    list[i] = (uint32_t)i;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    header[0] = (int)(2 * np < 0x7fffffff ? 2 * np : 0x7fffffff);
 }
 
 // After a failed check: empty every layer and put every particle on the
@@ -1114,10 +1120,12 @@ __global__ __launch_bounds__(256) void table_fallback(int32_t* __restrict__ ls, 
                                                       int64_t np, int* header,
                                                       int32_t* __restrict__ list) {
   if (header[kTableBad] == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i <= nl) ls[i] = 0;
-  if (i < np) list[i] = (int32_t)i;
-  if (i == 0) header[0] = (int)np;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i <= nl || i < np; i += stride) {
+    if (i <= nl) ls[i] = 0;
+    if (i < np) list[i] = (int32_t)i;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) header[0] = (int)np;
 }
 
 // ------------------------------------------------------- layer table ---
@@ -1444,10 +1452,9 @@ static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int
   PT_LAUNCH_CHECK();
   if (check) {
     const int64_t nl = tile_nlayers(g);
-    const int64_t n = (nl + 1 > a.np ? nl + 1 : a.np);
     hipLaunchKernelGGL(check_table, dim3(grid_1d(nl + 1, 256)), dim3(256), 0, s, a.lstart, nl,
                        a.np, a.defer_count + kTableBad);
-    hipLaunchKernelGGL(table_fallback, dim3(grid_1d(n, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(table_fallback, dim3(kFallbackBlocks), dim3(256), 0, s,
                        (int32_t*)a.lstart, nl, a.np, a.defer_count, (int32_t*)a.defer);
     PT_LAUNCH_CHECK();
   }
@@ -1552,7 +1559,7 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   if (check) {
     // a table the gather found invalid was emptied: every stencil goes to
     // the deferred list
-    hipLaunchKernelGGL(scatter_fallback, dim3(grid_1d(2 * np, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(scatter_fallback, dim3(kFallbackBlocks), dim3(256), 0, s,
                        b.defer_count, b.defer, np);
     PT_LAUNCH_CHECK();
   }
