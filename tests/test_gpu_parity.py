@@ -228,7 +228,7 @@ def test_interp_bwd_parity(pt):
 
 
 @pytest.mark.parametrize("shape", [(32, 32, 32), (45, 37, 20), (4, 5, 6), (4, 4, 4),
-                                   (100, 6, 33)] + LONG_SHAPES)
+                                   (100, 6, 33)] + LONG_SHAPES + FUSED_SHAPES)
 def test_spline_bwd_parity(pt, shape):
     nx, ny, nz = shape
     rng = np.random.default_rng(11)
