@@ -53,8 +53,8 @@ pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
 size_t tile_items_bytes(const pt_grid* g, int64_t np, bool scatter);
 pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, const double* lam, double* xbn,
-                       float* u0, float* ub0, float* gcoeff, void* defer, void* items_ws,
-                       bool check, hipStream_t s);
+                       float* u0, float* ub0, float* ub1, float* gcoeff, void* defer,
+                       void* items_ws, bool check, hipStream_t s);
 size_t tile_defer_bytes(int64_t np);
 pt_status tile_tv_stage1(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                          int64_t np, const double* x, double* x_out, float* u_n, void* defer,
@@ -173,7 +173,7 @@ struct Rk2BwdWs {
   double* pos_sorted;
   int32_t* perm;
   double* xbn;
-  double* xbs;
+  double* xbs;   // direct path; the tiled paths keep ub1 (12 bytes/particle) here
   float* u0;
   float* ub0;
   int32_t* lstart;
@@ -429,15 +429,14 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
     PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
                           stream));
     PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, g_pos, w.xbn, w.u0,
-                        w.ub0, g_coeff, w.defer, w.items, false, stream));
+                        w.ub0, (float*)w.xbs, g_coeff, w.defer, w.items, false, stream));
     return scatter_back(np, w.xbn, w.perm, g_pos, stream);
   }
   if (sort == PT_SORTED) {
+    // the order is kept, so dL/dx_n goes straight into g_pos
     PT_TRY(presorted_table(grid, np, pos_n, w.lstart, stream));
-    PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, pos_n, g_pos, w.xbn, w.u0, w.ub0,
-                        g_coeff, w.defer, w.items, true, stream));
-    PT_HIP_CHECK(hipMemcpyAsync(g_pos, w.xbn, 24 * (size_t)np, hipMemcpyDeviceToDevice, stream));
-    return PT_OK;
+    return tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, pos_n, g_pos, g_pos, w.u0, w.ub0,
+                        (float*)w.xbs, g_coeff, w.defer, w.items, true, stream);
   }
   return rk2_backward(grid, coeff, dtype, np, dt, pos_n, g_pos, g_pos, g_coeff, w.u0, w.xbs,
                       stream);

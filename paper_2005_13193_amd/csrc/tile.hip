@@ -54,6 +54,7 @@ struct TileArgs {
   double* xbn;            // bwd: dL/dx_n    [3][np]
   float* u0;              // bwd: stage-1 velocity  [3][np]
   float* ub0;             // bwd: adjoint of stage-1 velocity [3][np]
+  float* ub1;             // bwd: adjoint of stage-2 velocity, dt/2 lam [3][np]
   float* gcoeff;          // scatter target (padded FP32)
   uint32_t* defer;        // scatter: deferred stencils (2 p + stage)
   int* defer_count;
@@ -265,7 +266,7 @@ __device__ __forceinline__ void load_pdata(const TileArgs& a, int64_t p, bool ok
 struct Pend {
   int64_t off;  // c * np + p for lane c < 3 of the quad, or -1
   double d;     // x_out (forward modes) or dL/dx_n (backward)
-  float f0, f1; // stage 1: u_n; backward: u0, ub0
+  float f0, f1, f2; // stage 1: u_n; backward: u0, ub0, ub1
   int defer;    // quad lane 0: particle to redo from global memory, or -1
 };
 
@@ -293,6 +294,7 @@ __device__ __forceinline__ void flush_pend(const TileArgs& a, Pend* o, DeferBatc
       a.xbn[o->off] = o->d;
       a.u0[o->off] = o->f0;
       a.ub0[o->off] = o->f1;
+      a.ub1[o->off] = o->f2;
     } else {
       if (MODE == TILE_TV_STAGE1) a.u0[o->off] = o->f0;
       a.x_out[o->off] = o->d;
@@ -415,6 +417,7 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
       o->d = lane == 0 ? xb[0] : lane == 1 ? xb[1] : xb[2];
       o->f0 = lane == 0 ? on[0] : lane == 1 ? on[1] : on[2];
       o->f1 = lane == 0 ? ub0[0] : lane == 1 ? ub0[1] : ub0[2];
+      o->f2 = lane == 0 ? ub1[0] : lane == 1 ? ub1[1] : ub1[2];
     }
   }
 }
@@ -707,6 +710,7 @@ __global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
                             (double)(ub0[0] * on[3 + c] + ub0[1] * on[6 + c] + ub0[2] * on[9 + c]);
         a.u0[c * np + p] = on[c];
         a.ub0[c * np + p] = ub0[c];
+        a.ub1[c * np + p] = ub1[c];
         m = fmaxf(m, fmaxf(fabsf(ub0[c]), fabsf(ub1[c])));
       }
       atomicMax(a.defer_count + 1 + (int)(p & (kMaxSlots - 1)), __float_as_int(m));
@@ -789,7 +793,7 @@ __device__ __forceinline__ void scatter_ring(long long* ring, const Pt& q, int X
 struct SData {
   double x[3];
   float u0[3];
-  double lam[3];  // ub1 = dt/2 lam is formed at use
+  float ub1[3];
   float ub0[3];
   int p;
   bool ok;
@@ -804,7 +808,7 @@ __device__ __forceinline__ void load_sdata(const TileArgs& a, int64_t p, bool ok
   for (int c = 0; c < 3; ++c) {
     d->x[c] = a.x[c * np + i];
     d->u0[c] = a.u0[c * np + i];
-    d->lam[c] = a.lam[c * np + i];
+    d->ub1[c] = a.ub1[c * np + i];
     d->ub0[c] = a.ub0[c * np + i];
   }
 }
@@ -856,7 +860,7 @@ __device__ __forceinline__ void scatter_one(const TileArgs& a, long long* ring, 
   for (int c = 0; c < 3; ++c) {
     xs[c] = d.x[c] + a.dt * (double)d.u0[c];
     s0[c] = d.ub0[c] * scale;
-    s1[c] = (float)(0.5 * a.dt * d.lam[c]) * scale;
+    s1[c] = d.ub1[c] * scale;
   }
   // cells with tile-local index in [0, kTileX + 2) x [0, kTileY/2 + 2) and
   // layers zz-1 .. zz+2 have their stencils inside the tile and the ring
@@ -1053,7 +1057,7 @@ __global__ __launch_bounds__(256) void scatter_deferred(TileArgs a) {
         gu[c] = a.ub0[c * np + p];
       } else {
         x[c] = xn + a.dt * (double)a.u0[c * np + p];
-        gu[c] = (float)(0.5 * a.dt * a.lam[c * np + p]);
+        gu[c] = a.ub1[c * np + p];
       }
     }
     bool bad = false;
@@ -1529,24 +1533,28 @@ pt_status tile_tv_stage2(const pt_grid* g, const void* coeff, pt_dtype dtype, in
 }
 
 // defer: tile_defer_bytes(np) bytes; items_ws: tile_items_bytes(g, np, false)
-// followed by tile_items_bytes(g, np, true) bytes.
+// followed by tile_items_bytes(g, np, true) bytes.  The gather writes u0,
+// ub0 and ub1 for the scatter, which then needs neither lam nor xbn: xbn may
+// alias lam (each particle's lam is read before its xbn is written, by the
+// same thread, in the gather or in gather_deferred).
 pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, const double* lam, double* xbn,
-                       float* u0, float* ub0, float* gcoeff, void* defer, void* items_ws,
-                       bool check, hipStream_t s) {
+                       float* u0, float* ub0, float* ub1, float* gcoeff, void* defer,
+                       void* items_ws, bool check, hipStream_t s) {
   TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
   a.x = x;
   a.lam = lam;
   a.xbn = xbn;
   a.u0 = u0;
   a.ub0 = ub0;
+  a.ub1 = ub1;
   pt_status st = launch_gather(g, a, dtype, TILE_RK2_BWD_GRAD, defer, items_ws, check, s);
   if (st != PT_OK || !gcoeff) return st;
   TileArgs b = tile_args(g, coeff, ls, np, dt, kScatterSeg);
   b.x = x;
-  b.lam = lam;
   b.u0 = u0;
   b.ub0 = ub0;
+  b.ub1 = ub1;
   b.gcoeff = gcoeff;
   b.defer_count = (int*)defer;
   b.defer = (uint32_t*)((char*)defer + kDeferHeader);
