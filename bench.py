@@ -86,11 +86,12 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step):
         "sorted_table": np_ * 24,
         # x in, x_out out; field once
         "tile_rk2_fwd": 3 * p3 * cb + np_ * 48,
-        # x, lambda in; dL/dx_n, stage-1 velocity and its adjoint out
-        "tile_rk2_bwd_gather": 3 * p3 * cb + np_ * 96,
+        # x, lambda in; dL/dx_n, stage-1 velocity and the adjoints of both
+        # stage velocities out
+        "tile_rk2_bwd_gather": 3 * p3 * cb + np_ * 108,
         # all colours of one step together: the FP32 gradient read and
-        # written once, x, u0, lambda, ub0 read once
-        "tile_scatter": (3 * p3 * 4 * 2 + np_ * 72) / launches_per_step,
+        # written once, x, u0, ub0, ub1 read once
+        "tile_scatter": (3 * p3 * 4 * 2 + np_ * 60) / launches_per_step,
         # x in, x (sorted order) and u^n out; field once
         "tile_tv_stage1": 3 * p3 * cb + np_ * 60,
         # x and u^n in, x out; field once
