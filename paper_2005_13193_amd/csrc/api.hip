@@ -480,8 +480,8 @@ pt_status pt_timing_read(const char* kernel, double* total_ms, int64_t* launches
       st = PT_ERR_HIP;
     sum += ms;
     ++n;
-    hipEventDestroy(r.start);
-    hipEventDestroy(r.stop);
+    if (hipEventDestroy(r.start) != hipSuccess || hipEventDestroy(r.stop) != hipSuccess)
+      st = PT_ERR_HIP;
   }
   g_time_recs.swap(keep);
   *total_ms = sum;
