@@ -405,8 +405,8 @@ def main():
                          "kernel for scaling HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has "
-              "no multi-GPU path", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library "
+              "has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
