@@ -82,7 +82,8 @@ enum {
   PT_OP_RK2 = 2,        /* pt_rk2_step (with or without sort) */
   PT_OP_SPLINE_BWD = 3, /* pt_spline_coeffs_bwd */
   PT_OP_RK2_BWD = 4,    /* pt_rk2_step_bwd (with or without sort) */
-  PT_OP_SPLINE_SLAB = 5 /* pt_spline_coeffs_slab; np = input planes nzl + 3 + 2 halo */
+  PT_OP_SPLINE_SLAB = 5, /* pt_spline_coeffs_slab; np = input planes nzl + 3 + 2 halo */
+  PT_OP_SLAB_PARTITION = 6 /* pt_slab_partition */
 };
 
 /* Bytes of workspace the operation needs for this grid, coefficient dtype
@@ -266,6 +267,28 @@ pt_status pt_rk2_step_bwd(const pt_grid *grid, const void *coeff, pt_dtype dtype
                           double *g_pos, float *g_coeff, void *ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* One device's part of the particle migration between sub-domains
+ * (Sec. 4.4): with the grid split into z-slabs, the particles that left this
+ * device's slab [z0, z0 + nzl) (cells modulo nz) are separated from the ones
+ * that stay, with all their attributes, and the gaps are closed.  The output
+ * is one stable partition [stay | lower | upper]: each particle's group comes
+ * from its shadow z cell c (as in pt_sort_particles), rel = (c - z0) mod nz;
+ * rel < nzl stays, otherwise it goes to the neighbouring slab below if
+ * nz - rel <= rel - nzl + 1 (the nearer side, ties below), else above.
+ * Inside each group the input order is kept.
+ *   pos      in   double [3][np];  ids  in int32 [np] or NULL
+ *   z0, nzl  in   0 <= z0 < nz, 1 <= nzl <= nz
+ *   pos_out  out  double [3][np], must not overlap pos
+ *   ids_out  out  int32 [np] (not read when ids is NULL)
+ *   counts   out  int64 [3] in device memory: stay, lower, upper
+ *   ws            >= pt_workspace_bytes(PT_OP_SLAB_PARTITION, ...) bytes
+ * A non-finite position keeps its particle in the slab and sets the flag
+ * pt_last_device_error() reports. */
+pt_status pt_slab_partition(const pt_grid *grid, int64_t np, const double *pos,
+                            const int32_t *ids, int32_t z0, int32_t nzl, double *pos_out,
+                            int32_t *ids_out, int64_t *counts, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
+
 /* Synchronises `stream`, then returns PT_ERR_NONFINITE if any kernel on the
  * current device met a non-finite position since the previous call (and
  * clears the flag), PT_ERR_HIP on a runtime error, else PT_OK. */
@@ -283,7 +306,8 @@ const char *pt_status_string(pt_status status);
  * x pass that reads the padded gradient), "spline_y_carry" and
  * "spline_yx_pad" (the forward's fused y + x pass and the y pass that feeds
  * it its carries), "sort_keys", "sort_pass", "sort_permute",
- * "sorted_table" (the particle table of PT_SORTED), "tile_rk2_fwd",
+ * "sorted_table" (the particle table of PT_SORTED), "slab_partition",
+ * "tile_rk2_fwd",
  * "tile_rk2_bwd_gather", "tile_scatter", "tile_tv_stage1", "tile_tv_stage2",
  * "interp". */
 pt_status pt_timing_enable(int on);

@@ -143,6 +143,28 @@ def sort_particles(grid, pos, tile_x, tile_y):
     return np.ascontiguousarray(pos[:, perm]), perm, key[perm]
 
 
+def slab_groups(grid, pos, z0, nzl):
+    """Group of each particle for the migration between z-slabs (Sec. 4.4):
+    0 stays in the slab [z0, z0 + nzl) (shadow z cells modulo nz), 1 goes to
+    the slab below, 2 to the slab above, whichever side is nearer (ties below)."""
+    cells, _, _ = cell_keys(grid, pos, 1, 1)
+    nz = grid.nz
+    rel = (cells[2].astype(np.int64) - z0) % nz
+    up = rel - nzl + 1      # cells above the slab's top layer
+    down = nz - rel         # cells below its bottom layer
+    return np.where(rel < nzl, 0, np.where(down <= up, 1, 2)).astype(np.int64)
+
+
+def slab_partition(grid, pos, ids, z0, nzl):
+    """[stay | lower | upper] with the input order kept inside each group:
+    (pos_out, ids_out, counts)."""
+    grp = slab_groups(grid, pos, z0, nzl)
+    order = np.argsort(grp, kind="stable")
+    counts = np.bincount(grp, minlength=3)
+    ids_out = None if ids is None else np.asarray(ids)[order]
+    return np.ascontiguousarray(np.asarray(pos)[:, order]), ids_out, counts
+
+
 def interp(grid, coeff, pos, n_out=3):
     """(u,v,w) [3][np] or (u,v,w, du_i/dx_j) [12][np] at the positions."""
     coeff, pos = _f64(coeff), _f64(pos)

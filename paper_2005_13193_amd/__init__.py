@@ -114,6 +114,22 @@ def sort_particles(grid, pos, want_keys=True, ids=None, ws=None):
     return pos_sorted, perm, keys
 
 
+def slab_partition(grid, pos, z0, nzl, ids=None, ws=None):
+    """Particles of the z-slab [z0, z0 + nzl) first, then those for the slab
+    below, then those for the slab above (stable).  Returns (pos_out,
+    ids_out or None, counts) with counts a host list [stay, lower, upper]."""
+    pos = pos.contiguous()
+    np_ = pos.shape[1]
+    dev = pos.device
+    pos_out = torch.empty_like(pos)
+    ids_out = torch.empty_like(ids) if ids is not None else None
+    counts = torch.zeros(3, dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = workspace(_b.PT_OP_SLAB_PARTITION, grid, np_, torch.float32, dev)
+    _b.pt_slab_partition(grid, pos, ids, z0, nzl, pos_out, ids_out, counts, ws)
+    return pos_out, ids_out, counts.tolist()
+
+
 def interp_uvw(grid, coeff, pos, out=None):
     pos = pos.contiguous()
     if out is None:

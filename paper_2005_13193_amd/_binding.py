@@ -32,10 +32,11 @@ PT_OP_RK2 = 2
 PT_OP_SPLINE_BWD = 3
 PT_OP_RK2_BWD = 4
 PT_OP_SPLINE_SLAB = 5
+PT_OP_SLAB_PARTITION = 6
 PT_UNSORTED, PT_SORT, PT_SORTED = 0, 1, 2  # sort argument of the RK2 steps
 
 EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_spline_coeffs_slab",
-           "pt_sort_particles",
+           "pt_sort_particles", "pt_slab_partition",
            "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_rk2_stage1", "pt_rk2_stage2",
            "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
@@ -69,6 +70,7 @@ def _load():
         "pt_spline_coeffs_slab": [g, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int, vp,
                                   sz, vp],
         "pt_sort_particles": [g, i64, vp, vp, vp, vp, vp, vp, sz, vp],
+        "pt_slab_partition": [g, i64, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp],
         "pt_interp_uvw": [g, vp, ctypes.c_int, i64, vp, vp, vp],
         "pt_interp_grad": [g, vp, ctypes.c_int, i64, vp, vp, vp],
         "pt_rk2_step": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
@@ -182,6 +184,19 @@ def pt_spline_coeffs_bwd(grid, g_coeff, g_field, ws, stream=None):
     _check("pt_spline_coeffs_bwd",
            LIB.pt_spline_coeffs_bwd(ctypes.byref(_grid(grid)), _ptr(g_coeff), _ptr(g_field),
                                     _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pt_slab_partition(grid, pos, ids, z0, nzl, pos_out, ids_out, counts, ws, stream=None):
+    np_ = pos.shape[1]
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(ids, torch.int32, (np_,), "ids")
+    _need(pos_out, torch.float64, (3, np_), "pos_out")
+    _need(ids_out, torch.int32, (np_,), "ids_out")
+    _need(counts, torch.int64, (3,), "counts")
+    _check("pt_slab_partition",
+           LIB.pt_slab_partition(ctypes.byref(_grid(grid)), np_, _ptr(pos), _ptr(ids), int(z0),
+                                 int(nzl), _ptr(pos_out), _ptr(ids_out), _ptr(counts), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def pt_sort_particles(grid, pos, pos_sorted, perm, ids, keys_out, ws, stream=None):

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpt_spline.so")
-SOURCES = ["api.hip", "solve.hip", "sort.hip", "gather.hip", "tile.hip"]
+SOURCES = ["api.hip", "solve.hip", "sort.hip", "gather.hip", "tile.hip", "migrate.hip"]
 ARCH = os.environ.get("PT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

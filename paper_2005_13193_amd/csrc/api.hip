@@ -56,6 +56,11 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
                        float* u0, float* ub0, float* ub1, float* gcoeff, void* defer,
                        void* items_ws, bool check, hipStream_t s);
 size_t tile_defer_bytes(int64_t np);
+// migrate.hip
+size_t slab_partition_ws_bytes(int64_t np);
+pt_status slab_partition(const pt_grid* grid, int64_t np, const double* pos, const int32_t* ids,
+                         int z0, int nzl, double* pos_out, int32_t* ids_out, int64_t* counts,
+                         void* ws, hipStream_t s);
 pt_status tile_tv_stage1(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                          int64_t np, const double* x, double* x_out, float* u_n, void* defer,
                          void* items_ws, hipStream_t s);
@@ -225,6 +230,7 @@ pt_status pt_workspace_bytes(int op, const pt_grid* grid, pt_dtype dtype, int64_
     case PT_OP_RK2_BWD: *bytes = a256(rk2_bwd_ws_bytes(grid, np)); break;
     // np = input planes of the slab, nzl + 3 + 2 W
     case PT_OP_SPLINE_SLAB: *bytes = a256(4 * spline_slab_ws_floats(grid, (int)np - 3, 0)); break;
+    case PT_OP_SLAB_PARTITION: *bytes = a256(slab_partition_ws_bytes(np)); break;
     default: return PT_ERR_ARG;
   }
   return PT_OK;
@@ -296,6 +302,23 @@ pt_status pt_sort_particles(const pt_grid* grid, int64_t np, const double* pos, 
   PT_TRY(permute_ids(np, ids, perm, ids_tmp, stream));
   PT_HIP_CHECK(hipMemcpyAsync(ids, ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
   return PT_OK;
+}
+
+pt_status pt_slab_partition(const pt_grid* grid, int64_t np, const double* pos,
+                            const int32_t* ids, int32_t z0, int32_t nzl, double* pos_out,
+                            int32_t* ids_out, int64_t* counts, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_np(np));
+  if (z0 < 0 || z0 >= grid->nz || nzl < 1 || nzl > grid->nz) return PT_ERR_ARG;
+  if (!counts) return PT_ERR_NULL;
+  if (np > 0 && (!pos || !pos_out || (ids && !ids_out))) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_SLAB_PARTITION, grid, PT_F32, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  if (np > 0 && pos_out < pos + 3 * np && pos < pos_out + 3 * np) return PT_ERR_ARG;
+  PT_TRY(ready());
+  return slab_partition(grid, np, pos, ids, z0, nzl, pos_out, ids_out, counts, ws, stream);
 }
 
 pt_status pt_interp_uvw(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,

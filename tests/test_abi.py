@@ -97,6 +97,17 @@ def test_invalid_arguments_rejected_before_launch(b):
     nan = float("nan")
     assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, nan, fake, None, 1, fake, 1 << 40, None) == b.PT_ERR_ARG
     assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, 0.1, fake, None, 1, fake, 8, None) == b.PT_ERR_WORKSPACE
+    P = L.pt_slab_partition
+    assert P(ctypes.byref(g), 10, fake, None, -1, 4, fake, None, fake, fake, 1 << 30, None) == b.PT_ERR_ARG
+    assert P(ctypes.byref(g), 10, fake, None, 32, 4, fake, None, fake, fake, 1 << 30, None) == b.PT_ERR_ARG
+    assert P(ctypes.byref(g), 10, fake, None, 0, 0, fake, None, fake, fake, 1 << 30, None) == b.PT_ERR_ARG
+    assert P(ctypes.byref(g), 10, fake, None, 0, 33, fake, None, fake, fake, 1 << 30, None) == b.PT_ERR_ARG
+    assert P(ctypes.byref(g), 10, fake, None, 0, 4, fake, None, None, fake, 1 << 30, None) == b.PT_ERR_NULL
+    assert P(ctypes.byref(g), 10, fake, fake, 0, 4, fake, None, fake, fake, 1 << 30, None) == b.PT_ERR_NULL
+    assert P(ctypes.byref(g), 10, fake, None, 0, 4, fake, None, fake, fake, 8, None) == b.PT_ERR_WORKSPACE
+    # output overlapping the input
+    assert P(ctypes.byref(g), 10, fake, None, 0, 4, vp(0x1000 + 8), None, fake, fake, 1 << 30,
+             None) == b.PT_ERR_ARG
     for bad_sort in (-1, 3):  # only PT_UNSORTED, PT_SORT and PT_SORTED
         assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, 0.1, fake, None, bad_sort, fake, 1 << 40, None) == b.PT_ERR_ARG
         assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, 10, 0.1, fake, bad_sort, fake, None, fake, 1 << 40, None) == b.PT_ERR_ARG
