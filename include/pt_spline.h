@@ -268,7 +268,7 @@ pt_status pt_rk2_step_bwd(const pt_grid *grid, const void *coeff, pt_dtype dtype
                           hipStream_t stream);
 
 /* One device's part of the particle migration between sub-domains
- * (Sec. 4.4): with the grid split into z-slabs, the particles that left this
+ * (Sec. 4.3): with the grid split into z-slabs, the particles that left this
  * device's slab [z0, z0 + nzl) (cells modulo nz) are separated from the ones
  * that stay, with all their attributes, and the gaps are closed.  The output
  * is one stable partition [stay | lower | upper]: each particle's group comes

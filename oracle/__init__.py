@@ -144,7 +144,7 @@ def sort_particles(grid, pos, tile_x, tile_y):
 
 
 def slab_groups(grid, pos, z0, nzl):
-    """Group of each particle for the migration between z-slabs (Sec. 4.4):
+    """Group of each particle for the migration between z-slabs (Sec. 4.3):
     0 stays in the slab [z0, z0 + nzl) (shadow z cells modulo nz), 1 goes to
     the slab below, 2 to the slab above, whichever side is nearer (ties below)."""
     cells, _, _ = cell_keys(grid, pos, 1, 1)

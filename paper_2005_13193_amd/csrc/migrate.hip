@@ -1,4 +1,4 @@
-// One device's part of the particle migration between sub-domains (Sec. 4.4):
+// One device's part of the particle migration between sub-domains (Sec. 4.3):
 // after a step each process finds the particles that have left its
 // sub-domain, copies them with their attributes into outgoing buffers and
 // closes the gaps among the ones that stay, before the exchange with the

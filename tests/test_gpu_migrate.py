@@ -1,5 +1,5 @@
 """GPU-vs-oracle parity of pt_slab_partition (one device's part of the
-particle migration between z-slabs, Sec. 4.4), through the C ABI: positions,
+particle migration between z-slabs, Sec. 4.3), through the C ABI: positions,
 labels and group counts bit-exact."""
 import numpy as np
 import pytest

@@ -1,5 +1,5 @@
 """Pins of the oracle's particle grouping for the migration between z-slabs
-(Sec. 4.4: particles that left the sub-domain are separated, with their
+(Sec. 4.3: particles that left the sub-domain are separated, with their
 attributes, from the ones that stay; the gaps are closed).  With z-slabs a
 departing particle goes to the slab below or above; the oracle sends it to
 the nearer side, ties below."""
