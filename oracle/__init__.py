@@ -283,6 +283,16 @@ def interp_window(grid, field, pos, n_out=3, W=28):
     return out
 
 
+def rk2_tv_window(grid, field_n, field_np1, pos, dt, W=28):
+    """As rk2_step_tv, with the coefficients formed from the two fields
+    (predictor from field_n at x, corrector from field_np1 at x*)."""
+    p = _f64(pos)
+    u0 = interp_window(grid, field_n, p, n_out=3, W=W)
+    xs = p + dt * u0
+    u1 = interp_window(grid, field_np1, xs, n_out=3, W=W)
+    return p + 0.5 * dt * (u0 + u1)
+
+
 def rk2_window(grid, field, pos, dt, steps, W=28):
     """`steps` Heun steps (as rk2_step), coefficients formed from the field."""
     f, is32 = _field_arg(field)

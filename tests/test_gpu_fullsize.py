@@ -16,6 +16,8 @@ full with the plain oracle.
     for FP32, the adjoint of the last step at 256 sampled particles and 64
     sampled coefficient points, and the adjoint of the solve at 200 sampled
     grid points;
+  1024^3, the time-varying step (two fields, the two stages) at 256 sampled
+    particles;
   2048^3, 256M uniform particles (64-bit sort keys): sort, the 12-output
     gather on the sorted particles and one sorted Heun step, sampled;
   256^3, 1M particles: L = sum |x(8)|^2 through TrackParticles (checkpoints
@@ -234,6 +236,44 @@ def _check_c3_adjoint(og, rc, dt, adj):
     assert np.abs(ref).max() > 0
     err = normwise(adj["gco"], ref)
     log(f"c3 f32: adjoint dL/dS error (64 sampled coefficients) {err:.3e}")
+    assert err < F32_TOL
+
+
+def test_c3_1024_tv_sampled(pt):
+    """The time-varying step as the benchmark launches it (stage 1 with the
+    cell sort and the coefficients of the field at t_n, stage 2 with those of
+    the field at t_n + dt) at 1024^3 with the 64M clustered particles, at 256
+    sampled particles against the windowed oracle of the two FP32 fields."""
+    import torch
+    n, np_, kmax = 1024, 64 * 2 ** 20, 341
+    if free_bytes() < 100 * 2 ** 30:
+        pytest.skip("needs 100 GiB of free device memory")
+    dev = torch.device("cuda:0")
+    g, og = pt.Grid(n), oracle.Grid(n)
+    fa = synth.spectral_field_torch(n, kmax, seed=0, device=dev)
+    fb = synth.spectral_field_torch(n, kmax, seed=1, device=dev)
+    dt = synth.cfl_dt(max(max_abs(fa), max_abs(fb)), n)
+    ca = pt.spline_coeffs(g, fa)
+    cb = pt.spline_coeffs(g, fb)
+    torch.cuda.synchronize()
+    fah = field_to_host(fa)
+    fbh = field_to_host(fb)
+    del fa, fb
+    torch.cuda.empty_cache()
+    pos = synth.clustered_particles_torch(np_, sigma=0.1, device=dev)
+    sample = torch.arange(0, np_, np_ // 256, device=dev)
+    pos0 = pos[:, sample].cpu().numpy()
+    ids = torch.arange(np_, dtype=torch.int32, device=dev)
+    u_n, ws = pt.rk2_stage1(g, ca, pos, ids=ids, sort=True)
+    pt.rk2_stage2(g, cb, pos, u_n, dt, sorted_=True, ws=ws)
+    assert pt.last_device_error() == 0
+    fin = pos[:, slots_of(ids, sample)].cpu().numpy()
+    del pos, ids, u_n, ws, ca, cb
+    torch.cuda.empty_cache()
+    log("c3 tv: two stages done; windowed oracle")
+    ref = oracle.rk2_tv_window(og, fah, fbh, pos0, dt)
+    err = normwise(fin - pos0, ref - pos0)
+    log(f"c3 tv: displacement error (256 particles, windowed oracle) {err:.3e}")
     assert err < F32_TOL
 
 
