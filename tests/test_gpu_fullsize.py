@@ -19,7 +19,8 @@ full with the plain oracle.
   1024^3, the time-varying step (two fields, the two stages) at 256 sampled
     particles;
   2048^3, 256M uniform particles (64-bit sort keys): sort, the 12-output
-    gather on the sorted particles and one sorted Heun step, sampled;
+    gather on the sorted particles and one sorted Heun step, sampled, and one
+    device's 256-plane slab solve of the same field, sampled;
   256^3, 1M particles: L = sum |x(8)|^2 through TrackParticles (checkpoints
     every 2 steps) against the oracle's hand adjoint, all outputs.
 """
@@ -365,6 +366,27 @@ def test_c5_2048_sampled(pt):
     assert err < F32_TOL
     del pos, ids, coeff
     torch.cuda.empty_cache()
+    # one device's z-slab of this grid split 8 ways, as the slab workload
+    # solves it (256 planes, 16 halo planes per side, open-ended z lines):
+    # output plane P holds global plane z0 - 1 + P of the periodic solve
+    nzl, halo, z0 = 256, 16, 768
+    planes = [(z0 - 1 - halo + i) % n for i in range(nzl + 3 + 2 * halo)]
+    fs = torch.from_numpy(np.ascontiguousarray(fh[:, planes])).to(dev)
+    cs = pt.spline_coeffs_slab(g, fs, nzl, halo)
+    torch.cuda.synchronize()
+    del fs
+    rng = np.random.default_rng(31)
+    P = rng.integers(0, nzl + 3, size=200)
+    P[:4] = [0, 1, nzl + 1, nzl + 2]
+    xs, ys = rng.integers(0, n, size=200), rng.integers(0, n, size=200)
+    got = cs[:, torch.from_numpy(P).to(dev), torch.from_numpy(ys + 1).to(dev),
+             torch.from_numpy(xs + 1).to(dev)].double().cpu().numpy()
+    del cs
+    torch.cuda.empty_cache()
+    ref = oracle.coeffs_at(fh, np.stack([xs, ys, (z0 - 1 + P) % n]))
+    err = normwise(got, ref)
+    log(f"c5: slab coefficients error (200 sampled points) {err:.3e}")
+    assert err < F32_TOL
 
 
 def test_c4_256_adjoint_k8(pt):
