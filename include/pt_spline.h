@@ -183,7 +183,10 @@ enum {
                       give the same result more slowly: a particle outside its
                       column's tile is evaluated from global memory, and a cell
                       table that is not a partition of the particles (checked on
-                      the device) sends every particle that way. */
+                      the device) sends every particle that way.
+                      PT_SORT and PT_SORTED (and the sorted stages of the
+                      time-varying step) take at most 2^30 particles per call:
+                      more return PT_ERR_UNSUPPORTED. */
 };
 
 /* One RK2 step of dx/dt = u(x) (eq. (dxdt)), Heun's form:

@@ -127,6 +127,12 @@ static pt_status check_np(int64_t np) {
   return PT_OK;
 }
 
+// The column-tiled kernels count deferred stencils (up to 2 np) in 32-bit
+// signed words, so they take at most 2^30 particles per call.
+static pt_status check_tiled_np(int64_t np) {
+  return np > ((int64_t)1 << 30) ? PT_ERR_UNSUPPORTED : PT_OK;
+}
+
 static pt_status check_dtype(pt_dtype d) {
   return (d == PT_F32 || d == PT_BF16) ? PT_OK : PT_ERR_DTYPE;
 }
@@ -351,6 +357,7 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
   PT_TRY(check_np(np));
   if (!isfinite(dt)) return PT_ERR_ARG;
   if (sort != PT_UNSORTED && sort != PT_SORT && sort != PT_SORTED) return PT_ERR_ARG;
+  if (sort != PT_UNSORTED) PT_TRY(check_tiled_np(np));
   if (np == 0) return PT_OK;
   if (!coeff || !pos) return PT_ERR_NULL;
   size_t need = 0;
@@ -382,6 +389,7 @@ pt_status pt_rk2_stage1(const pt_grid* grid, const void* coeff_n, pt_dtype dtype
   PT_TRY(check_grid(grid));
   PT_TRY(check_dtype(dtype));
   PT_TRY(check_np(np));
+  if (sort) PT_TRY(check_tiled_np(np));
   if (np == 0) return PT_OK;
   if (!coeff_n || !pos || !u_n) return PT_ERR_NULL;
   size_t need = 0;
@@ -409,6 +417,7 @@ pt_status pt_rk2_stage2(const pt_grid* grid, const void* coeff_np1, pt_dtype dty
   PT_TRY(check_dtype(dtype));
   PT_TRY(check_np(np));
   if (!isfinite(dt)) return PT_ERR_ARG;
+  if (sorted) PT_TRY(check_tiled_np(np));
   if (np == 0) return PT_OK;
   if (!coeff_np1 || !pos || !u_n) return PT_ERR_NULL;
   PT_TRY(ready());
@@ -441,6 +450,7 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
   PT_TRY(check_np(np));
   if (!isfinite(dt)) return PT_ERR_ARG;
   if (sort != PT_UNSORTED && sort != PT_SORT && sort != PT_SORTED) return PT_ERR_ARG;
+  if (sort != PT_UNSORTED) PT_TRY(check_tiled_np(np));
   if (np == 0) return PT_OK;
   if (!coeff || !pos_n || !g_pos) return PT_ERR_NULL;
   size_t need = 0;

@@ -112,6 +112,13 @@ def test_invalid_arguments_rejected_before_launch(b):
         assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, 0.1, fake, None, bad_sort, fake, 1 << 40, None) == b.PT_ERR_ARG
         assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, 10, 0.1, fake, bad_sort, fake, None, fake, 1 << 40, None) == b.PT_ERR_ARG
     assert (b.PT_UNSORTED, b.PT_SORT, b.PT_SORTED) == (0, 1, 2)
+    # the tiled paths take at most 2^30 particles per call
+    big_np = (1 << 30) + 1
+    for srt in (1, 2):
+        assert L.pt_rk2_step(ctypes.byref(g), fake, 0, big_np, 0.1, fake, None, srt, fake, 1 << 62, None) == b.PT_ERR_UNSUPPORTED
+        assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, big_np, 0.1, fake, srt, fake, None, fake, 1 << 62, None) == b.PT_ERR_UNSUPPORTED
+    assert L.pt_rk2_stage1(ctypes.byref(g), fake, 0, big_np, fake, None, 1, fake, fake, 1 << 62, None) == b.PT_ERR_UNSUPPORTED
+    assert L.pt_rk2_stage2(ctypes.byref(g), fake, 0, big_np, 0.1, fake, fake, 1, fake, 1 << 62, None) == b.PT_ERR_UNSUPPORTED
     assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, 10, 0.1, fake, 1, None, None, fake, 1 << 40, None) == b.PT_ERR_NULL
     assert L.pt_interp_uvw_bwd(ctypes.byref(g), fake, 0, 10, fake, None, fake, None, None) == b.PT_ERR_NULL
     assert L.pt_interp_uvw_bwd(ctypes.byref(g), fake, 0, 10, fake, fake, None, None, None) == b.PT_OK
