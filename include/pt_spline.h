@@ -185,8 +185,8 @@ enum {
                       table that is not a partition of the particles (checked on
                       the device) sends every particle that way.
                       PT_SORT and PT_SORTED (and the sorted stages of the
-                      time-varying step) take at most 2^30 particles per call:
-                      more return PT_ERR_UNSUPPORTED. */
+                      time-varying step) take fewer than 2^30 particles per
+                      call: more return PT_ERR_UNSUPPORTED. */
 };
 
 /* One RK2 step of dx/dt = u(x) (eq. (dxdt)), Heun's form:

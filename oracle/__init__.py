@@ -219,20 +219,6 @@ def rk2_step_bwd(grid, coeff, pos_n, dt, lam, gcoeff=None):
     return g, gcoeff
 
 
-def advect(grid, coeff, pos, dt, steps, tile_x=None, tile_y=None):
-    """K Heun steps.  With tile sizes given, the particles are re-sorted by
-    cell key before every step (as the GPU path does); returns
-    (final positions, ids) where ids[i] is the input index of particle i."""
-    p = _f64(pos).copy()
-    ids = np.arange(p.shape[1], dtype=np.int64)
-    for _ in range(steps):
-        if tile_x is not None:
-            p, perm, _ = sort_particles(grid, p, tile_x, tile_y)
-            ids = ids[perm]
-        p = rk2_step(grid, coeff, p, dt)
-    return p, ids
-
-
 def loss_and_grads(grid, field, pos0, dt, steps):
     """L = sum |x(K)|^2 after K Heun steps (no sort: the loss is
     order-independent); returns (L, dL/dpos0, dL/dfield) by the hand adjoint."""

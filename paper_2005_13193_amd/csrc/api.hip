@@ -128,9 +128,9 @@ static pt_status check_np(int64_t np) {
 }
 
 // The column-tiled kernels count deferred stencils (up to 2 np) in 32-bit
-// signed words, so they take at most 2^30 particles per call.
+// signed words, so they take fewer than 2^30 particles per call.
 static pt_status check_tiled_np(int64_t np) {
-  return np > ((int64_t)1 << 30) ? PT_ERR_UNSUPPORTED : PT_OK;
+  return np >= ((int64_t)1 << 30) ? PT_ERR_UNSUPPORTED : PT_OK;
 }
 
 static pt_status check_dtype(pt_dtype d) {

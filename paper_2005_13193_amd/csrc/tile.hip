@@ -734,10 +734,10 @@ __global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
 // The LDS sums are 64-bit fixed point: FP32 atomic adds to LDS run at a small
 // fraction of the rate of integer ones on this hardware.  Every contribution
 // w * ub is formed in FP32 with ub pre-scaled by 2^k (k chosen per launch from
-// the largest |ub|, so that |w ub 2^k| < 2^31), converted to a 32-bit integer
-// and added as a 64-bit integer; the plane flush converts back.  The rounding
-// of each contribution (2^-k absolute, about 2^-30 of the largest |ub|) is
-// far below the FP32 rounding of the contribution itself.
+// the largest |ub|, so that |w ub 2^k| < 2^31), rounded to the nearest 32-bit
+// integer and added as a 64-bit integer; the plane flush converts back.  The
+// rounding of each contribution is at most 2^-(k+1) absolute (about 2^-31 of
+// the largest |ub|) and unbiased.
 constexpr int kSTW = kTileX + 5;           // 37: tile width with margin
 constexpr int kSTH = kTileY / 2 + 5;       // 21
 constexpr int kSComp = kSTW * kSTH;        // 777
@@ -779,7 +779,7 @@ __device__ __forceinline__ void scatter_ring(long long* ring, const Pt& q, int X
       const float w = wxi * wy[j] * wzk;
 #pragma unroll
       for (int comp = 0; comp < 3; ++comp) {
-        const int v = (int)(w * us[comp]);
+        const int v = __float2int_rn(w * us[comp]);
         atomicAdd((unsigned long long*)(pl + comp * kSComp + j * kSTW),
                   (unsigned long long)(long long)v);
       }
@@ -888,7 +888,8 @@ __device__ __forceinline__ float scatter_scale(const TileArgs& a) {
   if (!(m > 0.0f) || !(m < 3.0e38f)) return 1.0f;
   int e;
   frexpf(m, &e);  // m < 2^e
-  return ldexpf(1.0f, 30 - e);
+  // 2^126 at most: the scale and its inverse stay finite and normal
+  return ldexpf(1.0f, min(30 - e, 126));
 }
 
 // Offsets in g_coeff, less the plane term, of the plane words this thread
@@ -1024,10 +1025,11 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
       }
     }
   }
-  // planes above the last flushed one, up to z1 + 3 (the highest plane a
-  // predictor point of layer z1 - 1 reaches)
+  // planes above the last flushed one: the last slab accepted cells up to
+  // last_zs + kSlab, whose stencils reach plane last_zs + kSlab + 3 (z1 + 3
+  // for an even item length, z1 + 4 for an odd one)
   const int last_zs = z0 + ((nl - 1) / kSlab) * kSlab;
-  for (int P = last_zs + 1; P <= z1 + 3; ++P) {
+  for (int P = last_zs + 1; P <= last_zs + kSlab + 3; ++P) {
     flush_splane(a, ring, foff, P, inv_scale);
     __syncthreads();
   }
@@ -1149,8 +1151,9 @@ __global__ __launch_bounds__(256) void layer_table(const K* __restrict__ keys, i
 // run excepted) and at most lmax layers, so that dense clusters are spread
 // over many workgroups.  Scatter items carry a colour: parities of cx, of the
 // half-row 2 cy + h and of the run index; runs of one colour never share a
-// coefficient because every run between two of them is at least lmin >= 5
-// layers long and a run touches planes z0-1 .. z1+3 only.
+// coefficient because every run between two of them is at least lmin = 6
+// layers long and a run touches planes z0-1 .. z1+4 only (z1+4: an odd-length
+// run's last slab accepts cells up to z1+1).
 // Gather units are (z-block of lmax layers, column), ordered z-block first
 // and, inside a z-block, by groups of 8 x 4 neighbouring columns: the
 // workgroups that run at the same time on one XCD take neighbouring columns

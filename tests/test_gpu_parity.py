@@ -356,3 +356,56 @@ def test_rk2_tiled_fwd_bwd_parity(pt, shape, np_, clustered, cfl, dtype):
     assert normwise(host(gp), ref_in) < tol
     assert normwise(host(gco).reshape(3, -1), gc_ref.reshape(3, -1)) < F32_TOL
     assert pt.last_device_error() == 0
+
+
+def _dense_half_column(n, seed=12):
+    """44,000 particles uniform over the cells [0,32) x [0,16) x [8,48) of an
+    n^3 grid (about 1,100 per layer of that half-column), plus 10,000 uniform
+    ones: the scatter splits that half-column into runs of 7 layers (more than
+    8,192 particles would fall in a run of 8), so runs of odd length occur in
+    the middle of the column."""
+    rng = np.random.default_rng(seed)
+    h = 2 * np.pi / n
+    m = 44000
+    p = np.empty((3, m))
+    p[0] = rng.uniform(0, 32, m) * h
+    p[1] = rng.uniform(0, 16, m) * h
+    p[2] = rng.uniform(8, 48, m) * h
+    return np.concatenate([p, rng.uniform(0, 2 * np.pi, (3, 10000))], axis=1)
+
+
+@pytest.mark.parametrize("sort_mode", ["sort", "sorted"])
+def test_rk2_tiled_bwd_odd_scatter_runs(pt, sort_mode):
+    """Adjoint at 3x the Courant limit on a distribution whose scatter runs
+    have odd lengths: the last slab of such a run accepts predictor cells two
+    layers above it, whose stencils reach the run's end plane + 4."""
+    import torch
+    from paper_2005_13193_amd import _binding as B
+    n = 64
+    f = _field_any(n, n, n)
+    g, og = pt.Grid(n), oracle.Grid(n)
+    ref_coeff = oracle.spline_coeffs(f)
+    coeff = pt.spline_coeffs(g, dev(f, torch.float32))
+    pos = _dense_half_column(n)
+    np_ = pos.shape[1]
+    dt = 3.0 * 0.6 * (2 * np.pi / n) / np.abs(f).max()
+    _, perm_ref, _ = oracle.sort_particles(og, pos, 32, 32)
+    rng = np.random.default_rng(6)
+    lam = rng.standard_normal((3, np_))
+    gco = torch.zeros(g.padded_shape, dtype=torch.float32, device="cuda")
+    lam_ref, gc_ref = oracle.rk2_step_bwd(og, ref_coeff, pos[:, perm_ref], dt, lam,
+                                          np.zeros_like(ref_coeff))
+    if sort_mode == "sort":
+        gp = dev(lam)
+        pt.rk2_step_bwd(g, coeff, dev(pos), dt, gp, gco, sort=B.PT_SORT)
+        got = np.empty_like(lam_ref)
+        got[:, perm_ref] = lam_ref
+        assert normwise(host(gp), got) < F32_TOL
+    else:
+        ps, perm, _ = pt.sort_particles(g, dev(pos))
+        assert np.array_equal(host(perm), perm_ref)
+        gp = dev(lam)
+        pt.rk2_step_bwd(g, coeff, ps, dt, gp, gco, sort=B.PT_SORTED)
+        assert normwise(host(gp), lam_ref) < F32_TOL
+    assert normwise(host(gco).reshape(3, -1), gc_ref.reshape(3, -1)) < F32_TOL
+    assert pt.last_device_error() == 0
