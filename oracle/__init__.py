@@ -42,6 +42,8 @@ def _load():
         lib.oracle_interp.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, vp, i32, vp]
         lib.oracle_rk2_step.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, dbl, vp]
         lib.oracle_rk2_step_tv.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, vp, i64, dbl, vp]
+        lib.oracle_inertial_step.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, dbl, dbl,
+                                             vp, vp, vp]
         lib.oracle_interp_bwd.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, i64, vp, vp,
                                           vp, vp]
         lib.oracle_spline_coeffs_bwd.argtypes = [i32, i32, i32, vp, vp]
@@ -54,6 +56,7 @@ def _load():
                                           dbl, i32, vp]
         for name in ("oracle_solve_line", "oracle_spline_coeffs", "oracle_cell_keys",
                      "oracle_interp", "oracle_rk2_step", "oracle_rk2_step_tv",
+                     "oracle_inertial_step",
                      "oracle_interp_bwd",
                      "oracle_spline_coeffs_bwd", "oracle_rk2_step_bwd", "oracle_coeffs_at",
                      "oracle_interp_window", "oracle_rk2_window"):
@@ -190,6 +193,20 @@ def rk2_step_tv(grid, coeff_n, coeff_np1, pos, dt):
     _chk(_load().oracle_rk2_step_tv(*grid.args, _ptr(coeff_n), _ptr(coeff_np1), p.shape[1], dt,
                                     _ptr(p)))
     return p
+
+
+def inertial_step(grid, coeff, pos, vel, dt, tau, disp=None):
+    """One step of an inertial particle (Stokes drag with response time tau;
+    tau = 0 is the fluid tracer) with an optional displacement increment per
+    particle (a diffusive marker's random step); returns (positions,
+    velocities), velocities None when vel is None (tau = 0 only)."""
+    coeff = _f64(coeff)
+    p = _f64(pos).copy()
+    v = None if vel is None else _f64(vel).copy()
+    d = None if disp is None else _f64(disp)
+    _chk(_load().oracle_inertial_step(*grid.args, _ptr(coeff), p.shape[1], dt, tau, _ptr(p),
+                                      _ptr(v), _ptr(d)))
+    return p, v
 
 
 def interp_bwd(grid, coeff, pos, gout, want_pos=True, want_coeff=True):

@@ -26,7 +26,10 @@
  *     Sherman-Morrison rank-one correction for the two corner entries;
  *   - cell membership is half-open, alpha = floor(x/dx) of the shadow
  *     position;
- *   - the particle RK2 scheme is Heun's predictor-corrector.
+ *   - the particle RK2 scheme is Heun's predictor-corrector;
+ *   - inertial particles (Sec. 4.3 names them without an equation) follow
+ *     Stokes drag, advanced by the exponential-integrator form of Heun's
+ *     step given at oracle_inertial_step.
  */
 #include <math.h>
 #include <stdint.h>
@@ -381,6 +384,92 @@ int oracle_rk2_step(int nx, int ny, int nz, double lx, double ly, double lz,
  * coefficients recomputed from the velocity field of that sub-step: the
  * predictor uses the field at t_n, the corrector the field at t_n + dt.
  *   u0 = u^n(x);  x* = x + dt u0;  x <- x + dt/2 (u0 + u^{n+1}(x*)). */
+/* phi_m(r) = sum_{j>=0} (-r)^j / (j+m)!, the functions of exponential
+ * integrators: phi_1 = (1 - e^-r)/r, phi_2 = (1 - phi_1)/r,
+ * phi_3 = (1/2 - phi_2)/r.  The recursions lose digits to cancellation for
+ * small r, so there the series is summed (15 terms: truncation below 1e-27). */
+static void phi123(double r, double *p1, double *p2, double *p3) {
+  if (r >= 0.1) {
+    *p1 = (1.0 - exp(-r)) / r;
+    *p2 = (1.0 - *p1) / r;
+    *p3 = (0.5 - *p2) / r;
+    return;
+  }
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int m = 1; m <= 3; ++m) {
+    double fact = 1.0; /* m! */
+    for (int q = 2; q <= m; ++q) fact *= q;
+    double term = 1.0 / fact, sum = 0.0;
+    for (int j = 0; j < 15; ++j) {
+      sum += term;
+      term *= -r / (double)(j + 1 + m);
+    }
+    s[m - 1] = sum;
+  }
+  *p1 = s[0];
+  *p2 = s[1];
+  *p3 = s[2];
+}
+
+/* Inertial (or diffusive) particle step: Sec. 4.3 notes that inertial
+ * particles, or markers with a high molecular diffusivity, can move more than
+ * one grid spacing per step.  The paper gives no equation for them; reading
+ * taken here: the Stokes-drag particle
+ *   dx/dt = v,   dv/dt = (u(x) - v) / tau,
+ * advanced over a step h by the exact solution of these equations with the
+ * fluid velocity seen along the step taken as linear in time, from
+ * u0 = u(x^n) to u1 = u(x*) at the predicted end point x* (the position the
+ * exact solution reaches if the fluid velocity stays u0), i.e. an
+ * exponential-integrator form of Heun's predictor-corrector.  With
+ * r = h/tau, E = exp(-r):
+ *   x*   = x + h phi_1 v + h r phi_2 u0 + d
+ *   x+   = x* + h r phi_3 (u1 - u0)
+ *   v+   = E v + (phi_1 - E) u0 + r phi_2 u1,
+ * (written out: h phi_1 = tau (1 - E), h r phi_2 = h - tau (1 - E),
+ * h r phi_3 = h/2 - tau + tau^2 (1 - E)/h), where d is an optional
+ * displacement increment per particle (the random displacement
+ * sqrt(2 kappa h) xi of a diffusive marker, drawn by the caller), added to
+ * the predictor and kept in the corrector.  tau = 0 is the fluid tracer: the
+ * limits phi_1 -> 0, r phi_2 -> 1, r phi_3 -> 1/2, E -> 0 give Heun's step
+ * x+ = x + h/2 (u0 + u1) + d with v+ = u1.  vel may be NULL only when tau = 0
+ * (then not read or written). */
+int oracle_inertial_step(int nx, int ny, int nz, double lx, double ly, double lz,
+                         const double *coeff, int64_t np, double dt, double tau,
+                         double *pos, double *vel, const double *disp) {
+  if (!check_finite(np, pos)) return OR_ERR_NONFINITE;
+  if (!(tau >= 0.0) || !(dt > 0.0) || (tau > 0.0 && !vel)) return OR_ERR_SIZE;
+  or_grid gr = {nx, ny, nz, lx, ly, lz};
+  double E = 0.0, cv = 0.0, cu = dt, c1 = 0.5 * dt, b = 1.0;
+  if (tau > 0.0) {
+    const double r = dt / tau;
+    double p1, p2, p3;
+    phi123(r, &p1, &p2, &p3);
+    E = exp(-r);
+    cv = dt * p1;      /* coefficient of v in the predictor */
+    cu = dt * r * p2;  /* of u0 in the predictor */
+    c1 = dt * r * p3;  /* of (u1 - u0) in the corrector */
+    b = r * p2;        /* of u1 in the new velocity */
+  }
+  const double bu0 = tau > 0.0 ? (cv / dt - E) : 0.0; /* of u0 in the new velocity */
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < np; ++p) {
+    double x0[3], v0[3], dd[3], xs[3], u0[12], u1[12];
+    for (int d = 0; d < 3; ++d) {
+      x0[d] = pos[d * np + p];
+      v0[d] = tau > 0.0 ? vel[d * np + p] : 0.0;
+      dd[d] = disp ? disp[d * np + p] : 0.0;
+    }
+    eval_particle(&gr, coeff, x0[0], x0[1], x0[2], 0, u0);
+    for (int d = 0; d < 3; ++d) xs[d] = x0[d] + cv * v0[d] + cu * u0[d] + dd[d];
+    eval_particle(&gr, coeff, xs[0], xs[1], xs[2], 0, u1);
+    for (int d = 0; d < 3; ++d) {
+      pos[d * np + p] = xs[d] + c1 * (u1[d] - u0[d]);
+      if (vel) vel[d * np + p] = E * v0[d] + bu0 * u0[d] + b * u1[d];
+    }
+  }
+  return OR_OK;
+}
+
 int oracle_rk2_step_tv(int nx, int ny, int nz, double lx, double ly, double lz,
                        const double *coeff_n, const double *coeff_np1, int64_t np,
                        double dt, double *pos) {
