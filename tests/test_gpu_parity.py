@@ -16,7 +16,6 @@ pytestmark = pytest.mark.gpu
 
 F32_TOL = 1e-5
 BF16_TOL = 5e-3
-GRAD_BF16_TOL = 2e-2
 
 
 def bf16_round(a):
@@ -40,6 +39,33 @@ def normwise(y, ref):
     ref = np.asarray(ref, dtype=np.float64).reshape(ref.shape[0], -1)
     return max(np.abs(y[r] - ref[r]).max() / max(np.abs(ref[r]).max(), 1e-300)
                for r in range(ref.shape[0]))
+
+def bf16_grad_bounds(smax, inv_h):
+    """Worst case of BF16 coefficient storage in the nine gradient rows,
+    [9] array of absolute bounds: each stored coefficient is off by at most
+    2^-8 of its size (round to nearest, 8 significant bits), the derivative
+    weights along the differentiated axis sum in absolute value to at most
+    max_t sum_i |b_i'(t)| = 1.5 and the weights along the other axes to 1, so
+    |error of du_c/dx_d| <= 1.5 * 2^-8 * max|S_c| * n_d / L_d."""
+    t = np.linspace(0.0, 1.0, 1001)
+    dsum = (0.5 * (1 - t) ** 2 + np.abs(t * (1.5 * t - 2.0)) + np.abs(0.5 + t * (1.0 - 1.5 * t))
+            + 0.5 * t * t).max()
+    return np.array([dsum * 2.0 ** -8 * smax[c] * inv_h[d] for c in range(3) for d in range(3)])
+
+
+def check_bf16_grad(out_rows, ref_rows, smax, inv_h):
+    """Normwise error of each gradient row (BF16 storage) against the bound
+    of bf16_grad_bounds taken relative to the row's largest reference value;
+    returns the largest error."""
+    bound = bf16_grad_bounds(smax, inv_h)
+    errs = []
+    for r in range(9):
+        scale = max(np.abs(ref_rows[r]).max(), 1e-300)
+        e = np.abs(np.asarray(out_rows[r], np.float64) - ref_rows[r]).max() / scale
+        assert e < bound[r] / scale, (r, e, bound[r] / scale)
+        errs.append(e)
+    return max(errs)
+
 
 
 def dev(a, dtype=None):
@@ -159,8 +185,14 @@ def test_interp_uvw_and_grad_parity(pt, n, np_, clustered, dtype):
     out12 = host(pt.interp_grad(g, coeff, ps))
     ref12 = oracle.interp(og, ref_coeff, pos_s, n_out=12)
     assert normwise(out12[:3], ref12[:3]) < tol
-    # BF16 storage error is amplified ~1/(k h) in the derivative rows
-    assert normwise(out12[3:], ref12[3:]) < (tol if dtype == "f32" else GRAD_BF16_TOL)
+    if dtype == "f32":
+        assert normwise(out12[3:], ref12[3:]) < tol
+    else:
+        # the BF16 storage error is amplified ~1/(k h) in the derivative rows
+        # (the derivative weights sum to zero): held to its worst-case bound
+        e = check_bf16_grad(out12[3:], ref12[3:], np.abs(ref_coeff).reshape(3, -1).max(1),
+                            [n / (2 * np.pi)] * 3)
+        print(f"bf16 gradient rows, {n}^3: normwise error {e:.3e}")
     if dtype == "bf16":
         # the gather arithmetic itself: both sides read the same BF16 values
         import torch
