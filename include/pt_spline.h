@@ -28,7 +28,8 @@
  *  - Arrays are dense, C order, x the fastest index:
  *      field   float [3][nz][ny][nx]           grid values of (u, v, w)
  *      coeff   [3][nz+3][ny+3][nx+3]           padded spline coefficients,
- *              float (PT_F32) or bfloat16 bits (PT_BF16); along every axis the
+ *              float (PT_F32), bfloat16 bits (PT_BF16) or double (PT_F64);
+ *              along every axis the
  *              padded index P holds the coefficient of grid line (P-1) mod n,
  *              i.e. the index range 1..N+3 of eq. (spline) shifted to 0-based
  *      pos     double [3][np]                  positions x, y, z, unwrapped
@@ -65,8 +66,15 @@ typedef enum {
   PT_ERR_ARG = -8          /* other invalid argument (bad op code, dt) */
 } pt_status;
 
-/* Storage type of the spline coefficients.  Arithmetic is FP32 for both. */
-typedef enum { PT_F32 = 0, PT_BF16 = 1 } pt_dtype;
+/* Storage type of the spline coefficients.  PT_F32 and PT_BF16 compute in
+ * FP32 (BF16 values widened exactly); PT_F64 is the FP64 form of the same
+ * method (the baseline the other two are compared with on the same device):
+ * its solves and gathers compute in FP64, and the interpolated values and
+ * velocities it reads or writes (out, u_n, vel) are double instead of float.
+ * The column-tiled kernels stage FP32 or BF16 coefficients only: with PT_F64
+ * the sorted paths (PT_SORT, PT_SORTED) sort as usual and then gather from
+ * global memory, one thread per particle. */
+typedef enum { PT_F32 = 0, PT_BF16 = 1, PT_F64 = 2 } pt_dtype;
 
 /* Periodic box [0,lx) x [0,ly) x [0,lz) sampled at nx*ny*nz points with
  * uniform spacing lx/nx, ly/ny, lz/nz (Sec. 2.2). */
@@ -83,7 +91,8 @@ enum {
   PT_OP_SPLINE_BWD = 3, /* pt_spline_coeffs_bwd */
   PT_OP_RK2_BWD = 4,    /* pt_rk2_step_bwd (with or without sort) */
   PT_OP_SPLINE_SLAB = 5, /* pt_spline_coeffs_slab; np = input planes nzl + 3 + 2 halo */
-  PT_OP_SLAB_PARTITION = 6 /* pt_slab_partition */
+  PT_OP_SLAB_PARTITION = 6, /* pt_slab_partition */
+  PT_OP_INERTIAL = 7     /* pt_inertial_step (with or without sort) */
 };
 
 /* Bytes of workspace the operation needs for this grid, coefficient dtype
@@ -159,18 +168,20 @@ pt_status pt_sort_particles(const pt_grid *grid, int64_t np, const double *pos,
 
 /* Operations 2 and 3 of Sec. 2.2, eq. (spline): at every particle
  *   g+ = sum_{k,j,i=1..4} b_i(x') c_j(y') d_k(z') S[gamma+k-2][beta+j-2][alpha+i-2]
- * with the cubic B-spline pieces as basis functions, in FP32.
+ * with the cubic B-spline pieces as basis functions, in FP32 (FP64 for
+ * PT_F64).
  *   coeff  in   padded coefficients of `dtype`
  *   pos    in   double [3][np] (any order; sorted order is fastest)
- *   out    out  float [3][np] = (u, v, w) */
+ *   out    out  float [3][np] = (u, v, w); double for PT_F64 */
 pt_status pt_interp_uvw(const pt_grid *grid, const void *coeff, pt_dtype dtype,
-                        int64_t np, const double *pos, float *out, hipStream_t stream);
+                        int64_t np, const double *pos, void *out, hipStream_t stream);
 
 /* As pt_interp_uvw, plus the nine velocity gradients from the derivatives of
  * the basis functions (Sec. 2.2: the splines are twice differentiable):
- *   out  float [12][np]: u, v, w, then du_i/dx_j at row 3 + 3 i + j. */
+ *   out  float [12][np] (double for PT_F64): u, v, w, then du_i/dx_j at
+ *        row 3 + 3 i + j. */
 pt_status pt_interp_grad(const pt_grid *grid, const void *coeff, pt_dtype dtype,
-                         int64_t np, const double *pos, float *out, hipStream_t stream);
+                         int64_t np, const double *pos, void *out, hipStream_t stream);
 
 /* The sort argument of pt_rk2_step and pt_rk2_step_bwd. */
 enum {
@@ -191,7 +202,8 @@ enum {
 
 /* One RK2 step of dx/dt = u(x) (eq. (dxdt)), Heun's form:
  *   u0 = u(x);  x* = x + dt u0;  u1 = u(x*);  x <- x + dt/2 (u0 + u1),
- * velocities from the spline (FP32), positions in FP64, stored unwrapped.
+ * velocities from the spline (FP32; FP64 for PT_F64), positions in FP64,
+ * stored unwrapped.
  * With sort = PT_SORT the particles are first re-ordered as by
  * pt_sort_particles and pos (and ids, if not NULL) come back in the new
  * order; with PT_UNSORTED or PT_SORTED the order is kept.  Other values of
@@ -216,15 +228,16 @@ pt_status pt_rk2_step(const pt_grid *grid, const void *coeff, pt_dtype dtype,
  *   coeff_n  in   padded coefficients of the field at t_n, of `dtype`
  *   pos      in/out double [3][np]  (only re-ordered)
  *   ids      in/out int32 [np] or NULL
- *   u_n      out  float [3][np], in the order pos leaves in
+ *   u_n      out  float [3][np] (double for PT_F64), in the order pos
+ *                 leaves in
  *   ws            >= pt_workspace_bytes(PT_OP_RK2, ...) bytes */
 pt_status pt_rk2_stage1(const pt_grid *grid, const void *coeff_n, pt_dtype dtype,
-                        int64_t np, double *pos, int32_t *ids, int sort, float *u_n,
+                        int64_t np, double *pos, int32_t *ids, int sort, void *u_n,
                         void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Stage 2, with the coefficients of u(., t_n + dt):
  *   x* = x + dt u_n;  x <- x + dt/2 (u_n + u^{n+1}(x*))
- * (FP64 positions, FP32 velocities), pos updated in place.  With sorted != 0
+ * (FP64 positions, FP32 velocities (FP64 for PT_F64)), pos updated in place.  With sorted != 0
  * the particles are taken in the cell order of the stage 1 that sorted them,
  * and ws must be that call's workspace (same grid, np and size).  The table
  * it holds is checked on the device; a table that is not a partition of the
@@ -233,12 +246,44 @@ pt_status pt_rk2_stage1(const pt_grid *grid, const void *coeff_n, pt_dtype dtype
  * result.  Positions moved since stage 1 are handled the same way.
  *   coeff_np1  in   padded coefficients of the field at t_n + dt
  *   pos        in/out double [3][np]
- *   u_n        in   float [3][np] from stage 1
+ *   u_n        in   float [3][np] (double for PT_F64) from stage 1
  *   ws              >= pt_workspace_bytes(PT_OP_RK2, ...) bytes (unused when
  *                   sorted == 0, may then be NULL) */
 pt_status pt_rk2_stage2(const pt_grid *grid, const void *coeff_np1, pt_dtype dtype,
-                        int64_t np, double dt, double *pos, const float *u_n, int sorted,
+                        int64_t np, double dt, double *pos, const void *u_n, int sorted,
                         void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Inertial or diffusive particles (Sec. 4.3: inertial particles, and
+ * markers of high molecular diffusivity, can move more than one grid spacing
+ * per step; the paper gives no equation for them).  One step h = dt of the
+ * Stokes-drag particle
+ *   dx/dt = v,   dv/dt = (u(x) - v) / tau
+ * solved exactly with the fluid velocity seen over the step taken as linear
+ * in time from u0 = u(x) to u1 = u(x*), where x* is the end point of the
+ * exact solution with the fluid velocity held at u0 (an exponential-integrator
+ * form of Heun's predictor-corrector).  With r = dt/tau, E = exp(-r),
+ * p1 = (1 - E)/r, p2 = (1 - p1)/r:
+ *   x* = x + dt p1 v + dt (1 - p1) u0 + d
+ *   x <- x* + dt (1/2 - p2) (u1 - u0)
+ *   v <- E v + (p1 - E) u0 + (1 - p1) u1
+ * tau = 0 is the fluid tracer (Heun's step of pt_rk2_step, v not used);
+ * d is an optional displacement increment per particle, e.g. the random step
+ * sqrt(2 kappa dt) xi of a diffusive marker, drawn by the caller.  Steps may
+ * move particles any number of cells: a particle whose predicted point leaves
+ * its column's tile is evaluated from global memory.
+ *   dt > 0, tau >= 0 (finite), else PT_ERR_ARG
+ *   pos   in/out double [3][np], unwrapped
+ *   vel   in/out float [3][np] (double for PT_F64); may be NULL only if
+ *              tau = 0 (then neither read nor written)
+ *   disp  in     double [3][np] in the input order, or NULL (no increment)
+ *   ids   in/out int32 [np] or NULL
+ *   sort  as for pt_rk2_step; with PT_SORT, pos, vel and ids come back in
+ *         cell order
+ *   ws          >= pt_workspace_bytes(PT_OP_INERTIAL, ...) bytes */
+pt_status pt_inertial_step(const pt_grid *grid, const void *coeff, pt_dtype dtype, int64_t np,
+                           double dt, double tau, double *pos, void *vel, const double *disp,
+                           int32_t *ids, int sort, void *ws, size_t ws_bytes,
+                           hipStream_t stream);
 
 /* Adjoint of pt_interp_uvw (not in the paper).  With gu = dL/d(u,v,w):
  *   g_pos[d][p]  += sum_c gu[c][p] du_c/dx_d (p)          (may be NULL)

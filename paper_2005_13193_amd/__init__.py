@@ -20,6 +20,7 @@ from . import _binding as _b
 from ._binding import PT_SORT, PT_SORTED, PT_UNSORTED, PtError  # noqa: F401
 
 __all__ = ["Grid", "PtError", "spline_coeffs", "spline_coeffs_bwd", "sort_particles",
+           "inertial_step",
            "interp_uvw", "interp_grad", "interp_uvw_bwd", "rk2_step", "rk2_step_bwd",
            "last_device_error", "workspace", "key_layout"]
 
@@ -52,7 +53,9 @@ class Grid:
 
 
 def _code(dtype):
-    return _b.PT_BF16 if dtype == torch.bfloat16 else _b.PT_F32
+    if dtype == torch.bfloat16:
+        return _b.PT_BF16
+    return _b.PT_F64 if dtype == torch.float64 else _b.PT_F32
 
 
 def workspace(op, grid, np_=0, dtype=torch.float32, device=None):
@@ -133,7 +136,7 @@ def slab_partition(grid, pos, z0, nzl, ids=None, ws=None):
 def interp_uvw(grid, coeff, pos, out=None):
     pos = pos.contiguous()
     if out is None:
-        out = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=pos.device)
+        out = torch.empty((3, pos.shape[1]), dtype=_b.value_dtype(coeff), device=pos.device)
     _b.pt_interp_uvw(grid, coeff, pos, out)
     return out
 
@@ -141,7 +144,7 @@ def interp_uvw(grid, coeff, pos, out=None):
 def interp_grad(grid, coeff, pos, out=None):
     pos = pos.contiguous()
     if out is None:
-        out = torch.empty((12, pos.shape[1]), dtype=torch.float32, device=pos.device)
+        out = torch.empty((12, pos.shape[1]), dtype=_b.value_dtype(coeff), device=pos.device)
     _b.pt_interp_grad(grid, coeff, pos, out)
     return out
 
@@ -167,7 +170,7 @@ def rk2_stage1(grid, coeff_n, pos, ids=None, sort=True, u_n=None, ws=None):
     both to rk2_stage2."""
     np_ = pos.shape[1]
     if u_n is None:
-        u_n = torch.empty((3, np_), dtype=torch.float32, device=pos.device)
+        u_n = torch.empty((3, np_), dtype=_b.value_dtype(coeff_n), device=pos.device)
     if ws is None:
         ws = workspace(_b.PT_OP_RK2, grid, np_, coeff_n.dtype, pos.device)
     _b.pt_rk2_stage1(grid, coeff_n, pos, ids, sort, u_n, ws)
@@ -180,6 +183,17 @@ def rk2_stage2(grid, coeff_np1, pos, u_n, dt, sorted_=True, ws=None):
         raise ValueError("rk2_stage2 with sorted_=True needs the workspace of rk2_stage1")
     _b.pt_rk2_stage2(grid, coeff_np1, dt, pos, u_n, sorted_, ws)
     return pos
+
+
+def inertial_step(grid, coeff, pos, vel, dt, tau, disp=None, ids=None, sort=True, ws=None):
+    """One step of inertial particles (Stokes drag with response time tau;
+    tau = 0 and vel = None is the fluid tracer), in place on pos and vel (and
+    ids); disp: optional displacement increments [3][np] (FP64, input order).
+    sort: as for rk2_step.  Returns (pos, vel)."""
+    if ws is None:
+        ws = workspace(_b.PT_OP_INERTIAL, grid, pos.shape[1], coeff.dtype, pos.device)
+    _b.pt_inertial_step(grid, coeff, dt, tau, pos, vel, disp, ids, sort, ws)
+    return pos, vel
 
 
 def rk2_step_bwd(grid, coeff, pos_n, dt, g_pos, g_coeff, sort=True, ws=None):

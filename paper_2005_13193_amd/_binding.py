@@ -25,6 +25,7 @@ PT_ERR_ARG = -8
 
 PT_F32 = 0
 PT_BF16 = 1
+PT_F64 = 2
 
 PT_OP_SPLINE = 0
 PT_OP_SORT = 1
@@ -33,11 +34,13 @@ PT_OP_SPLINE_BWD = 3
 PT_OP_RK2_BWD = 4
 PT_OP_SPLINE_SLAB = 5
 PT_OP_SLAB_PARTITION = 6
+PT_OP_INERTIAL = 7
 PT_UNSORTED, PT_SORT, PT_SORTED = 0, 1, 2  # sort argument of the RK2 steps
 
 EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_spline_coeffs_slab",
            "pt_sort_particles", "pt_slab_partition",
            "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_rk2_stage1", "pt_rk2_stage2",
+           "pt_inertial_step",
            "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
            "pt_status_string", "pt_timing_enable", "pt_timing_read")
@@ -76,6 +79,8 @@ def _load():
         "pt_rk2_step": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
         "pt_rk2_stage1": [g, vp, ctypes.c_int, i64, vp, vp, ctypes.c_int, vp, vp, sz, vp],
         "pt_rk2_stage2": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
+        "pt_inertial_step": [g, vp, ctypes.c_int, i64, dbl, dbl, vp, vp, vp, vp, ctypes.c_int,
+                             vp, sz, vp],
         "pt_interp_uvw_bwd": [g, vp, ctypes.c_int, i64, vp, vp, vp, vp, vp],
         "pt_spline_coeffs_bwd": [g, vp, vp, vp, sz, vp],
         "pt_rk2_step_bwd": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp, vp, vp, sz,
@@ -126,7 +131,15 @@ def _dtype_code(coeff):
         return PT_F32
     if coeff.dtype in (torch.bfloat16, torch.int16, torch.uint16):
         return PT_BF16
-    raise TypeError(f"coefficients must be float32 or bfloat16, got {coeff.dtype}")
+    if coeff.dtype == torch.float64:
+        return PT_F64
+    raise TypeError(f"coefficients must be float32, bfloat16 or float64, got {coeff.dtype}")
+
+
+def value_dtype(coeff):
+    """Type of the interpolated values and velocities that go with these
+    coefficients: float64 for FP64 coefficients, else float32."""
+    return torch.float64 if coeff.dtype == torch.float64 else torch.float32
 
 
 def _need(t, dtype, shape=None, name="tensor"):
@@ -216,7 +229,7 @@ def pt_interp_uvw(grid, coeff, pos, out, stream=None):
     np_ = pos.shape[1]
     _need(coeff, None, grid.padded_shape, "coeff")
     _need(pos, torch.float64, (3, np_), "pos")
-    _need(out, torch.float32, (3, np_), "out")
+    _need(out, value_dtype(coeff), (3, np_), "out")
     _check("pt_interp_uvw",
            LIB.pt_interp_uvw(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
                              _ptr(pos), _ptr(out), _stream(stream)))
@@ -226,7 +239,7 @@ def pt_interp_grad(grid, coeff, pos, out, stream=None):
     np_ = pos.shape[1]
     _need(coeff, None, grid.padded_shape, "coeff")
     _need(pos, torch.float64, (3, np_), "pos")
-    _need(out, torch.float32, (12, np_), "out")
+    _need(out, value_dtype(coeff), (12, np_), "out")
     _check("pt_interp_grad",
            LIB.pt_interp_grad(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
                               _ptr(pos), _ptr(out), _stream(stream)))
@@ -248,7 +261,7 @@ def pt_rk2_stage1(grid, coeff_n, pos, ids, sort, u_n, ws, stream=None):
     _need(coeff_n, None, grid.padded_shape, "coeff_n")
     _need(pos, torch.float64, (3, np_), "pos")
     _need(ids, torch.int32, (np_,), "ids")
-    _need(u_n, torch.float32, (3, np_), "u_n")
+    _need(u_n, value_dtype(coeff_n), (3, np_), "u_n")
     _check("pt_rk2_stage1",
            LIB.pt_rk2_stage1(ctypes.byref(_grid(grid)), _ptr(coeff_n), _dtype_code(coeff_n), np_,
                              _ptr(pos), _ptr(ids), int(bool(sort)), _ptr(u_n), _ptr(ws),
@@ -260,12 +273,26 @@ def pt_rk2_stage2(grid, coeff_np1, dt, pos, u_n, sorted_, ws, stream=None):
     np_ = pos.shape[1]
     _need(coeff_np1, None, grid.padded_shape, "coeff_np1")
     _need(pos, torch.float64, (3, np_), "pos")
-    _need(u_n, torch.float32, (3, np_), "u_n")
+    _need(u_n, value_dtype(coeff_np1), (3, np_), "u_n")
     _check("pt_rk2_stage2",
            LIB.pt_rk2_stage2(ctypes.byref(_grid(grid)), _ptr(coeff_np1), _dtype_code(coeff_np1),
                              np_, float(dt), _ptr(pos), _ptr(u_n), int(bool(sorted_)), _ptr(ws),
                              0 if ws is None else ws.numel() * ws.element_size(),
                              _stream(stream)))
+
+
+def pt_inertial_step(grid, coeff, dt, tau, pos, vel, disp, ids, sort, ws, stream=None):
+    np_ = pos.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(vel, value_dtype(coeff), (3, np_), "vel")
+    _need(disp, torch.float64, (3, np_), "disp")
+    _need(ids, torch.int32, (np_,), "ids")
+    _check("pt_inertial_step",
+           LIB.pt_inertial_step(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                                float(dt), float(tau), _ptr(pos), _ptr(vel), _ptr(disp),
+                                _ptr(ids), int(sort), _ptr(ws), ws.numel() * ws.element_size(),
+                                _stream(stream)))
 
 
 def pt_interp_uvw_bwd(grid, coeff, pos, g_out, g_pos, g_coeff, stream=None):

@@ -21,7 +21,7 @@ SOURCES = ["api.hip", "solve.hip", "sort.hip", "gather.hip", "tile.hip", "migrat
 ARCH = os.environ.get("PT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wno-unused-command-line-argument",
     # keep single-lane counter draws as plain atomics: the wave-wide rewrite

@@ -8,12 +8,13 @@
 #include <vector>
 
 #include "pt_common.h"
+#include "pt_inertial.h"
 
 namespace pt {
 
 // solve.hip
 size_t spline_ws_floats(const pt_grid* g, pt_dtype dtype);
-size_t spline_slab_ws_floats(const pt_grid* g, int nzl, int W);
+size_t spline_slab_ws_floats(const pt_grid* g, int nzl, int W, pt_dtype dtype);
 pt_status spline_slab_fwd(const pt_grid* g, int nzl, int W, const float* field, void* coeff,
                           pt_dtype dtype, float* ws, hipStream_t s);
 pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype dtype, float* ws,
@@ -30,21 +31,26 @@ pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double
                          hipStream_t s);
 pt_status permute_ids(int64_t np, const int32_t* in, const int32_t* perm, int32_t* out,
                       hipStream_t s);
-// gather.hip
+pt_status permute_rows(int64_t np, const void* in, int elem_bytes, const int32_t* perm, void* out,
+                       hipStream_t s);
+// gather.hip (value arrays: float, or double for PT_F64)
 pt_status interp_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,
-                     const double* pos, float* out, int nout, hipStream_t s);
+                     const double* pos, void* out, int nout, hipStream_t s);
 pt_status rk2_advance(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
-                      const double* x, double* x_out, float* u0, hipStream_t s);
+                      const double* x, double* x_out, void* u0, hipStream_t s);
+pt_status inertial_advance(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,
+                           const InertialCoef& k, const double* x, const void* v,
+                           const double* disp, double* x_out, void* v_out, hipStream_t s);
 pt_status interp_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,
                      const double* pos, const float* gout, double* gpos, float* gcoeff,
                      hipStream_t s);
 pt_status rk2_backward(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
-                       const double* x, const double* lam, double* out, float* gcoeff, float* u0,
+                       const double* x, const double* lam, double* out, float* gcoeff, void* u0,
                        double* xbs, hipStream_t s);
 pt_status scatter_back(int64_t np, const double* in, const int32_t* perm, double* out,
                        hipStream_t s);
 pt_status rk2_correct(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
-                      const double* x, const float* u0, double* x_out, hipStream_t s);
+                      const double* x, const void* u0, double* x_out, hipStream_t s);
 // tile.hip
 int64_t tile_nlayers(const pt_grid* g);
 pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
@@ -56,6 +62,10 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
                        float* u0, float* ub0, float* ub1, float* gcoeff, void* defer,
                        void* items_ws, bool check, hipStream_t s);
 size_t tile_defer_bytes(int64_t np);
+pt_status tile_inertial(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
+                        int64_t np, const InertialCoef& k, const double* x, const float* v,
+                        const double* disp, double* x_out, float* v_out, void* defer,
+                        void* items_ws, bool check, hipStream_t s);
 // migrate.hip
 size_t slab_partition_ws_bytes(int64_t np);
 pt_status slab_partition(const pt_grid* grid, int64_t np, const double* pos, const int32_t* ids,
@@ -109,6 +119,42 @@ void timing_record(const char* name, hipEvent_t start, hipEvent_t stop) {
 
 static inline size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Coefficients of the inertial step (pt_inertial.h) for h > 0, tau >= 0.
+// With r = h / tau: p1 = (1 - e^-r)/r from expm1 (no cancellation), and
+// 1/2 - p2 = 1/2 - (1 - p1)/r, which cancels for small r, from its Taylor
+// series sum_{j>=1} (-1)^(j+1) r^j / (j+2)! there (Horner, 18 terms: below
+// 1e-20 relative for r < 0.5).
+InertialCoef inertial_coef(double h, double tau) {
+  InertialCoef k;
+  if (tau == 0.0) {
+    k.cv = 0.0; k.cu = h; k.cc = 0.5 * h; k.E = 0.0; k.bu0 = 0.0; k.b = 1.0;
+    return k;
+  }
+  const double r = h / tau;
+  const double E = exp(-r);
+  const double p1 = r > 0.0 ? -expm1(-r) / r : 1.0;
+  double half_minus_p2;
+  if (r < 0.5) {
+    // sum_{j=1..18} (-1)^(j+1) r^j / (j+2)!, from the highest term down
+    double acc = 0.0;
+    for (int j = 18; j >= 1; --j) {
+      double f = 1.0;  // 1 / (j+2)!
+      for (int q = 2; q <= j + 2; ++q) f /= (double)q;
+      acc = acc * r + ((j & 1) ? f : -f);
+    }
+    half_minus_p2 = acc * r;
+  } else {
+    half_minus_p2 = 0.5 - (1.0 - p1) / r;
+  }
+  k.cv = h * p1;
+  k.cu = h * (1.0 - p1);
+  k.cc = h * half_minus_p2;
+  k.E = E;
+  k.bu0 = p1 - E;
+  k.b = 1.0 - p1;
+  return k;
+}
+
 static pt_status check_grid(const pt_grid* g) {
   if (!g) return PT_ERR_NULL;
   const int n[3] = {g->nx, g->ny, g->nz};
@@ -134,8 +180,12 @@ static pt_status check_tiled_np(int64_t np) {
 }
 
 static pt_status check_dtype(pt_dtype d) {
-  return (d == PT_F32 || d == PT_BF16) ? PT_OK : PT_ERR_DTYPE;
+  return (d == PT_F32 || d == PT_BF16 || d == PT_F64) ? PT_OK : PT_ERR_DTYPE;
 }
+
+// The column-tiled kernels stage FP32 or BF16 coefficients; FP64 storage
+// takes the one-thread-per-particle gathers on the sorted particles.
+static bool tiled(pt_dtype d) { return d != PT_F64; }
 
 static pt_status ready() { return device_error_flag() ? PT_OK : PT_ERR_HIP; }
 
@@ -153,29 +203,39 @@ struct Rk2Ws {
   double* pos_sorted;
   int32_t* perm;
   int32_t* ids_tmp;
-  float* u0;
+  void* u0;          // 3 np values (float, double for PT_F64)
   int32_t* lstart;
   void* defer;
   void* items;
+  void* vel_sorted;  // inertial step: 3 np values
+  double* disp_sorted;  // inertial step: 3 np doubles
 };
 
-static size_t rk2_ws_bytes(const pt_grid* g, int64_t np) {
+static size_t rk2_ws_bytes(const pt_grid* g, int64_t np, pt_dtype dt) {
   return a256(sort_ws_bytes(g, np)) + a256(24 * (size_t)np) + 2 * a256(4 * (size_t)np) +
-         a256(12 * (size_t)np) + a256(lstart_bytes(g)) + a256(tile_defer_bytes(np)) +
-         a256(tile_items_bytes(g, np, false));
+         a256(3 * value_bytes(dt) * (size_t)np) + a256(lstart_bytes(g)) +
+         a256(tile_defer_bytes(np)) + a256(tile_items_bytes(g, np, false));
 }
 
-static Rk2Ws carve_rk2(const pt_grid* g, int64_t np, void* ws) {
+static size_t inertial_ws_bytes(const pt_grid* g, int64_t np, pt_dtype dt) {
+  return rk2_ws_bytes(g, np, dt) + a256(3 * value_bytes(dt) * (size_t)np) +
+         a256(24 * (size_t)np);
+}
+
+static Rk2Ws carve_rk2(const pt_grid* g, int64_t np, pt_dtype dt, void* ws) {
   char* p = (char*)ws;
   Rk2Ws w;
   w.sort = p; p += a256(sort_ws_bytes(g, np));
   w.pos_sorted = (double*)p; p += a256(24 * (size_t)np);
   w.perm = (int32_t*)p; p += a256(4 * (size_t)np);
   w.ids_tmp = (int32_t*)p; p += a256(4 * (size_t)np);
-  w.u0 = (float*)p; p += a256(12 * (size_t)np);
+  w.u0 = p; p += a256(3 * value_bytes(dt) * (size_t)np);
   w.lstart = (int32_t*)p; p += a256(lstart_bytes(g));
   w.defer = p; p += a256(tile_defer_bytes(np));
-  w.items = p;
+  w.items = p; p += a256(tile_items_bytes(g, np, false));
+  // inertial step only (inertial_ws_bytes)
+  w.vel_sorted = p; p += a256(3 * value_bytes(dt) * (size_t)np);
+  w.disp_sorted = (double*)p;
   return w;
 }
 
@@ -185,20 +245,21 @@ struct Rk2BwdWs {
   int32_t* perm;
   double* xbn;
   double* xbs;   // direct path; the tiled paths keep ub1 (12 bytes/particle) here
-  float* u0;
+  void* u0;      // 3 np values (float, double for PT_F64)
   float* ub0;
   int32_t* lstart;
   void* defer;
   void* items;
 };
 
-static size_t rk2_bwd_ws_bytes(const pt_grid* g, int64_t np) {
+static size_t rk2_bwd_ws_bytes(const pt_grid* g, int64_t np, pt_dtype dt) {
   return a256(sort_ws_bytes(g, np)) + 3 * a256(24 * (size_t)np) + a256(4 * (size_t)np) +
-         2 * a256(12 * (size_t)np) + a256(lstart_bytes(g)) + a256(tile_defer_bytes(np)) +
-         a256(tile_items_bytes(g, np, false)) + a256(tile_items_bytes(g, np, true));
+         a256(3 * value_bytes(dt) * (size_t)np) + a256(12 * (size_t)np) + a256(lstart_bytes(g)) +
+         a256(tile_defer_bytes(np)) + a256(tile_items_bytes(g, np, false)) +
+         a256(tile_items_bytes(g, np, true));
 }
 
-static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, void* ws) {
+static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, pt_dtype dt, void* ws) {
   char* p = (char*)ws;
   Rk2BwdWs w;
   w.sort = p; p += a256(sort_ws_bytes(g, np));
@@ -206,7 +267,7 @@ static Rk2BwdWs carve_rk2_bwd(const pt_grid* g, int64_t np, void* ws) {
   w.xbn = (double*)p; p += a256(24 * (size_t)np);
   w.xbs = (double*)p; p += a256(24 * (size_t)np);
   w.perm = (int32_t*)p; p += a256(4 * (size_t)np);
-  w.u0 = (float*)p; p += a256(12 * (size_t)np);
+  w.u0 = p; p += a256(3 * value_bytes(dt) * (size_t)np);
   w.ub0 = (float*)p; p += a256(12 * (size_t)np);
   w.lstart = (int32_t*)p; p += a256(lstart_bytes(g));
   w.defer = p; p += a256(tile_defer_bytes(np));
@@ -232,10 +293,13 @@ pt_status pt_workspace_bytes(int op, const pt_grid* grid, pt_dtype dtype, int64_
     case PT_OP_SPLINE: *bytes = a256(4 * spline_ws_floats(grid, dtype)); break;
     case PT_OP_SPLINE_BWD: *bytes = a256(4 * n3); break;
     case PT_OP_SORT: *bytes = a256(sort_ws_bytes(grid, np)) + a256(4 * (size_t)np); break;
-    case PT_OP_RK2: *bytes = a256(rk2_ws_bytes(grid, np)); break;
-    case PT_OP_RK2_BWD: *bytes = a256(rk2_bwd_ws_bytes(grid, np)); break;
+    case PT_OP_RK2: *bytes = a256(rk2_ws_bytes(grid, np, dtype)); break;
+    case PT_OP_RK2_BWD: *bytes = a256(rk2_bwd_ws_bytes(grid, np, dtype)); break;
+    case PT_OP_INERTIAL: *bytes = a256(inertial_ws_bytes(grid, np, dtype)); break;
     // np = input planes of the slab, nzl + 3 + 2 W
-    case PT_OP_SPLINE_SLAB: *bytes = a256(4 * spline_slab_ws_floats(grid, (int)np - 3, 0)); break;
+    case PT_OP_SPLINE_SLAB:
+      *bytes = a256(4 * spline_slab_ws_floats(grid, (int)np - 3, 0, dtype));
+      break;
     case PT_OP_SLAB_PARTITION: *bytes = a256(slab_partition_ws_bytes(np)); break;
     default: return PT_ERR_ARG;
   }
@@ -328,7 +392,7 @@ pt_status pt_slab_partition(const pt_grid* grid, int64_t np, const double* pos,
 }
 
 pt_status pt_interp_uvw(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
-                        const double* pos, float* out, hipStream_t stream) {
+                        const double* pos, void* out, hipStream_t stream) {
   PT_TRY(check_grid(grid));
   PT_TRY(check_dtype(dtype));
   PT_TRY(check_np(np));
@@ -339,7 +403,7 @@ pt_status pt_interp_uvw(const pt_grid* grid, const void* coeff, pt_dtype dtype, 
 }
 
 pt_status pt_interp_grad(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
-                         const double* pos, float* out, hipStream_t stream) {
+                         const double* pos, void* out, hipStream_t stream) {
   PT_TRY(check_grid(grid));
   PT_TRY(check_dtype(dtype));
   PT_TRY(check_np(np));
@@ -364,7 +428,7 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
   PT_TRY(pt_workspace_bytes(PT_OP_RK2, grid, dtype, np, &need));
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
   PT_TRY(ready());
-  Rk2Ws w = carve_rk2(grid, np, ws);
+  Rk2Ws w = carve_rk2(grid, np, dtype, ws);
   if (sort == PT_SORT) {
     PT_TRY(sort_particles(grid, np, pos, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
                           stream));
@@ -372,10 +436,12 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
       PT_TRY(permute_ids(np, ids, w.perm, w.ids_tmp, stream));
       PT_HIP_CHECK(hipMemcpyAsync(ids, w.ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
     }
+    if (!tiled(dtype))
+      return rk2_advance(grid, coeff, dtype, np, dt, w.pos_sorted, pos, w.u0, stream);
     return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, pos, w.defer, w.items,
                         false, stream);
   }
-  if (sort == PT_SORTED) {
+  if (sort == PT_SORTED && tiled(dtype)) {
     PT_TRY(presorted_table(grid, np, pos, w.lstart, stream));
     return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, pos, pos, w.defer, w.items, true,
                         stream);
@@ -384,7 +450,7 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
 }
 
 pt_status pt_rk2_stage1(const pt_grid* grid, const void* coeff_n, pt_dtype dtype, int64_t np,
-                        double* pos, int32_t* ids, int sort, float* u_n, void* ws,
+                        double* pos, int32_t* ids, int sort, void* u_n, void* ws,
                         size_t ws_bytes, hipStream_t stream) {
   PT_TRY(check_grid(grid));
   PT_TRY(check_dtype(dtype));
@@ -396,7 +462,7 @@ pt_status pt_rk2_stage1(const pt_grid* grid, const void* coeff_n, pt_dtype dtype
   PT_TRY(pt_workspace_bytes(PT_OP_RK2, grid, dtype, np, &need));
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
   PT_TRY(ready());
-  Rk2Ws w = carve_rk2(grid, np, ws);
+  Rk2Ws w = carve_rk2(grid, np, dtype, ws);
   if (sort) {
     PT_TRY(sort_particles(grid, np, pos, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
                           stream));
@@ -404,14 +470,19 @@ pt_status pt_rk2_stage1(const pt_grid* grid, const void* coeff_n, pt_dtype dtype
       PT_TRY(permute_ids(np, ids, w.perm, w.ids_tmp, stream));
       PT_HIP_CHECK(hipMemcpyAsync(ids, w.ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
     }
-    return tile_tv_stage1(grid, coeff_n, dtype, w.lstart, np, w.pos_sorted, pos, u_n, w.defer,
-                          w.items, stream);
+    if (!tiled(dtype)) {
+      PT_HIP_CHECK(hipMemcpyAsync(pos, w.pos_sorted, 24 * (size_t)np, hipMemcpyDeviceToDevice,
+                                  stream));
+      return interp_fwd(grid, coeff_n, dtype, np, pos, u_n, 3, stream);
+    }
+    return tile_tv_stage1(grid, coeff_n, dtype, w.lstart, np, w.pos_sorted, pos, (float*)u_n,
+                          w.defer, w.items, stream);
   }
   return interp_fwd(grid, coeff_n, dtype, np, pos, u_n, 3, stream);
 }
 
 pt_status pt_rk2_stage2(const pt_grid* grid, const void* coeff_np1, pt_dtype dtype, int64_t np,
-                        double dt, double* pos, const float* u_n, int sorted, void* ws,
+                        double dt, double* pos, const void* u_n, int sorted, void* ws,
                         size_t ws_bytes, hipStream_t stream) {
   PT_TRY(check_grid(grid));
   PT_TRY(check_dtype(dtype));
@@ -421,13 +492,14 @@ pt_status pt_rk2_stage2(const pt_grid* grid, const void* coeff_np1, pt_dtype dty
   if (np == 0) return PT_OK;
   if (!coeff_np1 || !pos || !u_n) return PT_ERR_NULL;
   PT_TRY(ready());
-  if (!sorted) return rk2_correct(grid, coeff_np1, dtype, np, dt, pos, u_n, pos, stream);
+  if (!sorted || !tiled(dtype))
+    return rk2_correct(grid, coeff_np1, dtype, np, dt, pos, u_n, pos, stream);
   size_t need = 0;
   PT_TRY(pt_workspace_bytes(PT_OP_RK2, grid, dtype, np, &need));
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
-  Rk2Ws w = carve_rk2(grid, np, ws);
-  return tile_tv_stage2(grid, coeff_np1, dtype, w.lstart, np, dt, pos, u_n, pos, w.defer,
-                        w.items, stream);
+  Rk2Ws w = carve_rk2(grid, np, dtype, ws);
+  return tile_tv_stage2(grid, coeff_np1, dtype, w.lstart, np, dt, pos, (const float*)u_n, pos,
+                        w.defer, w.items, stream);
 }
 
 pt_status pt_interp_uvw_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
@@ -457,22 +529,77 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
   PT_TRY(pt_workspace_bytes(PT_OP_RK2_BWD, grid, dtype, np, &need));
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
   PT_TRY(ready());
-  Rk2BwdWs w = carve_rk2_bwd(grid, np, ws);
+  Rk2BwdWs w = carve_rk2_bwd(grid, np, dtype, ws);
   if (sort == PT_SORT) {
     PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
                           stream));
-    PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, g_pos, w.xbn, w.u0,
-                        w.ub0, (float*)w.xbs, g_coeff, w.defer, w.items, false, stream));
+    if (!tiled(dtype))
+      PT_TRY(rk2_backward(grid, coeff, dtype, np, dt, w.pos_sorted, g_pos, w.xbn, g_coeff, w.u0,
+                          w.xbs, stream));
+    else
+      PT_TRY(tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, w.pos_sorted, g_pos, w.xbn,
+                          (float*)w.u0, w.ub0, (float*)w.xbs, g_coeff, w.defer, w.items, false,
+                          stream));
     return scatter_back(np, w.xbn, w.perm, g_pos, stream);
   }
-  if (sort == PT_SORTED) {
+  if (sort == PT_SORTED && tiled(dtype)) {
     // the order is kept, so dL/dx_n goes straight into g_pos
     PT_TRY(presorted_table(grid, np, pos_n, w.lstart, stream));
-    return tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, pos_n, g_pos, g_pos, w.u0, w.ub0,
-                        (float*)w.xbs, g_coeff, w.defer, w.items, true, stream);
+    return tile_rk2_bwd(grid, coeff, dtype, w.lstart, np, dt, pos_n, g_pos, g_pos, (float*)w.u0,
+                        w.ub0, (float*)w.xbs, g_coeff, w.defer, w.items, true, stream);
   }
   return rk2_backward(grid, coeff, dtype, np, dt, pos_n, g_pos, g_pos, g_coeff, w.u0, w.xbs,
                       stream);
+}
+
+pt_status pt_inertial_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                           double dt, double tau, double* pos, void* vel, const double* disp,
+                           int32_t* ids, int sort, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (!(dt > 0.0) || !isfinite(dt) || !(tau >= 0.0) || !isfinite(tau)) return PT_ERR_ARG;
+  if (sort != PT_UNSORTED && sort != PT_SORT && sort != PT_SORTED) return PT_ERR_ARG;
+  if (sort != PT_UNSORTED) PT_TRY(check_tiled_np(np));
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos || (tau > 0.0 && !vel)) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_INERTIAL, grid, dtype, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  if (tau == 0.0) vel = nullptr;  // the tracer: no velocity is carried
+  const InertialCoef k = inertial_coef(dt, tau);
+  Rk2Ws w = carve_rk2(grid, np, dtype, ws);
+  const size_t vb = value_bytes(dtype);
+  if (sort == PT_SORT) {
+    PT_TRY(sort_particles(grid, np, pos, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
+                          stream));
+    if (ids) {
+      PT_TRY(permute_ids(np, ids, w.perm, w.ids_tmp, stream));
+      PT_HIP_CHECK(hipMemcpyAsync(ids, w.ids_tmp, 4 * (size_t)np, hipMemcpyDeviceToDevice, stream));
+    }
+    const void* vs = nullptr;
+    if (vel) {
+      PT_TRY(permute_rows(np, vel, (int)vb, w.perm, w.vel_sorted, stream));
+      vs = w.vel_sorted;
+    }
+    const double* ds = nullptr;
+    if (disp) {
+      PT_TRY(permute_rows(np, disp, 8, w.perm, w.disp_sorted, stream));
+      ds = w.disp_sorted;
+    }
+    if (!tiled(dtype))
+      return inertial_advance(grid, coeff, dtype, np, k, w.pos_sorted, vs, ds, pos, vel, stream);
+    return tile_inertial(grid, coeff, dtype, w.lstart, np, k, w.pos_sorted, (const float*)vs, ds,
+                         pos, (float*)vel, w.defer, w.items, false, stream);
+  }
+  if (sort == PT_SORTED && tiled(dtype)) {
+    PT_TRY(presorted_table(grid, np, pos, w.lstart, stream));
+    return tile_inertial(grid, coeff, dtype, w.lstart, np, k, pos, (const float*)vel, disp, pos,
+                         (float*)vel, w.defer, w.items, true, stream);
+  }
+  return inertial_advance(grid, coeff, dtype, np, k, pos, vel, disp, pos, vel, stream);
 }
 
 pt_status pt_last_device_error(hipStream_t stream) {

@@ -71,24 +71,32 @@ __device__ __forceinline__ int cell_1d(double x, double cs, int n, double* t, bo
 
 // ------------------------------------------------------------- weights ---
 // Uniform cubic B-spline pieces on the cell, i = 1..4 <-> coefficient
-// offsets -1..+2 (eq. (spline): p = alpha + i - 2), and their t-derivatives.
-__device__ __forceinline__ void bspline_w(float t, float w[4]) {
-  const float s = 1.0f - t;
-  const float t2 = t * t, t3 = t2 * t;
-  const float r6 = 1.0f / 6.0f;
+// offsets -1..+2 (eq. (spline): p = alpha + i - 2), and their t-derivatives,
+// in the arithmetic type T of the gather (float, or double for FP64 storage).
+template <typename T>
+__device__ __forceinline__ void bspline_w(T t, T w[4]) {
+  const T s = T(1) - t;
+  const T t2 = t * t, t3 = t2 * t;
+  const T r6 = T(1) / T(6);
   w[0] = s * s * s * r6;
-  w[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * r6;
-  w[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * r6;
+  w[1] = (T(3) * t3 - T(6) * t2 + T(4)) * r6;
+  w[2] = (T(-3) * t3 + T(3) * t2 + T(3) * t + T(1)) * r6;
   w[3] = t3 * r6;
 }
 
-__device__ __forceinline__ void bspline_dw(float t, float w[4]) {
-  const float s = 1.0f - t;
-  w[0] = -0.5f * s * s;
-  w[1] = t * (1.5f * t - 2.0f);
-  w[2] = 0.5f + t * (1.0f - 1.5f * t);
-  w[3] = 0.5f * t * t;
+template <typename T>
+__device__ __forceinline__ void bspline_dw(T t, T w[4]) {
+  const T s = T(1) - t;
+  w[0] = T(-0.5) * s * s;
+  w[1] = t * (T(1.5) * t - T(2));
+  w[2] = T(0.5) + t * (T(1) - T(1.5) * t);
+  w[3] = T(0.5) * t * t;
 }
+
+// Arithmetic type of the gathers for a coefficient storage type: FP32 for
+// FP32 and BF16 storage, FP64 for FP64 storage.
+template <typename CT> struct AccOf { using T = float; };
+template <> struct AccOf<double> { using T = double; };
 
 // ------------------------------------------------------------ bfloat16 ---
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
@@ -105,6 +113,12 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 
 __device__ __forceinline__ float load_coeff(const float* p) { return *p; }
 __device__ __forceinline__ float load_coeff(const uint16_t* p) { return bf16_to_f32(*p); }
+__device__ __forceinline__ double load_coeff(const double* p) { return *p; }
+
+// Bytes of one stored coefficient (and of one velocity or interpolated value
+// on the FP64 path, which keeps them in FP64 too).
+inline size_t dtype_bytes(pt_dtype d) { return d == PT_F64 ? 8 : d == PT_BF16 ? 2 : 4; }
+inline size_t value_bytes(pt_dtype d) { return d == PT_F64 ? 8 : 4; }
 
 // ---------------------------------------------------------- host glue ---
 // Per-device pointer to the library's non-finite-position flag.

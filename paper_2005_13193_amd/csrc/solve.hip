@@ -53,16 +53,19 @@
 
 namespace pt {
 
-constexpr float kZ1 = -0.26794919243112270f;  // sqrt(3) - 2
-constexpr float kGain = 1.6076951545867361f;  // -6 z1
+// z1 = sqrt(3) - 2 and the gain -6 z1 in the arithmetic type T of a pass
+// (FP32, or FP64 for FP64 coefficient storage).
+template <typename T> __device__ __forceinline__ constexpr T z1c() { return T(-0.26794919243112270); }
+template <typename T> __device__ __forceinline__ constexpr T gainc() { return T(1.6076951545867361); }
 
-// z1^k rounded to FP32 (0 once it underflows).
-static float z1_pow(int k) {
+// z1^k in FP64 (0 once it underflows); the FP32 passes use it rounded to FP32.
+static double z1_pow_d(int k) {
   double p = 1.0;
   const double z = sqrt(3.0) - 2.0;
   for (int i = 0; i < k && p != 0.0; ++i) p *= z;
-  return (float)p;
+  return p;
 }
+static float z1_pow(int k) { return (float)z1_pow_d(k); }
 
 // Padded index that also holds grid index m (besides m + 1), or -1.
 __device__ __forceinline__ int pad_extra(int m, int n) {
@@ -75,55 +78,59 @@ __device__ __forceinline__ int pad_extra(int m, int n) {
 // and points past len stay zero through both recursions.
 
 // Causal recursion from zero; returns the local end state.
-template <int Q, bool FULL>
-__device__ __forceinline__ float causal_local(float (&v)[Q], int len) {
-  float c = 0.0f, e = 0.0f;
+template <int Q, bool FULL, typename T>
+__device__ __forceinline__ T causal_local(T (&v)[Q], int len) {
+  const T z1 = z1c<T>();
+  T c = 0, e = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    c = v[i] + kZ1 * c;
-    v[i] = (FULL || i < len) ? c : 0.0f;
+    c = v[i] + z1 * c;
+    v[i] = (FULL || i < len) ? c : T(0);
     e = FULL ? c : (i == len - 1 ? c : e);
   }
   return e;
 }
 
 // Adds z1^(i+1) cin to point i (the carry entering the chunk).
-template <int Q, bool FULL>
-__device__ __forceinline__ void causal_carry(float (&v)[Q], int len, float cin) {
-  float p = kZ1 * cin;
+template <int Q, bool FULL, typename T>
+__device__ __forceinline__ void causal_carry(T (&v)[Q], int len, T cin) {
+  const T z1 = z1c<T>();
+  T p = z1 * cin;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    v[i] += (FULL || i < len) ? p : 0.0f;
-    p *= kZ1;
+    v[i] += (FULL || i < len) ? p : T(0);
+    p *= z1;
   }
 }
 
 // Anti-causal recursion from zero (points past len are zero, so it starts at
 // len - 1); returns the local state at the chunk start.
-template <int Q>
-__device__ __forceinline__ float anticausal_local(float (&v)[Q]) {
-  float d = 0.0f;
+template <int Q, typename T>
+__device__ __forceinline__ T anticausal_local(T (&v)[Q]) {
+  const T z1 = z1c<T>();
+  T d = 0;
 #pragma unroll
   for (int i = Q - 1; i >= 0; --i) {
-    d = v[i] + kZ1 * d;
+    d = v[i] + z1 * d;
     v[i] = d;
   }
   return d;
 }
 
 // Adds z1^(len-i) din to point i < len (the carry entering from the right).
-template <int Q, bool FULL>
-__device__ __forceinline__ void anticausal_carry(float (&v)[Q], int len, float din) {
-  float p = 0.0f;
+template <int Q, bool FULL, typename T>
+__device__ __forceinline__ void anticausal_carry(T (&v)[Q], int len, T din) {
+  const T z1 = z1c<T>();
+  T p = 0;
 #pragma unroll
   for (int i = Q - 1; i >= 0; --i) {
-    p = (FULL ? i == Q - 1 : i == len - 1) ? kZ1 * din : p * kZ1;
+    p = (FULL ? i == Q - 1 : i == len - 1) ? z1 * din : p * z1;
     v[i] += p;
   }
 }
 
 // ------------------------------------------------------------ x lines ---
-enum RowMode { ROW_PLAIN = 0, ROW_PAD_F32 = 1, ROW_PAD_BF16 = 2, ROW_FOLD = 3 };
+enum RowMode { ROW_PLAIN = 0, ROW_PAD_F32 = 1, ROW_PAD_BF16 = 2, ROW_FOLD = 3, ROW_PAD_F64 = 4 };
 
 //  PLAIN: plain rows in and out.
 //  PAD_*: plain rows in; the solved row (y, z) is written to every padded
@@ -132,12 +139,12 @@ enum RowMode { ROW_PLAIN = 0, ROW_PAD_F32 = 1, ROW_PAD_BF16 = 2, ROW_FOLD = 3 };
 //  FOLD:  padded rows in: output row (y, z) is the solve of the sum of the
 //         padded copies of the row and, along x, of each point's copies.
 struct RowArgs {
-  const float* in;
+  const void* in;  // float rows (double for ROW_PAD_F64)
   void* out;
   int nx, ny, nz;
   int q;       // points per lane chunk, ceil(nx / 64)
   int nrows;   // ny * nz
-  int pitch;   // LDS floats per wave
+  int pitch;   // LDS words (of the pass's arithmetic type) per wave
   int zpad;    // PAD_*: 1 = rows are grid planes (write z + 1 and its wrapped
                // copy); 0 = rows are already padded planes (write z only)
 };
@@ -146,15 +153,20 @@ struct RowArgs {
 // (lane l reads l q + i) free of bank conflicts for q = 16.
 __device__ __forceinline__ int lds_ix(int p) { return p + (p >> 4); }
 
-template <typename T>
-__device__ __forceinline__ void put(void* out, int64_t i, float s) {
-  if constexpr (sizeof(T) == 4) ((float*)out)[i] = s;
+template <typename TO, typename T>
+__device__ __forceinline__ void put(void* out, int64_t i, T s) {
+  if constexpr (sizeof(TO) == 8) ((double*)out)[i] = s;
+  else if constexpr (sizeof(TO) == 4) ((float*)out)[i] = s;
   else ((uint16_t*)out)[i] = f32_to_bf16_rne(s);
 }
 
 template <int MODE, int Q>
 __global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
-  extern __shared__ float lds[];
+  // arithmetic (and input) type: FP64 for the FP64 padded output
+  using T = typename std::conditional<MODE == ROW_PAD_F64, double, float>::type;
+  extern __shared__ __align__(16) unsigned char lds_bytes[];
+  T* lds = (T*)lds_bytes;
+  const T kZ1 = z1c<T>(), kGain = gainc<T>();
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int r = blockIdx.x * (blockDim.x >> 6) + wid;
@@ -162,15 +174,15 @@ __global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
   const int nx = a.nx, px = nx + 3;
   const int64_t py = a.ny + 3;
   const int y = active ? r % a.ny : 0, z = active ? r / a.ny : 0;
-  float* L = lds + wid * a.pitch;
+  T* L = lds + wid * a.pitch;
 
   // 1. contiguous loads (all issued before the first LDS write), then LDS.
   // A row has at most 64 Q + 3 points: Q + 1 loads per lane.
   constexpr int J = Q + 1;
-  float w[J];
+  T w[J];
   if (active) {
     if (MODE == ROW_FOLD) {
-      const float* in = a.in;
+      const float* in = (const float*)a.in;
       const int ye = pad_extra(y, a.ny), ze = pad_extra(z, a.nz);
       const float* r00 = in + ((int64_t)(z + 1) * py + (y + 1)) * px;
       const float* r01 = in + ((int64_t)(z + 1) * py + ye) * px;
@@ -201,11 +213,11 @@ __global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
         if (p < px) L[lds_ix(p)] = w[j];
       }
     } else {
-      const float* src = a.in + (int64_t)r * nx;
+      const T* src = (const T*)a.in + (int64_t)r * nx;
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         const int p = lane + 64 * j;
-        w[j] = p < nx ? src[p] : 0.0f;
+        w[j] = p < nx ? src[p] : T(0);
       }
 #pragma unroll
       for (int j = 0; j < J; ++j) {
@@ -221,28 +233,28 @@ __global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
   const int len = active ? min(max(nx - m0, 0), a.q) : 0;
   const int last = max(len - 1, 0);
   const int off = MODE == ROW_FOLD ? 1 : 0;  // padded position of point x is x + 1
-  float v[Q];
+  T v[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int x = min(m0 + min(i, last), nx - 1);  // in the row even when len = 0
-    float t = L[lds_ix(x + off)];
+    T t = L[lds_ix(x + off)];
     if (MODE == ROW_FOLD) {
       const int xe = pad_extra(x, nx);
       if (xe >= 0) t += L[lds_ix(xe)];
     }
-    v[i] = i < len ? t : 0.0f;
+    v[i] = i < len ? t : T(0);
   }
   __syncthreads();
 
   // 3. the periodic solve of the row
-  float a_len = 1.0f;  // z1^len
+  T a_len = 1;  // z1^len
 #pragma unroll
   for (int i = 0; i < Q; ++i) a_len = i < len ? a_len * kZ1 : a_len;
-  const float e = causal_local<Q, false>(v, len);
-  float sa = a_len, se = e;
+  const T e = causal_local<Q, false>(v, len);
+  T sa = a_len, se = e;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const float pa = __shfl_up(sa, d), pe = __shfl_up(se, d);
+    const T pa = __shfl_up(sa, d), pe = __shfl_up(se, d);
     if (lane >= d) {
       se = sa * pe + se;
       sa = sa * pa;
@@ -250,36 +262,36 @@ __global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
   }
   {
     // the whole row maps C -> A C + B; periodicity fixes C = B / (1 - A)
-    const float A = __shfl(sa, 63), B = __shfl(se, 63);
-    const float C0 = B / (1.0f - A);
-    const float pa = __shfl_up(sa, 1), pe = __shfl_up(se, 1);
+    const T A = __shfl(sa, 63), B = __shfl(se, 63);
+    const T C0 = B / (T(1) - A);
+    const T pa = __shfl_up(sa, 1), pe = __shfl_up(se, 1);
     causal_carry<Q, false>(v, len, lane == 0 ? C0 : pa * C0 + pe);
   }
-  const float f = anticausal_local<Q>(v);
+  const T f = anticausal_local<Q>(v);
   sa = a_len;
-  float sf = f;
+  T sf = f;
 #pragma unroll
   for (int s = 1; s < 64; s <<= 1) {
-    const float pa = __shfl_down(sa, s), pf = __shfl_down(sf, s);
+    const T pa = __shfl_down(sa, s), pf = __shfl_down(sf, s);
     if (lane + s < 64) {
       sf = sa * pf + sf;
       sa = sa * pa;
     }
   }
   {
-    const float A = __shfl(sa, 0), B = __shfl(sf, 0);
-    const float D0 = B / (1.0f - A);
-    const float pa = __shfl_down(sa, 1), pf = __shfl_down(sf, 1);
+    const T A = __shfl(sa, 0), B = __shfl(sf, 0);
+    const T D0 = B / (T(1) - A);
+    const T pa = __shfl_down(sa, 1), pf = __shfl_down(sf, 1);
     anticausal_carry<Q, false>(v, len, lane == 63 ? D0 : pa * D0 + pf);
   }
 
   // 4. results back to LDS (padded positions for PAD), then contiguous stores
-  const bool pad_out = MODE == ROW_PAD_F32 || MODE == ROW_PAD_BF16;
+  const bool pad_out = MODE == ROW_PAD_F32 || MODE == ROW_PAD_BF16 || MODE == ROW_PAD_F64;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (i < len) {
       const int x = m0 + i;
-      const float s = kGain * v[i];
+      const T s = kGain * v[i];
       if (pad_out) {
         L[lds_ix(x + 1)] = s;
         const int xe = pad_extra(x, nx);
@@ -295,10 +307,12 @@ __global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int p = lane + 64 * j;
-    w[j] = p < n_out ? L[lds_ix(p)] : 0.0f;
+    w[j] = p < n_out ? L[lds_ix(p)] : T(0);
   }
   if (pad_out) {
-    using T = typename std::conditional<MODE == ROW_PAD_F32, float, uint16_t>::type;
+    using TO = typename std::conditional<
+        MODE == ROW_PAD_F64, double,
+        typename std::conditional<MODE == ROW_PAD_F32, float, uint16_t>::type>::type;
     const int ye = pad_extra(y, a.ny), ze = a.zpad ? pad_extra(z, a.nz) : -1;
     const int Ys[2] = {y + 1, ye}, Zs[2] = {a.zpad ? z + 1 : z, ze};
     for (int zc = 0; zc < 2; ++zc) {
@@ -309,12 +323,12 @@ __global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
 #pragma unroll
         for (int j = 0; j < J; ++j) {
           const int p = lane + 64 * j;
-          if (p < px) put<T>(a.out, row + p, w[j]);
+          if (p < px) put<TO>(a.out, row + p, w[j]);
         }
       }
     }
   } else {
-    float* dst = (float*)a.out + (int64_t)r * nx;
+    T* dst = (T*)a.out + (int64_t)r * nx;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int p = lane + 64 * j;
@@ -327,16 +341,16 @@ __global__ __launch_bounds__(256) void solve_rows(RowArgs a) {
 // Lines along axis A (length na), stride sa; lanes across x; third axis B
 // (stride sb); plain layout in and out.
 struct LineArgs {
-  const float* in;
-  float* out;
+  const void* in;  // float, or double for the FP64 passes after the first
+  void* out;       // float, or double for the FP64 passes
   int nx, na;
   int64_t sa, sb;
   int G;          // x points per lane group; a wave holds 64 / G chunks
   int K;          // chunks per line
   int L;          // chunk length
-  float a_full;   // z1^L
-  float a_last;   // z1^(length of the last, shorter chunk)
-  float closure;  // 1 / (1 - z1^na); 1 for open lines
+  double a_full;   // z1^L (in the pass's arithmetic type, widened)
+  double a_last;   // z1^(length of the last, shorter chunk)
+  double closure;  // 1 / (1 - z1^na); 1 for open lines
   int open;       // 1: lines with open ends (recursions start from zero at
                   // the ends), 0: periodic lines
   int bx0;        // first x-block of the launch
@@ -345,18 +359,22 @@ struct LineArgs {
                   // for solve_yx (whole chunks of a multiple of 16 points)
 };
 
-__device__ __forceinline__ float chunk_gain(const LineArgs& a, int k) {
+template <typename T>
+__device__ __forceinline__ T chunk_gain(const LineArgs& a, int k) {
   const int lk = min(max(a.na - k * a.L, 0), a.L);
-  return lk == a.L ? a.a_full : (lk == 0 ? 1.0f : a.a_last);
+  return lk == a.L ? (T)a.a_full : (lk == 0 ? T(1) : (T)a.a_last);
 }
 
 // FULL: every thread of the launch holds a whole chunk of Q = L points
 // (launched only on x-blocks inside nx, with K * L = na).
 // CARRY: write only the run carries to a.carry (FULL launches only).
-template <int Q, bool FULL, bool CARRY = false>
+// TI: input type; T: arithmetic and output type (float, float or float,
+// double or double, double).
+template <int Q, bool FULL, bool CARRY = false, typename TI = float, typename T = float>
 __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
-  __shared__ float s_e[1024];
-  __shared__ float s_f[1024];
+  __shared__ T s_e[1024];
+  __shared__ T s_f[1024];
+  const T kGain = gainc<T>();
   const int lane = threadIdx.x & 63;
   const int xg = lane & (a.G - 1);
   const int k = (threadIdx.x >> 6) * (64 / a.G) + lane / a.G;
@@ -366,34 +384,36 @@ __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
   const int len = FULL ? Q : (x < a.nx ? min(max(a.na - m0, 0), a.L) : 0);
   const int last = max(len - 1, 0);
 
-  float v[Q];
+  T v[Q];
   {
     // clamped addresses keep every load in bounds; selects zero the rest
-    const float* src = len > 0 ? a.in + x + (int64_t)b * a.sb + (int64_t)m0 * a.sa : a.in;
+    const TI* in = (const TI*)a.in;
+    const TI* src = len > 0 ? in + x + (int64_t)b * a.sb + (int64_t)m0 * a.sa : in;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const float t = *src;
-      v[i] = (FULL || i < len) ? t : 0.0f;
+      const T t = (T)*src;
+      v[i] = (FULL || i < len) ? t : T(0);
       src += (FULL || i < last) ? a.sa : 0;
     }
   }
 
   s_e[k * a.G + xg] = causal_local<Q, FULL>(v, len);
   __syncthreads();
-  float s_c;  // the causal carry entering this chunk
+  const T closure = (T)a.closure;
+  T s_c;  // the causal carry entering this chunk
   {
-    float cin = 0.0f, P = 1.0f;
+    T cin = 0, P = 1;
     const int jn = a.open ? k : a.K;  // chunks before this one (open: no wrap)
-    for (int j = 1; j <= jn && P != 0.0f; ++j) {
+    for (int j = 1; j <= jn && P != T(0); ++j) {
       int kk = k - j;
       if (kk < 0) kk += a.K;
       cin += P * s_e[kk * a.G + xg];
-      P *= chunk_gain(a, kk);
+      P *= chunk_gain<T>(a, kk);
     }
-    causal_carry<Q, FULL>(v, len, cin * a.closure);
-    s_c = cin * a.closure;
+    causal_carry<Q, FULL>(v, len, cin * closure);
+    s_c = cin * closure;
   }
-  float cv[Q / 16 > 1 ? Q / 16 - 1 : 1];  // causal values ending runs of 16
+  T cv[Q / 16 > 1 ? Q / 16 - 1 : 1];  // causal values ending runs of 16
   if constexpr (CARRY) {
 #pragma unroll
     for (int r = 0; r + 1 < Q / 16; ++r) cv[r] = v[16 * r + 15];
@@ -401,37 +421,37 @@ __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
   s_f[k * a.G + xg] = anticausal_local<Q>(v);
   __syncthreads();
   {
-    float din = 0.0f, R = 1.0f;
+    T din = 0, R = 1;
     const int jn = a.open ? a.K - 1 - k : a.K;
-    for (int j = 1; j <= jn && R != 0.0f; ++j) {
+    for (int j = 1; j <= jn && R != T(0); ++j) {
       int kk = k + j;
       if (kk >= a.K) kk -= a.K;
       din += R * s_f[kk * a.G + xg];
-      R *= chunk_gain(a, kk);
+      R *= chunk_gain<T>(a, kk);
     }
     if constexpr (CARRY) {
       // the state entering each run of 16 points from the left (the causal
       // value before it) and from the right (the anti-causal value after it)
       constexpr int R = Q / 16;
-      float cl[R];
+      T cl[R];
       cl[0] = s_c;
 #pragma unroll
       for (int r = 1; r < R; ++r) cl[r] = cv[r - 1];
-      anticausal_carry<Q, FULL>(v, len, din * a.closure);
+      anticausal_carry<Q, FULL>(v, len, din * closure);
       if (len > 0) {
-        float* cr = a.carry + ((int64_t)b * a.na + m0) / 16 * 2 * a.nx + x;
+        T* cr = (T*)a.carry + ((int64_t)b * a.na + m0) / 16 * 2 * a.nx + x;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           cr[2 * r * a.nx] = cl[r];
-          cr[(2 * r + 1) * a.nx] = r + 1 < R ? v[16 * (r + 1)] : din * a.closure;
+          cr[(2 * r + 1) * a.nx] = r + 1 < R ? v[16 * (r + 1)] : din * closure;
         }
       }
       return;
     }
-    anticausal_carry<Q, FULL>(v, len, din * a.closure);
+    anticausal_carry<Q, FULL>(v, len, din * closure);
   }
 
-  float* o = a.out + x + (int64_t)b * a.sb + (int64_t)m0 * a.sa;
+  T* o = (T*)a.out + x + (int64_t)b * a.sb + (int64_t)m0 * a.sa;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (FULL || i < len) *o = kGain * v[i];
@@ -462,6 +482,7 @@ struct YXArgs {
 
 template <int W, int QY, typename T>
 __global__ __launch_bounds__(1024) void solve_yx(YXArgs a) {
+  const float kZ1 = z1c<float>(), kGain = gainc<float>();
   extern __shared__ float lds[];
   constexpr int QX = W;  // x points per lane: nx = 64 W
   constexpr int J = QX + 1;
@@ -568,7 +589,13 @@ __global__ __launch_bounds__(1024) void solve_yx(YXArgs a) {
 
 // ------------------------------------------------------------ launchers ---
 
-static pt_status pass_rows(const float* in, void* out, int nx, int ny, int nz, int mode,
+template <typename F>
+static bool allow_lds(F* fn, size_t bytes) {
+  return hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes) == hipSuccess;
+}
+
+static pt_status pass_rows(const void* in, void* out, int nx, int ny, int nz, int mode,
                            hipStream_t s, int zpad = 1) {
   RowArgs a;
   a.in = in;
@@ -579,14 +606,18 @@ static pt_status pass_rows(const float* in, void* out, int nx, int ny, int nz, i
   a.nrows = ny * nz;
   const int px = nx + 3;
   a.pitch = px + (px >> 4) + 1;
-  const int waves = 4 * (size_t)a.pitch * 4 <= 64 * 1024 ? 4 : 1;
-  const size_t lds = (size_t)waves * a.pitch * 4;
+  const size_t wb = mode == ROW_PAD_F64 ? 8 : 4;  // bytes per LDS word
+  const int waves = 4 * (size_t)a.pitch * wb <= 64 * 1024 ? 4 : 1;
+  const size_t lds = (size_t)waves * a.pitch * wb;
   const unsigned blocks = (unsigned)((a.nrows + waves - 1) / waves);
   const char* name = mode == ROW_FOLD ? "spline_x_fold"
                      : mode == ROW_PLAIN ? "spline_x" : "spline_x_pad";
   TimedLaunch t(name, s);
-#define PT_ROWS(M, QQ) \
-  hipLaunchKernelGGL((solve_rows<M, QQ>), dim3(blocks), dim3(64 * waves), lds, s, a)
+#define PT_ROWS(M, QQ)                                                                  \
+  do {                                                                                  \
+    if (lds > 65536 && !allow_lds(solve_rows<M, QQ>, lds)) return PT_ERR_HIP;           \
+    hipLaunchKernelGGL((solve_rows<M, QQ>), dim3(blocks), dim3(64 * waves), lds, s, a); \
+  } while (0)
 #define PT_ROWS_Q(M)                    \
   do {                                  \
     if (a.q <= 4) PT_ROWS(M, 4);        \
@@ -601,6 +632,7 @@ static pt_status pass_rows(const float* in, void* out, int nx, int ny, int nz, i
     case ROW_PLAIN: PT_ROWS_Q(ROW_PLAIN); break;
     case ROW_PAD_F32: PT_ROWS_Q(ROW_PAD_F32); break;
     case ROW_PAD_BF16: PT_ROWS_Q(ROW_PAD_BF16); break;
+    case ROW_PAD_F64: PT_ROWS_Q(ROW_PAD_F64); break;
     default: PT_ROWS_Q(ROW_FOLD); break;
   }
 #undef PT_ROWS_Q
@@ -631,9 +663,14 @@ static bool line_shape(int na, int* Q, int* G, int* waves) {
   return false;
 }
 
+// Precisions of a line pass: FP32 in and out, FP32 in and FP64 out (the
+// first pass of an FP64 solve), FP64 in and out.
+enum { LINES_F32 = 0, LINES_F32_F64 = 1, LINES_F64 = 2 };
+
 // axis 1 = y, axis 2 = z; plain layout in and out.
-static pt_status pass_lines(const float* in, float* out, int nx, int ny, int nz, int axis,
-                            hipStream_t s, int open = 0, float* carry = nullptr) {
+static pt_status pass_lines(const void* in, void* out, int nx, int ny, int nz, int axis,
+                            hipStream_t s, int open = 0, float* carry = nullptr,
+                            int prec = LINES_F32) {
   LineArgs a;
   a.in = in;
   a.out = out;
@@ -653,15 +690,47 @@ static pt_status pass_lines(const float* in, float* out, int nx, int ny, int nz,
   a.G = G;
   a.K = waves * (64 / G);
   a.L = (a.na + a.K - 1) / a.K;
-  a.a_full = z1_pow(a.L);
-  a.a_last = z1_pow(a.na - (a.na / a.L) * a.L);
-  a.closure = open ? 1.0f : (float)(1.0 / (1.0 - (double)z1_pow(a.na)));
+  if (prec == LINES_F32) {
+    a.a_full = z1_pow(a.L);
+    a.a_last = z1_pow(a.na - (a.na / a.L) * a.L);
+    a.closure = open ? 1.0f : (float)(1.0 / (1.0 - (double)z1_pow(a.na)));
+  } else {
+    a.a_full = z1_pow_d(a.L);
+    a.a_last = z1_pow_d(a.na - (a.na / a.L) * a.L);
+    a.closure = open ? 1.0 : 1.0 / (1.0 - z1_pow_d(a.na));
+  }
   // Whole chunks everywhere except possibly a last, partial x-block: the
   // FULL kernel takes the whole x-blocks, the general one the rest.
   const int xblocks = (nx + G - 1) / G;
   const int full_x = (a.L == Q && a.K * a.L == a.na) ? nx / G : 0;
   const dim3 block(64 * waves);
   TimedLaunch t(carry ? "spline_y_carry" : (axis == 2 ? "spline_z" : "spline_y"), s);
+  if (prec != LINES_F32) {
+    if (carry) return PT_ERR_UNSUPPORTED;
+#define PT_LINES64(QQ, FF, TI)                                                              \
+  hipLaunchKernelGGL((solve_lines<QQ, FF, false, TI, double>), grid2, block, 0, s, a)
+#define PT_LINES64_Q(FF, TI)                   \
+  do {                                         \
+    if (Q == 32) PT_LINES64(32, FF, TI);       \
+    else PT_LINES64(64, FF, TI);               \
+  } while (0)
+    if (full_x > 0) {
+      a.bx0 = 0;
+      const dim3 grid2(full_x, nb);
+      if (prec == LINES_F32_F64) PT_LINES64_Q(true, float);
+      else PT_LINES64_Q(true, double);
+    }
+    if (full_x < xblocks) {
+      a.bx0 = full_x;
+      const dim3 grid2(xblocks - full_x, nb);
+      if (prec == LINES_F32_F64) PT_LINES64_Q(false, float);
+      else PT_LINES64_Q(false, double);
+    }
+#undef PT_LINES64_Q
+#undef PT_LINES64
+    PT_LAUNCH_CHECK();
+    return PT_OK;
+  }
   if (carry) {
     if (full_x != xblocks) return PT_ERR_UNSUPPORTED;
     a.bx0 = 0;
@@ -713,11 +782,6 @@ static size_t yx_carry_floats(const pt_grid* g, int planes) {
   return 2 * (size_t)K * g->nx * planes;
 }
 
-template <typename F>
-static bool allow_lds(F* fn, size_t bytes) {
-  return hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes) == hipSuccess;
-}
 
 // y then x of `planes` planes of in (plain, z-solved) into the padded out:
 // the carries-only y pass into carry, then solve_yx.
@@ -762,6 +826,7 @@ static pt_status pass_yx(const float* in, float* carry, void* out, bool bf16, in
 
 size_t spline_ws_floats(const pt_grid* g, pt_dtype dtype) {
   const size_t n3 = (size_t)g->nx * g->ny * g->nz;
+  if (dtype == PT_F64) return 2 * n3;  // the z- and y-solved component, FP64
   const size_t cf = yx_carry_floats(g, g->nz);
   if (cf) return n3 + 64 + cf;  // z-solved field, then the y carries
   return dtype == PT_BF16 ? 2 * n3 : n3;
@@ -772,6 +837,21 @@ pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype
   const int nx = g->nx, ny = g->ny, nz = g->nz;
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int64_t p3 = (int64_t)(nx + 3) * (ny + 3) * (nz + 3);
+  if (dtype == PT_F64) {
+    // FP64 arithmetic throughout: z pass (FP32 field in), y pass in place
+    // (a line pass reads all of its lines before it writes any, and
+    // workgroups own disjoint lines), x pass into the padded FP64 output
+    double* t = (double*)ws;
+    for (int c = 0; c < 3; ++c) {
+      pt_status st = pass_lines(field + c * n3, t, nx, ny, nz, 2, s, 0, nullptr, LINES_F32_F64);
+      if (st != PT_OK) return st;
+      st = pass_lines(t, t, nx, ny, nz, 1, s, 0, nullptr, LINES_F64);
+      if (st != PT_OK) return st;
+      st = pass_rows(t, (double*)coeff + c * p3, nx, ny, nz, ROW_PAD_F64, s);
+      if (st != PT_OK) return st;
+    }
+    return PT_OK;
+  }
   const bool fused = yx_carry_floats(g, nz) > 0;
   for (int c = 0; c < 3; ++c) {
     const float* f = field + c * n3;
@@ -802,8 +882,9 @@ pt_status spline_fwd(const pt_grid* g, const float* field, void* coeff, pt_dtype
   return PT_OK;
 }
 
-size_t spline_slab_ws_floats(const pt_grid* g, int nzl, int W) {
+size_t spline_slab_ws_floats(const pt_grid* g, int nzl, int W, pt_dtype dtype) {
   const size_t planes = (size_t)(nzl + 3 + 2 * W);
+  if (dtype == PT_F64) return 2 * (size_t)g->nx * g->ny * planes;
   const size_t cf = yx_carry_floats(g, (int)planes);
   return (size_t)g->nx * g->ny * planes + (cf ? 64 + cf : 0);
 }
@@ -816,6 +897,20 @@ pt_status spline_slab_fwd(const pt_grid* g, int nzl, int W, const float* field, 
   const int nzo = nzl + 3, nzi = nzo + 2 * W;
   const int64_t plane = (int64_t)nx * ny;
   const int64_t pb = (int64_t)(nx + 3) * (ny + 3) * nzo;  // output block per component
+  if (dtype == PT_F64) {
+    double* t = (double*)ws;
+    for (int c = 0; c < 3; ++c) {
+      pt_status st = pass_lines(field + c * plane * nzi, t, nx, ny, nzi, 2, s, 1, nullptr,
+                                LINES_F32_F64);
+      if (st != PT_OK) return st;
+      double* mid = t + plane * W;
+      st = pass_lines(mid, mid, nx, ny, nzo, 1, s, 0, nullptr, LINES_F64);
+      if (st != PT_OK) return st;
+      st = pass_rows(mid, (double*)coeff + c * pb, nx, ny, nzo, ROW_PAD_F64, s, 0);
+      if (st != PT_OK) return st;
+    }
+    return PT_OK;
+  }
   for (int c = 0; c < 3; ++c) {
     // z with open ends over all nzi planes into the workspace, then y and x
     // of the nzo central planes: fused where solve_yx applies, else y in

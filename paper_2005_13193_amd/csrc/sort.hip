@@ -317,6 +317,20 @@ __global__ __launch_bounds__(256) void permute_i32(int64_t np, const int32_t* __
   if ((uint64_t)p < (uint64_t)np) out[i] = in[p];
 }
 
+// out[r][i] = in[r][perm[i]] for the three rows of a [3][np] array.
+template <typename T>
+__global__ __launch_bounds__(256) void permute_rows3(int64_t np, const T* __restrict__ in,
+                                                     const int32_t* __restrict__ perm,
+                                                     T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  const int64_t p = perm[i];
+  if ((uint64_t)p >= (uint64_t)np) return;
+  out[i] = in[p];
+  out[np + i] = in[np + p];
+  out[2 * np + i] = in[2 * np + p];
+}
+
 template <typename K>
 __global__ __launch_bounds__(256) void widen_keys(int64_t np, const K* __restrict__ k,
                                                   uint64_t* __restrict__ out) {
@@ -450,6 +464,19 @@ pt_status sort_particles(const pt_grid* g, int64_t np, const double* pos, double
                        pos_sorted);
     PT_LAUNCH_CHECK();
   }
+  return PT_OK;
+}
+
+// [3][np] rows of 4- or 8-byte elements permuted as the particles.
+pt_status permute_rows(int64_t np, const void* in, int elem_bytes, const int32_t* perm, void* out,
+                       hipStream_t s) {
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(permute_rows3<double>, dim3(grid_1d(np, 256)), dim3(256), 0, s, np,
+                       (const double*)in, perm, (double*)out);
+  else
+    hipLaunchKernelGGL(permute_rows3<float>, dim3(grid_1d(np, 256)), dim3(256), 0, s, np,
+                       (const float*)in, perm, (float*)out);
+  PT_LAUNCH_CHECK();
   return PT_OK;
 }
 

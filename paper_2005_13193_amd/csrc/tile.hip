@@ -23,6 +23,7 @@
 // plane at a time; launches by colour keep concurrent workgroups on disjoint
 // coefficients, and stencils that do not fit go to scatter_deferred.
 #include "pt_common.h"
+#include "pt_inertial.h"
 
 namespace pt {
 
@@ -55,6 +56,9 @@ struct TileArgs {
   float* u0;              // bwd: stage-1 velocity  [3][np]
   float* ub0;             // bwd: adjoint of stage-1 velocity [3][np]
   float* ub1;             // bwd: adjoint of stage-2 velocity, dt/2 lam [3][np]
+  const double* disp;     // inertial: displacement increments [3][np] or null
+  float* vel_out;         // inertial: new particle velocities [3][np] or null
+  InertialCoef ik;        // inertial: step coefficients
   float* gcoeff;          // scatter target (padded FP32)
   uint32_t* defer;        // scatter: deferred stencils (2 p + stage)
   int* defer_count;
@@ -169,10 +173,17 @@ constexpr int kGChunks = (kGComp + 63) / 64;   // 64-word chunks per component (
 constexpr int kGChunksPerLoader = (kGChunks + kLoaders - 1) / kLoaders;
 constexpr int kGGroups = kCompute / 4;
 
-// Modes of the tiled gather: the fused Heun step, its adjoint's gathers, and
-// the two stages of a Heun step in a field that changes over the step
-// (stage 1 with the field at t_n, stage 2 with the field at t_n + dt).
-enum { TILE_RK2_FWD = 0, TILE_RK2_BWD_GRAD = 1, TILE_TV_STAGE1 = 2, TILE_TV_STAGE2 = 3 };
+// Modes of the tiled gather: the fused Heun step, its adjoint's gathers, the
+// two stages of a Heun step in a field that changes over the step (stage 1
+// with the field at t_n, stage 2 with the field at t_n + dt), and the
+// inertial / diffusive particle step (both stages, velocities carried).
+enum {
+  TILE_RK2_FWD = 0,
+  TILE_RK2_BWD_GRAD = 1,
+  TILE_TV_STAGE1 = 2,
+  TILE_TV_STAGE2 = 3,
+  TILE_INERTIAL = 4
+};
 
 __device__ __forceinline__ int gslot(int P) { return (P + kGRing) % kGRing; }
 
@@ -234,8 +245,8 @@ __device__ __forceinline__ void eval_ring(const uint32_t* ring, const GridDev& g
 // Per-particle data of one pass.
 struct PData {
   double x[3];
-  double lam[3];
-  float un[3];  // stage 2: velocity of stage 1
+  double lam[3];  // backward: dL/dx_out; inertial: displacement increment
+  float un[3];    // stage 2: velocity of stage 1; inertial: particle velocity
   int p;
   bool ok;
 };
@@ -255,6 +266,14 @@ __device__ __forceinline__ void load_pdata(const TileArgs& a, int64_t p, bool ok
   if (MODE == TILE_TV_STAGE2) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) d->un[c] = a.u0[c * np + i];
+  }
+  if (MODE == TILE_INERTIAL) {
+    // a null velocity (tracer) or increment reads as zero (uniform branches)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      d->un[c] = a.u0 ? a.u0[c * np + i] : 0.0f;
+      d->lam[c] = a.disp ? a.disp[c * np + i] : 0.0;
+    }
   }
 }
 
@@ -297,6 +316,7 @@ __device__ __forceinline__ void flush_pend(const TileArgs& a, Pend* o, DeferBatc
       a.ub1[o->off] = o->f2;
     } else {
       if (MODE == TILE_TV_STAGE1) a.u0[o->off] = o->f0;
+      if (MODE == TILE_INERTIAL && a.vel_out) a.vel_out[o->off] = o->f0;
       a.x_out[o->off] = o->d;
     }
   }
@@ -362,6 +382,28 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
       const float ub = lane == 0 ? u1[0] : lane == 1 ? u1[1] : u1[2];
       o->off = lane * np + p;
       o->d = x0 + h * ((double)ua + (double)ub);
+    }
+  } else if (MODE == TILE_INERTIAL) {
+    float u0[12], u1[12];
+    eval_ring<CT, false>(ring, g, qn, X0, Y0, lane, u0);
+    double xs[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      xs[c] = inertial_predict(a.ik, xn[c], (double)d.un[c], (double)u0[c], d.lam[c]);
+    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
+    if (!qs.in_ring) {
+      if (lane == 0) o->defer = d.p;
+      return;
+    }
+    eval_ring<CT, false>(ring, g, qs, X0, Y0, lane, u1);
+    if (lane < 3) {
+      const double xl = lane == 0 ? xs[0] : lane == 1 ? xs[1] : xs[2];
+      const double ua = lane == 0 ? u0[0] : lane == 1 ? u0[1] : u0[2];
+      const double ub = lane == 0 ? u1[0] : lane == 1 ? u1[1] : u1[2];
+      const double vl = lane == 0 ? d.un[0] : lane == 1 ? d.un[1] : d.un[2];
+      o->off = lane * np + p;
+      o->d = inertial_correct(a.ik, xl, ua, ub);
+      o->f0 = (float)inertial_velocity(a.ik, vl, ua, ub);
     }
   } else if (MODE == TILE_RK2_FWD) {
     float u0[12], u1[12];
@@ -677,6 +719,23 @@ __global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
       eval_global<CT, false>(coeff, g, qs, u1);
       for (int c = 0; c < 3; ++c)
         a.x_out[c * np + p] = xn[c] + 0.5 * a.dt * ((double)ua[c] + (double)u1[c]);
+    } else if (MODE == TILE_INERTIAL) {
+      float u0[12], u1[12];
+      eval_global<CT, false>(coeff, g, qn, u0);
+      double xs[3], vn[3];
+      for (int c = 0; c < 3; ++c) {
+        vn[c] = a.u0 ? (double)a.u0[c * np + p] : 0.0;
+        xs[c] = inertial_predict(a.ik, xn[c], vn[c], (double)u0[c],
+                                 a.disp ? a.disp[c * np + p] : 0.0);
+      }
+      const Pt qs = locate_pt<0>(g, xs, 0, 0, 0, -1, a.err);
+      eval_global<CT, false>(coeff, g, qs, u1);
+      for (int c = 0; c < 3; ++c) {
+        a.x_out[c * np + p] = inertial_correct(a.ik, xs[c], (double)u0[c], (double)u1[c]);
+        if (a.vel_out)
+          a.vel_out[c * np + p] =
+              (float)inertial_velocity(a.ik, vn[c], (double)u0[c], (double)u1[c]);
+      }
     } else if (MODE == TILE_RK2_FWD) {
       float u0[12], u1[12];
       eval_global<CT, false>(coeff, g, qn, u0);
@@ -1444,6 +1503,7 @@ static const char* gather_name(int mode) {
     case TILE_RK2_FWD: return "tile_rk2_fwd";
     case TILE_RK2_BWD_GRAD: return "tile_rk2_bwd_gather";
     case TILE_TV_STAGE1: return "tile_tv_stage1";
+    case TILE_INERTIAL: return "tile_inertial";
     default: return "tile_tv_stage2";
   }
 }
@@ -1488,11 +1548,13 @@ static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int
       case TILE_RK2_FWD: PT_TG(CT, TILE_RK2_FWD); break;  \
       case TILE_RK2_BWD_GRAD: PT_TG(CT, TILE_RK2_BWD_GRAD); break; \
       case TILE_TV_STAGE1: PT_TG(CT, TILE_TV_STAGE1); break; \
+      case TILE_INERTIAL: PT_TG(CT, TILE_INERTIAL); break; \
       default: PT_TG(CT, TILE_TV_STAGE2); break;          \
     }                                                     \
   } while (0)
   if (dtype == PT_F32) PT_TG_MODES(float);
-  else PT_TG_MODES(uint16_t);
+  else if (dtype == PT_BF16) PT_TG_MODES(uint16_t);
+  else return PT_ERR_UNSUPPORTED;  // the ring stages FP32 or BF16 only
 #undef PT_TG_MODES
 #undef PT_TG
   PT_LAUNCH_CHECK();
@@ -1509,6 +1571,23 @@ pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   a.x = x;
   a.x_out = x_out;
   return launch_gather(g, a, dtype, TILE_RK2_FWD, defer, items_ws, check, s);
+}
+
+// Inertial / diffusive step on sorted particles x (table ls, checked on the
+// device when `check`): x_out, v_out may alias x, v; v and v_out may be null
+// (tracer), disp may be null.
+pt_status tile_inertial(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
+                        int64_t np, const InertialCoef& k, const double* x, const float* v,
+                        const double* disp, double* x_out, float* v_out, void* defer,
+                        void* items_ws, bool check, hipStream_t s) {
+  TileArgs a = tile_args(g, coeff, ls, np, 0.0, kGatherSeg);
+  a.x = x;
+  a.x_out = x_out;
+  a.u0 = (float*)v;  // read only in this mode
+  a.vel_out = v_out;
+  a.disp = disp;
+  a.ik = k;
+  return launch_gather(g, a, dtype, TILE_INERTIAL, defer, items_ws, check, s);
 }
 
 // Stage 1 of the time-varying step on sorted particles x (table ls):

@@ -91,7 +91,8 @@ def test_invalid_arguments_rejected_before_launch(b):
     assert L.pt_sort_particles(ctypes.byref(g), 10, fake, fake, fake, None, None, fake, 8, None) == b.PT_ERR_WORKSPACE
     assert L.pt_sort_particles(ctypes.byref(g), 0, None, None, None, None, None, None, 0, None) == b.PT_OK
     assert L.pt_interp_uvw(ctypes.byref(g), None, 0, 10, fake, fake, None) == b.PT_ERR_NULL
-    assert L.pt_interp_uvw(ctypes.byref(g), fake, 2, 10, fake, fake, None) == b.PT_ERR_DTYPE
+    assert L.pt_interp_uvw(ctypes.byref(g), fake, 3, 10, fake, fake, None) == b.PT_ERR_DTYPE
+    assert (b.PT_F32, b.PT_BF16, b.PT_F64) == (0, 1, 2)
     assert L.pt_interp_uvw(ctypes.byref(g), None, 0, 0, None, None, None) == b.PT_OK
     assert L.pt_interp_grad(ctypes.byref(g), fake, 0, 10, None, fake, None) == b.PT_ERR_NULL
     nan = float("nan")
@@ -112,8 +113,8 @@ def test_invalid_arguments_rejected_before_launch(b):
         assert L.pt_rk2_step(ctypes.byref(g), fake, 0, 10, 0.1, fake, None, bad_sort, fake, 1 << 40, None) == b.PT_ERR_ARG
         assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, 10, 0.1, fake, bad_sort, fake, None, fake, 1 << 40, None) == b.PT_ERR_ARG
     assert (b.PT_UNSORTED, b.PT_SORT, b.PT_SORTED) == (0, 1, 2)
-    # the tiled paths take at most 2^30 particles per call
-    big_np = (1 << 30) + 1
+    # the tiled paths take fewer than 2^30 particles per call
+    big_np = 1 << 30
     for srt in (1, 2):
         assert L.pt_rk2_step(ctypes.byref(g), fake, 0, big_np, 0.1, fake, None, srt, fake, 1 << 62, None) == b.PT_ERR_UNSUPPORTED
         assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, big_np, 0.1, fake, srt, fake, None, fake, 1 << 62, None) == b.PT_ERR_UNSUPPORTED
@@ -122,6 +123,45 @@ def test_invalid_arguments_rejected_before_launch(b):
     assert L.pt_rk2_step_bwd(ctypes.byref(g), fake, 0, 10, 0.1, fake, 1, None, None, fake, 1 << 40, None) == b.PT_ERR_NULL
     assert L.pt_interp_uvw_bwd(ctypes.byref(g), fake, 0, 10, fake, None, fake, None, None) == b.PT_ERR_NULL
     assert L.pt_interp_uvw_bwd(ctypes.byref(g), fake, 0, 10, fake, fake, None, None, None) == b.PT_OK
+    # inertial step: dt > 0, tau >= 0 and finite, vel required when tau > 0
+    I = L.pt_inertial_step
+    inf = float("inf")
+    for dt, tau in ((0.0, 0.1), (-0.1, 0.1), (nan, 0.1), (0.1, -1.0), (0.1, nan), (0.1, inf)):
+        assert I(ctypes.byref(g), fake, 0, 10, dt, tau, fake, fake, None, None, 1, fake, 1 << 40,
+                 None) == b.PT_ERR_ARG
+    assert I(ctypes.byref(g), fake, 0, 10, 0.1, 0.5, fake, None, None, None, 1, fake, 1 << 40,
+             None) == b.PT_ERR_NULL
+    assert I(ctypes.byref(g), fake, 0, 10, 0.1, 0.5, fake, fake, None, None, 3, fake, 1 << 40,
+             None) == b.PT_ERR_ARG
+    assert I(ctypes.byref(g), fake, 0, 10, 0.1, 0.5, fake, fake, None, None, 1, fake, 8,
+             None) == b.PT_ERR_WORKSPACE
+    assert I(ctypes.byref(g), fake, 0, big_np, 0.1, 0.5, fake, fake, None, None, 2, fake, 1 << 62,
+             None) == b.PT_ERR_UNSUPPORTED
+    assert I(ctypes.byref(g), fake, 7, 10, 0.1, 0.5, fake, fake, None, None, 1, fake, 1 << 40,
+             None) == b.PT_ERR_DTYPE
+    assert I(ctypes.byref(g), None, 0, 0, 0.1, 0.0, None, None, None, None, 0, None, 0,
+             None) == b.PT_OK
+
+
+def test_f64_workspaces_hold_fp64_values(b):
+    """FP64 storage keeps velocities in FP64: its RK2 and inertial
+    workspaces are larger than the FP32 ones by the 12 extra bytes per value
+    triple of each velocity buffer."""
+    L = b.LIB
+    g = _g(b, (64, 64, 64))
+    np_ = 100000
+    size = {}
+    for op in (b.PT_OP_RK2, b.PT_OP_INERTIAL, b.PT_OP_SPLINE):
+        for dt in (b.PT_F32, b.PT_F64):
+            sp = ctypes.c_size_t()
+            assert L.pt_workspace_bytes(op, ctypes.byref(g), dt, np_, ctypes.byref(sp)) == 0
+            size[op, dt] = sp.value
+    slack = 1024  # 256-byte alignment of each buffer
+    assert size[b.PT_OP_RK2, b.PT_F64] >= size[b.PT_OP_RK2, b.PT_F32] + 12 * np_ - slack
+    assert size[b.PT_OP_INERTIAL, b.PT_F32] >= size[b.PT_OP_RK2, b.PT_F32] + 36 * np_ - slack
+    assert size[b.PT_OP_INERTIAL, b.PT_F64] >= size[b.PT_OP_INERTIAL, b.PT_F32] + 24 * np_ - slack
+    # the FP64 solve keeps one FP64 copy of a component
+    assert size[b.PT_OP_SPLINE, b.PT_F64] >= 8 * 64 ** 3
 
 
 def test_status_strings(b):
