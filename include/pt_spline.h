@@ -315,6 +315,27 @@ pt_status pt_rk2_step_bwd(const pt_grid *grid, const void *coeff, pt_dtype dtype
                           double *g_pos, float *g_coeff, void *ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* pt_rk2_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same step, with the same kernels and results, without a caller
+ * workspace.  Its scratch is a static device array of the library, 64 MiB per
+ * device (PT_NOALLOC_SCRATCH_BYTES), held until the process ends; the call
+ * itself allocates nothing (with kernel timing, pt_timing_enable, off).
+ *   sort  PT_UNSORTED (scratch: 12 bytes per particle, 24 for PT_F64) or
+ *         PT_SORTED (scratch: the particle table, 8 bytes per particle and the
+ *         work items); PT_SORT needs the sort's workspace: PT_ERR_ARG
+ *   pos   in/out double [3][np]
+ * Returns PT_ERR_WORKSPACE when the step needs more scratch than the array
+ * holds (more than about 5.5M particles unsorted in FP32, or about 7M sorted
+ * on a 1024^3 grid).  Every call on a device uses that device's one array: calls that
+ * overlap on one device (several streams, several host threads) race; calls
+ * in one stream order are safe, since each call writes every scratch word it
+ * reads before reading it. */
+#define PT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pt_status pt_rk2_step_noalloc(const pt_grid *grid, const void *coeff, pt_dtype dtype,
+                              int64_t np, double dt, double *pos, int sort,
+                              hipStream_t stream);
+
 /* One device's part of the particle migration between sub-domains
  * (Sec. 4.3): with the grid split into z-slabs, the particles that left this
  * device's slab [z0, z0 + nzl) (cells modulo nz) are separated from the ones

@@ -40,7 +40,7 @@ PT_UNSORTED, PT_SORT, PT_SORTED = 0, 1, 2  # sort argument of the RK2 steps
 EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_spline_coeffs_slab",
            "pt_sort_particles", "pt_slab_partition",
            "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_rk2_stage1", "pt_rk2_stage2",
-           "pt_inertial_step",
+           "pt_inertial_step", "pt_rk2_step_noalloc",
            "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
            "pt_status_string", "pt_timing_enable", "pt_timing_read")
@@ -81,6 +81,7 @@ def _load():
         "pt_rk2_stage2": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
         "pt_inertial_step": [g, vp, ctypes.c_int, i64, dbl, dbl, vp, vp, vp, vp, ctypes.c_int,
                              vp, sz, vp],
+        "pt_rk2_step_noalloc": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp],
         "pt_interp_uvw_bwd": [g, vp, ctypes.c_int, i64, vp, vp, vp, vp, vp],
         "pt_spline_coeffs_bwd": [g, vp, vp, vp, sz, vp],
         "pt_rk2_step_bwd": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp, vp, vp, sz,
@@ -293,6 +294,15 @@ def pt_inertial_step(grid, coeff, dt, tau, pos, vel, disp, ids, sort, ws, stream
                                 float(dt), float(tau), _ptr(pos), _ptr(vel), _ptr(disp),
                                 _ptr(ids), int(sort), _ptr(ws), ws.numel() * ws.element_size(),
                                 _stream(stream)))
+
+
+def pt_rk2_step_noalloc(grid, coeff, dt, pos, sort, stream=None):
+    np_ = pos.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos, torch.float64, (3, np_), "pos")
+    _check("pt_rk2_step_noalloc",
+           LIB.pt_rk2_step_noalloc(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                                   float(dt), _ptr(pos), int(sort), _stream(stream)))
 
 
 def pt_interp_uvw_bwd(grid, coeff, pos, g_out, g_pos, g_coeff, stream=None):

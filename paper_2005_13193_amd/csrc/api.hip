@@ -98,6 +98,28 @@ int* device_error_flag() {
   return g_flag_ptr[dev];
 }
 
+// ------------------------------------------------- no-allocation scratch ---
+// Scratch of pt_rk2_step_noalloc: one array per device in the library's
+// static device memory, held until the process ends.  Host code must not pass
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): its device address is looked up once per device, with that device
+// current, and kept here.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static void* g_scratch_ptr[kMaxDevices];
+
+static void* noalloc_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_flag_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 // ------------------------------------------------------------- timing ---
 struct TimingRec {
   std::string name;
@@ -600,6 +622,37 @@ pt_status pt_inertial_step(const pt_grid* grid, const void* coeff, pt_dtype dtyp
                          (float*)vel, w.defer, w.items, true, stream);
   }
   return inertial_advance(grid, coeff, dtype, np, k, pos, vel, disp, pos, vel, stream);
+}
+
+pt_status pt_rk2_step_noalloc(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                              double dt, double* pos, int sort, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (!isfinite(dt)) return PT_ERR_ARG;
+  if (sort != PT_UNSORTED && sort != PT_SORTED) return PT_ERR_ARG;
+  if (sort == PT_SORTED) PT_TRY(check_tiled_np(np));
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos) return PT_ERR_NULL;
+  const bool tile = sort == PT_SORTED && tiled(dtype);
+  // scratch layout: the particle table, the deferred list and the work items
+  // (tiled), or the stage-1 velocities (one thread per particle)
+  const size_t need = tile ? a256(lstart_bytes(grid)) + a256(tile_defer_bytes(np)) +
+                                 a256(tile_items_bytes(grid, np, false))
+                           : a256(3 * value_bytes(dtype) * (size_t)np);
+  if (need > kNoAllocScratchBytes) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  char* sp = (char*)noalloc_scratch();
+  if (!sp) return PT_ERR_HIP;
+  if (!tile) return rk2_advance(grid, coeff, dtype, np, dt, pos, pos, sp, stream);
+  int32_t* lstart = (int32_t*)sp;
+  void* defer = sp + a256(lstart_bytes(grid));
+  void* items = (char*)defer + a256(tile_defer_bytes(np));
+  // every scratch word the kernels read is written first in this call: the
+  // table by presorted_table, the deferred-list header and item counters by
+  // the launch's own clearing kernels
+  PT_TRY(presorted_table(grid, np, pos, lstart, stream));
+  return tile_rk2_fwd(grid, coeff, dtype, lstart, np, dt, pos, pos, defer, items, true, stream);
 }
 
 pt_status pt_last_device_error(hipStream_t stream) {
