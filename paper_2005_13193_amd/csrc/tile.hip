@@ -786,29 +786,36 @@ __global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
 // plane is added to g_coeff once nothing more can reach it.  Launches run one
 // colour (parities of cx, the half-row and the segment) at a time, so no two
 // concurrent workgroups touch the same coefficient and the order of the
-// additions to each coefficient is fixed.  Stencils that do not fit the tile (periodic wrap, or a move of
-// more than one cell) go to a list that scatter_deferred adds with atomics
-// after all colours.
+// additions to each coefficient is fixed.  Stencils that do not fit the tile
+// (periodic wrap, or a move of more than one cell) go to a list that
+// scatter_deferred adds with atomics after all colours.
 //
-// The LDS sums are 64-bit fixed point: FP32 atomic adds to LDS run at a small
-// fraction of the rate of integer ones on this hardware.  Every contribution
-// w * ub is formed in FP32 with ub pre-scaled by 2^k (k chosen per launch from
-// the largest |ub|, so that |w ub 2^k| < 2^31), rounded to the nearest 32-bit
-// integer and added as a 64-bit integer; the plane flush converts back.  The
-// rounding of each contribution is at most 2^-(k+1) absolute (about 2^-31 of
-// the largest |ub|) and unbiased.
+// The LDS sums are fixed point: LDS atomic adds of FP32 values run at a small
+// fraction of the rate of integer ones on this hardware (measured about 0.33
+// against 7.6 lane operations per clock per CU for 64-bit integers).  Every
+// contribution w * ub is formed in FP32 with ub pre-scaled by 2^k (k chosen
+// per launch from the largest |ub|, so that |w ub 2^k| < 2^31), rounded to
+// the nearest 32-bit integer and added as a 64-bit integer; the plane flush
+// converts back.  The rounding of each contribution is at most 2^-(k+1)
+// absolute (about 2^-31 of the largest |ub|) and unbiased.  (Two components
+// in the two halves of one 64-bit word would halve the LDS and a third of the
+// atomics, but each half then needs a range bound per work item, and bounds
+// from particle counts per layer leave too coarse a resolution in dense
+// clusters.)
 constexpr int kSTW = kTileX + 5;           // 37: tile width with margin
 constexpr int kSTH = kTileY / 2 + 5;       // 21
 constexpr int kSComp = kSTW * kSTH;        // 777
 constexpr int kSPlane = 3 * kSComp;        // 2331
 constexpr int kSSlot = kSPlane + 1;        // slot pitch (64-bit words)
-constexpr int kSRing = 8;
+// A slab touches planes zs-1 .. zs+5 and then frees zs-1 and zs, which the
+// next slab's planes zs+6 and zs+7 take over: 7 slots.
+constexpr int kSRing = 7;
 constexpr int kSTB = 512;
 constexpr int kSLanes = 8;                 // lanes per particle
 constexpr int kSGroups = kSTB / kSLanes;   // 64
 constexpr int kSPer = (kSPlane + kSTB - 1) / kSTB;  // plane words per thread (5)
 
-__device__ __forceinline__ int sslot(int P) { return (P + kSRing) & (kSRing - 1); }
+__device__ __forceinline__ int sslot(int P) { return (P + 2 * kSRing) % kSRing; }
 
 // Tile point of element e of a plane: component, row, column.
 __device__ __forceinline__ void selem(int e, int* c, int* y, int* x) {
@@ -968,25 +975,41 @@ __device__ __forceinline__ void flush_offsets(const GridDev& g, int X0, int Y0,
   }
 }
 
+// 64-bit fixed-point sum to FP32: the high and low halves converted in FP32
+// and combined with one fused multiply-add (at most one FP32 rounding more
+// than a direct conversion, far below the accumulated FP32 rounding of the
+// gradient).
+__device__ __forceinline__ float fixed_to_float(long long acc, float inv_scale) {
+  const float hi = (float)(int)(acc >> 32);
+  const float lo = (float)(uint32_t)acc;
+  return fmaf(hi, 4294967296.0f, lo) * inv_scale;
+}
+
 // Adds a finished plane of the ring to the gradient with one FP32 atomic add
 // per point (a single instruction instead of a load and a store; the colours
 // keep every other workgroup of the launch off these points, so the sums are
-// the same as a read-modify-write) and clears it for reuse.
+// the same as a read-modify-write) and clears it for reuse.  The thread's LDS
+// reads are all issued before any conversion or global atomic.
 __device__ __forceinline__ void flush_splane(const TileArgs& a, long long* ring,
                                              const int64_t off[kSPer], int P, float inv_scale) {
   const GridDev& g = a.g;
   if (P < 0 || P >= g.nz + 3) return;
   long long* sl = ring + sslot(P) * kSSlot;
   float* gp = a.gcoeff + (int64_t)P * g.plane;
+  long long acc[kSPer];
+#pragma unroll
+  for (int q = 0; q < kSPer; ++q) {
+    const int e = min((int)threadIdx.x + q * kSTB, kSPlane - 1);  // a word of the plane
+    acc[q] = sl[e];
+  }
 #pragma unroll
   for (int q = 0; q < kSPer; ++q) {
     const int e = threadIdx.x + q * kSTB;
-    if (e >= kSPlane) continue;
-    const long long acc = sl[e];
-    sl[e] = 0;
-    if (acc == 0 || off[q] < 0) continue;
-    atomicAdd(gp + off[q], (float)((double)acc * (double)inv_scale));
+    if (e < kSPlane) sl[e] = 0;
   }
+#pragma unroll
+  for (int q = 0; q < kSPer; ++q)
+    if (acc[q] != 0 && off[q] >= 0) atomicAdd(gp + off[q], fixed_to_float(acc[q], inv_scale));
 }
 
 __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
@@ -1479,15 +1502,16 @@ static pt_status build_tile_items(const pt_grid* g, int64_t np, const int32_t* h
   return PT_OK;
 }
 
-// Blocks of a tiled launch: one per compute unit (the tiled kernels hold one
-// workgroup per CU), a multiple of 8 (the XCD ranges), at most one per item.
-static unsigned item_blocks(int64_t bound) {
+// Blocks of a tiled launch: per_cu per compute unit (the gathers hold one
+// workgroup per CU, the scatter two), a multiple of 8 (the XCD ranges), at
+// most one per item.
+static unsigned item_blocks(int64_t bound, int per_cu = 1) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus <= 0)
     cus = 256;
-  const int64_t want = ((int64_t)cus + 7) / 8 * 8;
+  const int64_t want = ((int64_t)cus * per_cu + 7) / 8 * 8;
   const int64_t cap = (bound + 7) / 8 * 8;
   return (unsigned)(want < cap ? want : cap);
 }
