@@ -19,8 +19,21 @@ With --workload slab a step is the spline solve of one device's z-slab of a
 2048^3 grid split 8 ways (256 planes, z lines solved with open ends over 16
 halo planes per side).
 
-    python bench.py [--steps K] [--warmup W] [--config c3] [--dtype f32|bf16]
-                    [--workload fwd_adjoint|tv|slab] [--no-overlap]
+With --workload inertial a step is one inertial-particle step (Stokes drag,
+response time tau = 2 dt, particles launched at twice the local fluid
+velocity, so that they move up to about 1.2 cells per step) with the cell
+sort, on the configuration's particles.
+
+With --workload c5 (2048^3 grid, 256M uniform particles; coefficients of the
+frozen field computed once, outside the timed steps) a step is the cell sort,
+the 12-output gather of (u, v, w) and the nine velocity gradients at every
+particle (column-tiled), and the Heun step on the sorted particles.
+
+--dtype f64 runs the FP64 form of the same step (FP64 solves and gathers),
+the baseline the FP32 and BF16 forms are compared with.
+
+    python bench.py [--steps K] [--warmup W] [--config c3] [--dtype f32|bf16|f64]
+                    [--workload fwd_adjoint|tv|slab|inertial|c5] [--no-overlap]
 """
 import argparse
 import json
@@ -38,6 +51,10 @@ METRIC_SLAB = ("spline coefficient points/s, one 256-plane z-slab (halo 16) of a
                "2048^3 grid")
 METRIC_TV = ("particle-interpolations/s (u,v,w) at 1024^3, 64M particles; "
              "forward step with the coefficients recomputed at each RK sub-step")
+METRIC_INERTIAL = ("inertial-particle steps/s at 1024^3, 64M particles (Stokes drag, "
+                   "sort every step)")
+METRIC_C5 = ("particle steps/s at 2048^3, 256M particles: sort, 12-output gather "
+             "(u,v,w and 9 gradients), Heun step")
 HBM_PEAK_GBS = 8000.0
 
 CONFIGS = {
@@ -47,7 +64,9 @@ CONFIGS = {
     "c3": (1024, 64 * 2 ** 20, 341, True,
            "1024^3 grid, 64M particles (half uniform, half in 64 Gaussian blobs, sigma=0.1)"),
     "c4": (256, 2 ** 20, 85, False, "256^3 grid, 1M uniform particles"),
+    "c5": (2048, 256 * 2 ** 20, 682, False, "2048^3 grid, 256M uniform particles"),
 }
+DTYPES = {"f32": ("float32", 4), "bf16": ("bfloat16", 2), "f64": ("float64", 8)}
 
 
 def log(*a):
@@ -57,7 +76,8 @@ def log(*a):
 KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold",
            "spline_y_carry", "spline_yx_pad", "sorted_table", "sort_keys",
            "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter",
-           "tile_tv_stage1", "tile_tv_stage2")
+           "tile_tv_stage1", "tile_tv_stage2", "tile_inertial", "tile_interp", "tile_interp_grad",
+           "inertial_direct", "interp", "rk2_direct_stage2", "rk2_direct_bwd")
 
 
 def key_bytes(n):
@@ -66,10 +86,11 @@ def key_bytes(n):
     return 8 if (total - 1).bit_length() > 32 else 4
 
 
-def launch_bytes(kernel, n, np_, cb, launches_per_step):
+def launch_bytes(kernel, n, np_, cb, launches_per_step, vb=4):
     """Algorithmic HBM bytes of one launch: every array the kernel must touch,
     read or written once (n^3 grid points, (n+3)^3 padded coefficients per
-    component, np_ particles with FP64 positions)."""
+    component, np_ particles with FP64 positions; cb bytes per stored
+    coefficient, vb per velocity value: 8 for the FP64 form)."""
     n3, p3, kb = n ** 3, (n + 3) ** 3, key_bytes(n)
     per_step = {
         "spline_x": 8 * n3, "spline_y": 8 * n3, "spline_z": 8 * n3,
@@ -96,6 +117,17 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step):
         "tile_tv_stage1": 3 * p3 * cb + np_ * 60,
         # x and u^n in, x out; field once
         "tile_tv_stage2": 3 * p3 * cb + np_ * 60,
+        # x, v in; x, v out; field once
+        "tile_inertial": 3 * p3 * cb + np_ * (48 + 24),
+        "inertial_direct": 3 * p3 * cb + np_ * (48 + 6 * vb),
+        # x in, 3 or 12 values out
+        "tile_interp": 3 * p3 * cb + np_ * (24 + 12),
+        "tile_interp_grad": 3 * p3 * cb + np_ * (24 + 48),
+        # one thread per particle (FP64 form): u0 = u(x); x, u0 in, x out;
+        # adjoint: two gathers and the FP32 gradient read and written once
+        "interp": 3 * p3 * cb + np_ * (24 + 3 * vb),
+        "rk2_direct_stage2": 3 * p3 * cb + np_ * (48 + 3 * vb),
+        "rk2_direct_bwd": 2 * 3 * p3 * cb + 2 * 3 * p3 * 4 + np_ * (24 + 3 * vb + 48 + 96),
     }
     return per_step[kernel]
 
@@ -138,44 +170,108 @@ def cpu_baseline(n_full, np_full, clustered):
     the spline solve and its adjoint on a 512^3 grid and the fwd+adjoint
     particle work (sort, Heun step, step adjoint) for 2^24 particles
     of the workload's distribution, each scaled linearly to the full grid and
-    particle count."""
+    particle count; then the same on one core for a 256^3 grid and 2^20
+    particles."""
     import numpy as np
 
     import oracle
     import synth
 
-    ns, nps = 512, 2 ** 24
-    # the same synthetic spectrum; generated on the device (numpy's FFT at
-    # 512^3 would take longer than the timed sample), timed work is host-only
-    f = synth.spectral_field_torch(ns, ns // 3, seed=0, device="cuda:0").double().cpu().numpy()
-    if clustered:
-        pos = synth.clustered_particles_np(nps)
-    else:
-        pos = synth.uniform_particles_np(nps, seed=1)
-    g = oracle.Grid(ns)
-    dt = synth.cfl_dt(np.abs(f).max(), ns)
+    def sample(ns, nps):
+        f = synth.spectral_field_torch(ns, ns // 3, seed=0, device="cuda:0").double().cpu().numpy()
+        if clustered:
+            pos = synth.clustered_particles_np(nps)
+        else:
+            pos = synth.uniform_particles_np(nps, seed=1)
+        g = oracle.Grid(ns)
+        dt = synth.cfl_dt(np.abs(f).max(), ns)
+        t0 = time.perf_counter()
+        coeff = oracle.spline_coeffs(f)
+        t1 = time.perf_counter()
+        ps, _, _ = oracle.sort_particles(g, pos, 32, 32)
+        p1 = oracle.rk2_step(g, coeff, ps, dt)
+        gc = np.zeros_like(coeff)
+        oracle.rk2_step_bwd(g, coeff, ps, dt, 2.0 * p1, gc)
+        t2 = time.perf_counter()
+        oracle.spline_coeffs_bwd(gc)
+        t3 = time.perf_counter()
+        grid_scale = (n_full / ns) ** 3
+        part_scale = np_full / nps
+        t_step = ((t1 - t0) + (t3 - t2)) * grid_scale + (t2 - t1) * part_scale
+        desc = (f"FP64 oracle: spline solve + solve adjoint on a {ns}^3 grid "
+                f"(x{grid_scale:.0f} to {n_full}^3) and sort + Heun step + step adjoint "
+                f"for {nps} {'clustered' if clustered else 'uniform'} particles "
+                f"(x{part_scale:.0f} to {np_full}); sample took {t3 - t0:.1f} s")
+        return t_step, desc
+
+    cores = oracle.num_threads()
+    t_step, desc = sample(512, 2 ** 24)
+    out = {"value": 2.0 * np_full / t_step, "unit": "particle-interpolations/s",
+           "cores": cores, "kind": "oracle", "sample": desc, "ms_per_step_est": 1e3 * t_step}
+    oracle.set_num_threads(1)
+    try:
+        t1c, desc1 = sample(256, 2 ** 20)
+    finally:
+        oracle.set_num_threads(cores)
+    out["one_core"] = {"value": 2.0 * np_full / t1c, "unit": "particle-interpolations/s",
+                       "cores": 1, "kind": "oracle", "sample": desc1,
+                       "ms_per_step_est": 1e3 * t1c}
+    return out
+
+
+def oracle_errors(g, field, pos_n, pos_1, uvw, dt, sample):
+    """Max normwise error of the timed run against the FP64 oracle on a
+    sample of particles (the windowed closed form of the oracle, read from the
+    FP32 field the GPU used): the displacement of the last Heun step and
+    (u, v, w) at the step's starting points."""
+    import numpy as np
+
+    import oracle
+
+    fh = np.empty(tuple(field.shape), dtype=np.float32)
+    n = field.shape[1]
+    for c in range(3):
+        for z0 in range(0, n, max(1, n // 16)):
+            fh[c, z0:z0 + n // 16] = field[c, z0:z0 + n // 16].cpu().numpy()
+    og = oracle.Grid(g.nx, g.ny, g.nz)
+    x0 = pos_n[:, sample].double().cpu().numpy()
+    x1 = pos_1[:, sample].double().cpu().numpy()
+    u = uvw[:, sample].double().cpu().numpy()
+
+    def normwise(y, ref):
+        return max(float(np.abs(y[r] - ref[r]).max() / max(np.abs(ref[r]).max(), 1e-300))
+                   for r in range(ref.shape[0]))
+
+    ref1 = oracle.rk2_window(og, fh, x0, dt, 1)
+    refu = oracle.interp_window(og, fh, x0, n_out=3)
+    return {"displacement": normwise(x1 - x0, ref1 - x0), "uvw": normwise(u, refu),
+            "sample": f"{x0.shape[1]} particles of the last timed step, windowed FP64 oracle "
+                      "on the FP32 field"}
+
+
+def c4_adjoint_time(torch, pt, synth, reps=3):
+    """fwd+adjoint of K = 8 Heun steps with position checkpoints every 2
+    steps (TrackParticles) at 256^3 with 1M particles, FP32: ms per call."""
+    from paper_2005_13193_amd.autograd import TrackParticles
+    n, np_, K = 256, 2 ** 20, 8
+    g = pt.Grid(n)
+    field = synth.spectral_field_torch(n, 85, seed=0, device="cuda:0")
+    dt = synth.cfl_dt(float(field.abs().max()), n)
+    pos0 = synth.uniform_particles_torch(np_, seed=1, device="cuda:0")
+
+    def once():
+        f = field.clone().requires_grad_(True)
+        p = pos0.clone().requires_grad_(True)
+        xk, _ = TrackParticles.apply(f, p, g, dt, K)
+        (xk * xk).sum().backward()
+
+    once()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    coeff = oracle.spline_coeffs(f)
-    t1 = time.perf_counter()
-    ps, _, _ = oracle.sort_particles(g, pos, 32, 32)
-    p1 = oracle.rk2_step(g, coeff, ps, dt)
-    gc = np.zeros_like(coeff)
-    oracle.rk2_step_bwd(g, coeff, ps, dt, 2.0 * p1, gc)
-    t2 = time.perf_counter()
-    gfield = oracle.spline_coeffs_bwd(gc)
-    t3 = time.perf_counter()
-    del gfield
-    grid_scale = (n_full / ns) ** 3
-    part_scale = np_full / nps
-    t_step = ((t1 - t0) + (t3 - t2)) * grid_scale + (t2 - t1) * part_scale
-    return {"value": 2.0 * np_full / t_step, "unit": "particle-interpolations/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": (f"FP64 oracle: spline solve + solve adjoint on a {ns}^3 grid "
-                       f"(x{grid_scale:.0f} to {n_full}^3) and sort + Heun step + step adjoint "
-                       f"for {nps} {'clustered' if clustered else 'uniform'} particles "
-                       f"(x{part_scale:.0f} to {np_full}); "
-                       f"sample took {t3 - t0:.1f} s"),
-            "ms_per_step_est": 1e3 * t_step}
+    for _ in range(reps):
+        once()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
 
 
 def cpu_baseline_tv(n_full, np_full, clustered):
@@ -222,7 +318,7 @@ def kernel_stats(B, steps):
 
 def roofline(kstats, n, np_, cb, config, dtype, clustered):
     dom = max(kstats, key=lambda k: kstats[k]["ms_per_step"])
-    bpl = launch_bytes(dom, n, np_, cb, kstats[dom]["launches_per_step"])
+    bpl = launch_bytes(dom, n, np_, cb, kstats[dom]["launches_per_step"], 8 if cb == 8 else 4)
     achieved = bpl / (kstats[dom]["avg_launch_ms"] * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -393,9 +489,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
-    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--dtype", default="f32", choices=sorted(DTYPES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="fwd_adjoint", choices=["fwd_adjoint", "tv", "slab"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the sorted-gather timing, the C4 adjoint timing and the "
+                         "sampled oracle error after the timed steps")
+    ap.add_argument("--workload", default="fwd_adjoint",
+                    choices=["fwd_adjoint", "tv", "slab", "inertial", "c5"])
     ap.add_argument("--no-overlap", action="store_true",
                     help="tv: run the solves on the main stream (no overlap)")
     ap.add_argument("--uniform", action="store_true",
@@ -426,14 +526,16 @@ def main():
     from paper_2005_13193_amd import _binding as B
     import synth
 
+    if args.workload == "c5":
+        args.config = "c5"
     n, np_, kmax, clustered, desc = CONFIGS[args.config]
     if args.uniform and clustered:
         clustered = False
         desc = desc.split(" (")[0].replace("particles", "uniform particles")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cdt = torch.float32 if args.dtype == "f32" else torch.bfloat16
-    cb = 4 if args.dtype == "f32" else 2
+    cdt = getattr(torch, DTYPES[args.dtype][0])
+    cb = DTYPES[args.dtype][1]
     g = pt.Grid(n)
 
     log(f"[bench] config {args.config}: {desc}; coefficients {args.dtype}")
@@ -442,6 +544,12 @@ def main():
         return
     if args.workload == "slab":
         run_slab(args, torch, pt, B, synth, cdt, cb)
+        return
+    if args.workload == "inertial":
+        run_inertial(args, torch, pt, B, synth, n, np_, kmax, clustered, desc, cdt, cb)
+        return
+    if args.workload == "c5":
+        run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb)
         return
     field = synth.spectral_field_torch(n, kmax, seed=0, device=dev)
     umax = float(field.abs().max())
@@ -535,9 +643,221 @@ def main():
         "kernels": kstats,
         "roofline": roofline(kstats, n, np_, cb, args.config, args.dtype, clustered),
     }
+    if args.dtype != "f64":
+        out["deferred_particles"] = B.pt_tiled_deferred(B.PT_OP_RK2, g, pt._code(cdt), np_, ws_f)
+    uvw = None
+    if not args.no_extras:
+        # after the timed steps: (u, v, w) alone at the last step's sorted x_n
+        del ws_s, ws_b, g_field, perm
+        torch.cuda.empty_cache()
+        ws_i = pt.workspace(B.PT_OP_INTERP_SORTED, g, np_, cdt, dev)
+        uvw = torch.empty((3, np_), dtype=B.value_dtype(coeff), device=dev)
+        B.pt_interp_sorted(g, coeff, pos_n, uvw, ws_i)
+        torch.cuda.synchronize()
+        for k in KERNELS:
+            B.pt_timing_read(k)
+        B.pt_timing_enable(True)
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            B.pt_interp_sorted(g, coeff, pos_n, uvw, ws_i)
+        torch.cuda.synchronize()
+        ms_i = 1e3 * (time.perf_counter() - t0) / reps
+        ks = kernel_stats(B, reps)
+        B.pt_timing_enable(False)
+        kname = "tile_interp" if args.dtype != "f64" else "interp"
+        kb = launch_bytes(kname, n, np_, cb, 1, 8 if cb == 8 else 4)
+        k_ms = ks[kname]["avg_launch_ms"] if kname in ks else ms_i
+        out["interp_sorted"] = {
+            "what": "(u,v,w) alone at the sorted x_n of the last step (pt_interp_sorted)",
+            "ms": ms_i, "particles_per_s": np_ / (ms_i * 1e-3), "kernel": kname,
+            "kernel_ms": k_ms, "hbm_frac": kb / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del ws_i
+        torch.cuda.empty_cache()
+        log("[bench] timing the 256^3 / 1M / K=8 fwd+adjoint (checkpoints every 2 steps)")
+        out["c4_fwd_adjoint_k8_ms"] = c4_adjoint_time(torch, pt, synth)
     if not args.no_cpu_baseline:
+        if uvw is not None:
+            log("[bench] sampled error against the FP64 oracle")
+            sample = torch.arange(0, np_, max(1, np_ // 256), device=dev)
+            out["error"] = oracle_errors(g, field, pos_n, pos, uvw, dt, sample)
         log("[bench] timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(n, np_, clustered)
+    print(json.dumps(out), flush=True)
+
+
+def run_inertial(args, torch, pt, B, synth, n, np_, kmax, clustered, desc, cdt, cb):
+    """Inertial particles (Stokes drag, tau = 2 dt) launched at twice the
+    local fluid velocity: one step with the cell sort per timed step, the
+    coefficients of the frozen field computed once before."""
+    dev = torch.device("cuda:0")
+    g = pt.Grid(n)
+    field = synth.spectral_field_torch(n, kmax, seed=0, device=dev)
+    dt = synth.cfl_dt(float(field.abs().max()), n)
+    tau = 2.0 * dt
+    coeff = pt.spline_coeffs(g, field, cdt)
+    del field
+    torch.cuda.empty_cache()
+    pos = (synth.clustered_particles_torch(np_, sigma=0.1, device=dev) if clustered
+           else synth.uniform_particles_torch(np_, seed=1, device=dev))
+    vel = 2.0 * pt.interp_uvw(g, coeff, pos)
+    ids = torch.arange(np_, dtype=torch.int32, device=dev)
+    ws = pt.workspace(B.PT_OP_INERTIAL, g, np_, cdt, dev)
+    torch.cuda.synchronize()
+
+    def step():
+        B.pt_inertial_step(g, coeff, dt, tau, pos, vel, None, ids, B.PT_SORT, ws)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+    for k in KERNELS:
+        B.pt_timing_read(k)
+    B.pt_timing_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log(f"[bench] timed step {i + 1}/{args.steps} issued")
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    if B.pt_last_device_error() != 0:
+        raise RuntimeError("device error flag set")
+    kstats = kernel_stats(B, args.steps)
+    B.pt_timing_enable(False)
+    out = {
+        "metric": METRIC_INERTIAL, "value": np_ / (ms_step * 1e-3), "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": desc + f", {args.dtype} coefficients, inertial particles "
+                   "(tau = 2 dt, launched at 2x the fluid velocity), sort every step, frozen "
+                   "field", "grid": n, "particles": np_, "dt": dt, "tau": tau},
+        "kernels": kstats,
+        "roofline": roofline(kstats, n, np_, cb, args.config + "_inertial", args.dtype, clustered),
+    }
+    if args.dtype != "f64":
+        d = B.pt_tiled_deferred(B.PT_OP_INERTIAL, g, pt._code(cdt), np_, ws)
+        out["deferred_particles"] = d
+        out["deferred_fraction"] = d / np_
+    if not args.no_cpu_baseline:
+        import numpy as np
+
+        import oracle
+        log("[bench] timing the FP64 oracle on a bounded sample")
+        ns, nps = 512, 2 ** 22
+        f = synth.spectral_field_torch(ns, ns // 3, seed=0, device=dev).double().cpu().numpy()
+        og = oracle.Grid(ns)
+        p0 = (synth.clustered_particles_np(nps) if clustered
+              else synth.uniform_particles_np(nps, seed=1))
+        dts = synth.cfl_dt(np.abs(f).max(), ns)
+        co = oracle.spline_coeffs(f)
+        v0 = 2.0 * oracle.interp(og, co, p0)
+        t0 = time.perf_counter()
+        ps, perm, _ = oracle.sort_particles(og, p0, 32, 32)
+        oracle.inertial_step(og, co, ps, v0[:, perm], dts, 2.0 * dts)
+        t = (time.perf_counter() - t0) * np_ / nps
+        out["cpu_baseline"] = {"value": np_ / t, "unit": "particle-steps/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"FP64 oracle: sort + inertial step of {nps} particles "
+                                         f"on a {ns}^3 grid (x{np_ / nps:.0f})",
+                               "ms_per_step_est": 1e3 * t}
+    print(json.dumps(out), flush=True)
+
+
+def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
+    """2048^3 grid, 256M uniform particles: per step the cell sort, the
+    column-tiled 12-output gather at x_n and the Heun step on the sorted
+    particles; the coefficients of the frozen field are computed once before
+    (and timed once, reported apart)."""
+    dev = torch.device("cuda:0")
+    g = pt.Grid(n)
+    field = synth.spectral_field_torch_chunked(n, kmax, seed=0, device=dev)
+    dt = synth.cfl_dt(max(float(field.max()), -float(field.min())), n)
+    coeff = torch.empty(g.padded_shape, dtype=cdt, device=dev)
+    ws_sp = pt.workspace(B.PT_OP_SPLINE, g, 0, cdt, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.pt_spline_coeffs(g, field, coeff, ws_sp)
+    torch.cuda.synchronize()
+    solve_ms = 1e3 * (time.perf_counter() - t0)
+    del field, ws_sp
+    torch.cuda.empty_cache()
+    pos = synth.uniform_particles_torch(np_, seed=1, device=dev)
+    pos_n = torch.empty_like(pos)
+    perm = torch.empty(np_, dtype=torch.int32, device=dev)
+    ids = torch.arange(np_, dtype=torch.int32, device=dev)
+    out12 = torch.empty((12, np_), dtype=B.value_dtype(coeff), device=dev)
+    ws_s = pt.workspace(B.PT_OP_SORT, g, np_, cdt, dev)
+    ws_i = pt.workspace(B.PT_OP_INTERP_SORTED, g, np_, cdt, dev)
+    ws_f = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
+    torch.cuda.synchronize()
+    log(f"[bench] c5 inputs ready: solve {solve_ms:.1f} ms, "
+        f"mem={torch.cuda.memory_allocated() / 2**30:.1f} GiB")
+
+    def step():
+        B.pt_sort_particles(g, pos, pos_n, perm, ids, None, ws_s)
+        pos.copy_(pos_n)
+        B.pt_interp_sorted(g, coeff, pos, out12, ws_i)
+        B.pt_rk2_step(g, coeff, dt, pos, None, B.PT_SORTED, ws_f)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+    for k in KERNELS:
+        B.pt_timing_read(k)
+    B.pt_timing_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] timed step {i + 1}/{args.steps} done")
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    if B.pt_last_device_error() != 0:
+        raise RuntimeError("device error flag set")
+    kstats = kernel_stats(B, args.steps)
+    B.pt_timing_enable(False)
+    out = {
+        "metric": METRIC_C5, "value": np_ / (ms_step * 1e-3), "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": desc + f", {args.dtype} coefficients of a frozen field, per "
+                   "step: cell sort, 12-output gather (u,v,w and 9 gradients), Heun step",
+                   "grid": n, "particles": np_, "dt": dt, "solve_ms_once": solve_ms},
+        "kernels": kstats,
+        "roofline": roofline(kstats, n, np_, cb, "c5", args.dtype, False),
+    }
+    if "tile_interp_grad" in kstats:
+        kb = launch_bytes("tile_interp_grad", n, np_, cb, 1)
+        k_ms = kstats["tile_interp_grad"]["avg_launch_ms"]
+        out["grad_gather"] = {"kernel": "tile_interp_grad", "ms": k_ms,
+                              "interpolations_per_s": np_ / (k_ms * 1e-3),
+                              "algorithmic_bytes": kb,
+                              "hbm_frac": kb / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if not args.no_cpu_baseline:
+        import numpy as np
+
+        import oracle
+        log("[bench] timing the FP64 oracle on a bounded sample")
+        ns, nps = 512, 2 ** 22
+        f = synth.spectral_field_torch(ns, ns // 3, seed=0, device=dev).double().cpu().numpy()
+        og = oracle.Grid(ns)
+        p0 = synth.uniform_particles_np(nps, seed=1)
+        dts = synth.cfl_dt(np.abs(f).max(), ns)
+        co = oracle.spline_coeffs(f)
+        t0 = time.perf_counter()
+        ps, _, _ = oracle.sort_particles(og, p0, 32, 32)
+        oracle.interp(og, co, ps, n_out=12)
+        oracle.rk2_step(og, co, ps, dts)
+        t = (time.perf_counter() - t0) * np_ / nps
+        out["cpu_baseline"] = {"value": np_ / t, "unit": "particle-steps/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"FP64 oracle: sort + 12-output interpolation + Heun "
+                                         f"step of {nps} particles on a {ns}^3 grid "
+                                         f"(x{np_ / nps:.0f})",
+                               "ms_per_step_est": 1e3 * t}
     print(json.dumps(out), flush=True)
 
 

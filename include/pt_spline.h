@@ -92,7 +92,8 @@ enum {
   PT_OP_RK2_BWD = 4,    /* pt_rk2_step_bwd (with or without sort) */
   PT_OP_SPLINE_SLAB = 5, /* pt_spline_coeffs_slab; np = input planes nzl + 3 + 2 halo */
   PT_OP_SLAB_PARTITION = 6, /* pt_slab_partition */
-  PT_OP_INERTIAL = 7     /* pt_inertial_step (with or without sort) */
+  PT_OP_INERTIAL = 7,    /* pt_inertial_step (with or without sort) */
+  PT_OP_INTERP_SORTED = 8 /* pt_interp_sorted */
 };
 
 /* Bytes of workspace the operation needs for this grid, coefficient dtype
@@ -182,6 +183,24 @@ pt_status pt_interp_uvw(const pt_grid *grid, const void *coeff, pt_dtype dtype,
  *        row 3 + 3 i + j. */
 pt_status pt_interp_grad(const pt_grid *grid, const void *coeff, pt_dtype dtype,
                          int64_t np, const double *pos, void *out, hipStream_t stream);
+
+/* pt_interp_uvw (nout = 3) or pt_interp_grad (nout = 12) for particles in
+ * cell order (as pt_sort_particles leaves them): the column-tiled kernels
+ * stage each column's coefficient planes in LDS once and gather from there,
+ * the particle-per-thread kernels of pt_interp_uvw / pt_interp_grad read
+ * them from global memory.  Particles out of order give the same values more
+ * slowly (a particle outside its column's tile is evaluated from global
+ * memory, and a cell table that is not a partition of the particles, checked
+ * on the device, sends every particle that way).  Fewer than 2^30 particles
+ * per call (else PT_ERR_UNSUPPORTED).  PT_F64 gathers from global memory.
+ *   pos   in   double [3][np], cell order
+ *   nout  3 or 12 (else PT_ERR_ARG)
+ *   out   out  float [nout][np] (double for PT_F64), rows as for
+ *              pt_interp_grad
+ *   ws         >= pt_workspace_bytes(PT_OP_INTERP_SORTED, ...) bytes */
+pt_status pt_interp_sorted(const pt_grid *grid, const void *coeff, pt_dtype dtype, int64_t np,
+                           const double *pos, int nout, void *out, void *ws, size_t ws_bytes,
+                           hipStream_t stream);
 
 /* The sort argument of pt_rk2_step and pt_rk2_step_bwd. */
 enum {
@@ -358,6 +377,15 @@ pt_status pt_slab_partition(const pt_grid *grid, int64_t np, const double *pos,
                             int32_t *ids_out, int64_t *counts, void *ws, size_t ws_bytes,
                             hipStream_t stream);
 
+/* Diagnostics: the number of particles (PT_OP_RK2, PT_OP_INERTIAL,
+ * PT_OP_INTERP_SORTED) or of particles plus stencils (PT_OP_RK2_BWD, whose
+ * list is reused by the scatter) that the last column-tiled call on this
+ * workspace sent to the global-memory path (a predicted point outside its
+ * column's tile).  Synchronises the device; grid, dtype and np as given to
+ * that call.  Other ops return PT_ERR_ARG. */
+pt_status pt_tiled_deferred(int op, const pt_grid *grid, pt_dtype dtype, int64_t np,
+                            const void *ws, int64_t *count);
+
 /* Synchronises `stream`, then returns PT_ERR_NONFINITE if any kernel on the
  * current device met a non-finite position since the previous call (and
  * clears the flag), PT_ERR_HIP on a runtime error, else PT_OK. */
@@ -378,7 +406,8 @@ const char *pt_status_string(pt_status status);
  * "sorted_table" (the particle table of PT_SORTED), "slab_partition",
  * "tile_rk2_fwd",
  * "tile_rk2_bwd_gather", "tile_scatter", "tile_tv_stage1", "tile_tv_stage2",
- * "interp". */
+ * "tile_inertial", "tile_interp", "tile_interp_grad", "inertial_direct",
+ * "interp", "rk2_direct_stage2", "rk2_direct_bwd". */
 pt_status pt_timing_enable(int on);
 pt_status pt_timing_read(const char *kernel, double *total_ms, int64_t *launches);
 

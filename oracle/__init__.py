@@ -33,6 +33,8 @@ def _load():
         lib = ctypes.CDLL(_SO)
         i32, i64, dbl, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
         lib.oracle_num_threads.restype = i32
+        lib.oracle_set_num_threads.argtypes = [i32]
+        lib.oracle_set_num_threads.restype = None
         lib.oracle_solve_line.argtypes = [i32, vp, vp]
         lib.oracle_spline_coeffs.argtypes = [i32, i32, i32, vp, vp]
         lib.oracle_cell_keys.argtypes = [i32, i32, i32, dbl, dbl, dbl, i32, i32, i64,
@@ -84,6 +86,11 @@ def _f64(a):
 
 def num_threads() -> int:
     return _load().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    _load().oracle_set_num_threads(int(n))
 
 
 class Grid:

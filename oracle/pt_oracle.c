@@ -51,6 +51,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads of the parallel loops that follow (timing on one core). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Operation 1: spline coefficients (Sec. 2.2).                              */
 /* ------------------------------------------------------------------------ */

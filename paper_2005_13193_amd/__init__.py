@@ -20,7 +20,7 @@ from . import _binding as _b
 from ._binding import PT_SORT, PT_SORTED, PT_UNSORTED, PtError  # noqa: F401
 
 __all__ = ["Grid", "PtError", "spline_coeffs", "spline_coeffs_bwd", "sort_particles",
-           "inertial_step",
+           "inertial_step", "interp_sorted",
            "interp_uvw", "interp_grad", "interp_uvw_bwd", "rk2_step", "rk2_step_bwd",
            "last_device_error", "workspace", "key_layout"]
 
@@ -146,6 +146,18 @@ def interp_grad(grid, coeff, pos, out=None):
     if out is None:
         out = torch.empty((12, pos.shape[1]), dtype=_b.value_dtype(coeff), device=pos.device)
     _b.pt_interp_grad(grid, coeff, pos, out)
+    return out
+
+
+def interp_sorted(grid, coeff, pos, nout=3, out=None, ws=None):
+    """(u, v, w) (nout = 3) or with the nine gradients (nout = 12) at
+    particles in cell order, through the column-tiled gathers."""
+    pos = pos.contiguous()
+    if out is None:
+        out = torch.empty((nout, pos.shape[1]), dtype=_b.value_dtype(coeff), device=pos.device)
+    if ws is None:
+        ws = workspace(_b.PT_OP_INTERP_SORTED, grid, pos.shape[1], coeff.dtype, pos.device)
+    _b.pt_interp_sorted(grid, coeff, pos, out, ws)
     return out
 
 

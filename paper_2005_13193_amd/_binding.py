@@ -35,12 +35,13 @@ PT_OP_RK2_BWD = 4
 PT_OP_SPLINE_SLAB = 5
 PT_OP_SLAB_PARTITION = 6
 PT_OP_INERTIAL = 7
+PT_OP_INTERP_SORTED = 8
 PT_UNSORTED, PT_SORT, PT_SORTED = 0, 1, 2  # sort argument of the RK2 steps
 
 EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_spline_coeffs_slab",
            "pt_sort_particles", "pt_slab_partition",
            "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_rk2_stage1", "pt_rk2_stage2",
-           "pt_inertial_step", "pt_rk2_step_noalloc",
+           "pt_inertial_step", "pt_rk2_step_noalloc", "pt_interp_sorted", "pt_tiled_deferred",
            "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
            "pt_status_string", "pt_timing_enable", "pt_timing_read")
@@ -82,6 +83,8 @@ def _load():
         "pt_inertial_step": [g, vp, ctypes.c_int, i64, dbl, dbl, vp, vp, vp, vp, ctypes.c_int,
                              vp, sz, vp],
         "pt_rk2_step_noalloc": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp],
+        "pt_interp_sorted": [g, vp, ctypes.c_int, i64, vp, ctypes.c_int, vp, vp, sz, vp],
+        "pt_tiled_deferred": [ctypes.c_int, g, ctypes.c_int, i64, vp, ctypes.POINTER(i64)],
         "pt_interp_uvw_bwd": [g, vp, ctypes.c_int, i64, vp, vp, vp, vp, vp],
         "pt_spline_coeffs_bwd": [g, vp, vp, vp, sz, vp],
         "pt_rk2_step_bwd": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp, vp, vp, sz,
@@ -246,6 +249,18 @@ def pt_interp_grad(grid, coeff, pos, out, stream=None):
                               _ptr(pos), _ptr(out), _stream(stream)))
 
 
+def pt_interp_sorted(grid, coeff, pos, out, ws, stream=None):
+    np_ = pos.shape[1]
+    nout = out.shape[0]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos, torch.float64, (3, np_), "pos")
+    _need(out, value_dtype(coeff), (nout, np_), "out")
+    _check("pt_interp_sorted",
+           LIB.pt_interp_sorted(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                                _ptr(pos), int(nout), _ptr(out), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)))
+
+
 def pt_rk2_step(grid, coeff, dt, pos, ids, sort, ws, stream=None):
     np_ = pos.shape[1]
     _need(coeff, None, grid.padded_shape, "coeff")
@@ -329,6 +344,14 @@ def pt_rk2_step_bwd(grid, coeff, dt, pos_n, sort, g_pos, g_coeff, ws, stream=Non
                                float(dt), _ptr(pos_n), int(sort), _ptr(g_pos),
                                _ptr(g_coeff), _ptr(ws), ws.numel() * ws.element_size(),
                                _stream(stream)))
+
+
+def pt_tiled_deferred(op, grid, dtype_code, np_, ws):
+    """Particles the last tiled call on ws evaluated from global memory."""
+    out = ctypes.c_int64(0)
+    _check("pt_tiled_deferred", LIB.pt_tiled_deferred(op, ctypes.byref(_grid(grid)), dtype_code,
+                                                      np_, _ptr(ws), ctypes.byref(out)))
+    return out.value
 
 
 def pt_last_device_error(stream=None):

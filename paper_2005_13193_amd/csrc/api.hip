@@ -62,6 +62,9 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
                        float* u0, float* ub0, float* ub1, float* gcoeff, void* defer,
                        void* items_ws, bool check, hipStream_t s);
 size_t tile_defer_bytes(int64_t np);
+pt_status tile_interp(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
+                      int64_t np, const double* x, int nout, float* out, void* defer,
+                      void* items_ws, hipStream_t s);
 pt_status tile_inertial(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                         int64_t np, const InertialCoef& k, const double* x, const float* v,
                         const double* disp, double* x_out, float* v_out, void* defer,
@@ -318,6 +321,10 @@ pt_status pt_workspace_bytes(int op, const pt_grid* grid, pt_dtype dtype, int64_
     case PT_OP_RK2: *bytes = a256(rk2_ws_bytes(grid, np, dtype)); break;
     case PT_OP_RK2_BWD: *bytes = a256(rk2_bwd_ws_bytes(grid, np, dtype)); break;
     case PT_OP_INERTIAL: *bytes = a256(inertial_ws_bytes(grid, np, dtype)); break;
+    case PT_OP_INTERP_SORTED:
+      *bytes = a256(lstart_bytes(grid)) + a256(tile_defer_bytes(np)) +
+               a256(tile_items_bytes(grid, np, false));
+      break;
     // np = input planes of the slab, nzl + 3 + 2 W
     case PT_OP_SPLINE_SLAB:
       *bytes = a256(4 * spline_slab_ws_floats(grid, (int)np - 3, 0, dtype));
@@ -433,6 +440,30 @@ pt_status pt_interp_grad(const pt_grid* grid, const void* coeff, pt_dtype dtype,
   if (!coeff || !pos || !out) return PT_ERR_NULL;
   PT_TRY(ready());
   return interp_fwd(grid, coeff, dtype, np, pos, out, 12, stream);
+}
+
+pt_status pt_interp_sorted(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                           const double* pos, int nout, void* out, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (nout != 3 && nout != 12) return PT_ERR_ARG;
+  PT_TRY(check_tiled_np(np));
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos || !out) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_INTERP_SORTED, grid, dtype, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  if (!tiled(dtype)) return interp_fwd(grid, coeff, dtype, np, pos, out, nout, stream);
+  char* p = (char*)ws;
+  int32_t* lstart = (int32_t*)p;
+  void* defer = p + a256(lstart_bytes(grid));
+  void* items = (char*)defer + a256(tile_defer_bytes(np));
+  PT_TRY(presorted_table(grid, np, pos, lstart, stream));
+  return tile_interp(grid, coeff, dtype, lstart, np, pos, nout, (float*)out, defer, items,
+                     stream);
 }
 
 pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
@@ -653,6 +684,29 @@ pt_status pt_rk2_step_noalloc(const pt_grid* grid, const void* coeff, pt_dtype d
   // the launch's own clearing kernels
   PT_TRY(presorted_table(grid, np, pos, lstart, stream));
   return tile_rk2_fwd(grid, coeff, dtype, lstart, np, dt, pos, pos, defer, items, true, stream);
+}
+
+pt_status pt_tiled_deferred(int op, const pt_grid* grid, pt_dtype dtype, int64_t np,
+                            const void* ws, int64_t* count) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (!ws || !count) return PT_ERR_NULL;
+  const void* defer = nullptr;
+  if (op == PT_OP_RK2 || op == PT_OP_INERTIAL) {
+    defer = carve_rk2(grid, np, dtype, (void*)ws).defer;
+  } else if (op == PT_OP_RK2_BWD) {
+    defer = carve_rk2_bwd(grid, np, dtype, (void*)ws).defer;
+  } else if (op == PT_OP_INTERP_SORTED) {
+    defer = (const char*)ws + a256(lstart_bytes(grid));
+  } else {
+    return PT_ERR_ARG;
+  }
+  int v = 0;
+  PT_HIP_CHECK(hipDeviceSynchronize());
+  PT_HIP_CHECK(hipMemcpy(&v, defer, sizeof(int), hipMemcpyDeviceToHost));
+  *count = v;
+  return PT_OK;
 }
 
 pt_status pt_last_device_error(hipStream_t stream) {

@@ -308,6 +308,7 @@ pt_status interp_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_
 pt_status rk2_correct(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
                       const double* x, const void* u0, double* x_out, hipStream_t s) {
   const GridDev gd = make_grid_dev(g);
+  TimedLaunch t("rk2_direct_stage2", s);
   return with_ct(dtype, [&]<typename CT>() {
     using VT = typename AccOf<CT>::T;
     hipLaunchKernelGGL(rk2_stage2<CT>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd,
@@ -356,6 +357,7 @@ pt_status rk2_backward(const pt_grid* g, const void* coeff, pt_dtype dtype, int6
   const GridDev gd = make_grid_dev(g);
   const dim3 grid(grid_1d(np, 256)), block(256);
   int* err = device_error_flag();
+  TimedLaunch t("rk2_direct_bwd", s);
   return with_ct(dtype, [&]<typename CT>() {
     using VT = typename AccOf<CT>::T;
     hipLaunchKernelGGL(rk2_bwd_star<CT>, grid, block, 0, s, gd, (const CT*)coeff, np, dt, x,

@@ -59,6 +59,7 @@ struct TileArgs {
   const double* disp;     // inertial: displacement increments [3][np] or null
   float* vel_out;         // inertial: new particle velocities [3][np] or null
   InertialCoef ik;        // inertial: step coefficients
+  float* out;             // interpolation modes: [3][np] or [12][np]
   float* gcoeff;          // scatter target (padded FP32)
   uint32_t* defer;        // scatter: deferred stencils (2 p + stage)
   int* defer_count;
@@ -182,7 +183,9 @@ enum {
   TILE_RK2_BWD_GRAD = 1,
   TILE_TV_STAGE1 = 2,
   TILE_TV_STAGE2 = 3,
-  TILE_INERTIAL = 4
+  TILE_INERTIAL = 4,
+  TILE_INTERP3 = 5,   // (u, v, w) at the particles
+  TILE_INTERP12 = 6   // (u, v, w) and the nine velocity gradients
 };
 
 __device__ __forceinline__ int gslot(int P) { return (P + kGRing) % kGRing; }
@@ -309,7 +312,14 @@ __device__ __forceinline__ void flush_pend(const TileArgs& a, Pend* o, DeferBatc
     if (db->part >= 0 && (int64_t)(base + rank) < np) ((int32_t*)a.defer)[base + rank] = db->part;
   }
   if (o->off >= 0) {
-    if (MODE == TILE_RK2_BWD_GRAD) {
+    if (MODE == TILE_INTERP3) {
+      a.out[(int64_t)(lane64 & 3) * np + o->off] = o->f0;
+    } else if (MODE == TILE_INTERP12) {
+      const int64_t r = 3 * (lane64 & 3);
+      a.out[r * np + o->off] = o->f0;
+      a.out[(r + 1) * np + o->off] = o->f1;
+      a.out[(r + 2) * np + o->off] = o->f2;
+    } else if (MODE == TILE_RK2_BWD_GRAD) {
       a.xbn[o->off] = o->d;
       a.u0[o->off] = o->f0;
       a.ub0[o->off] = o->f1;
@@ -382,6 +392,22 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
       const float ub = lane == 0 ? u1[0] : lane == 1 ? u1[1] : u1[2];
       o->off = lane * np + p;
       o->d = x0 + h * ((double)ua + (double)ub);
+    }
+  } else if (MODE == TILE_INTERP3 || MODE == TILE_INTERP12) {
+    // lane c < 3 writes row c (INTERP3); lane c writes rows 3c .. 3c+2
+    // (INTERP12)
+    float o12[12];
+    eval_ring<CT, MODE == TILE_INTERP12>(ring, g, qn, X0, Y0, lane, o12);
+    if (MODE == TILE_INTERP3) {
+      if (lane < 3) {
+        o->off = p;
+        o->f0 = lane == 0 ? o12[0] : lane == 1 ? o12[1] : o12[2];
+      }
+    } else {
+      o->off = p;
+      o->f0 = lane == 0 ? o12[0] : lane == 1 ? o12[3] : lane == 2 ? o12[6] : o12[9];
+      o->f1 = lane == 0 ? o12[1] : lane == 1 ? o12[4] : lane == 2 ? o12[7] : o12[10];
+      o->f2 = lane == 0 ? o12[2] : lane == 1 ? o12[5] : lane == 2 ? o12[8] : o12[11];
     }
   } else if (MODE == TILE_INERTIAL) {
     float u0[12], u1[12];
@@ -700,7 +726,12 @@ __global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
     if (p < 0 || p >= np) continue;
     double xn[3] = {a.x[p], a.x[np + p], a.x[2 * np + p]};
     const Pt qn = locate_pt<0>(g, xn, 0, 0, 0, -1, a.err);
-    if (MODE == TILE_TV_STAGE1) {
+    if (MODE == TILE_INTERP3 || MODE == TILE_INTERP12) {
+      constexpr int kOut = MODE == TILE_INTERP12 ? 12 : 3;
+      float o12[12];
+      eval_global<CT, MODE == TILE_INTERP12>(coeff, g, qn, o12);
+      for (int r = 0; r < kOut; ++r) a.out[r * np + p] = o12[r];
+    } else if (MODE == TILE_TV_STAGE1) {
       float u0[12];
       eval_global<CT, false>(coeff, g, qn, u0);
       for (int c = 0; c < 3; ++c) {
@@ -1528,6 +1559,8 @@ static const char* gather_name(int mode) {
     case TILE_RK2_BWD_GRAD: return "tile_rk2_bwd_gather";
     case TILE_TV_STAGE1: return "tile_tv_stage1";
     case TILE_INERTIAL: return "tile_inertial";
+    case TILE_INTERP3: return "tile_interp";
+    case TILE_INTERP12: return "tile_interp_grad";
     default: return "tile_tv_stage2";
   }
 }
@@ -1573,6 +1606,8 @@ static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int
       case TILE_RK2_BWD_GRAD: PT_TG(CT, TILE_RK2_BWD_GRAD); break; \
       case TILE_TV_STAGE1: PT_TG(CT, TILE_TV_STAGE1); break; \
       case TILE_INERTIAL: PT_TG(CT, TILE_INERTIAL); break; \
+      case TILE_INTERP3: PT_TG(CT, TILE_INTERP3); break; \
+      case TILE_INTERP12: PT_TG(CT, TILE_INTERP12); break; \
       default: PT_TG(CT, TILE_TV_STAGE2); break;          \
     }                                                     \
   } while (0)
@@ -1612,6 +1647,18 @@ pt_status tile_inertial(const pt_grid* g, const void* coeff, pt_dtype dtype, con
   a.disp = disp;
   a.ik = k;
   return launch_gather(g, a, dtype, TILE_INERTIAL, defer, items_ws, check, s);
+}
+
+// (u, v, w) (nout = 3) or with the nine gradients (nout = 12) at particles
+// in cell order (table ls built from x, checked on the device).
+pt_status tile_interp(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
+                      int64_t np, const double* x, int nout, float* out, void* defer,
+                      void* items_ws, hipStream_t s) {
+  TileArgs a = tile_args(g, coeff, ls, np, 0.0, kGatherSeg);
+  a.x = x;
+  a.out = out;
+  return launch_gather(g, a, dtype, nout == 12 ? TILE_INTERP12 : TILE_INTERP3, defer, items_ws,
+                       true, s);
 }
 
 // Stage 1 of the time-varying step on sorted particles x (table ls):
