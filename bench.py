@@ -77,7 +77,8 @@ KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold",
            "spline_y_carry", "spline_yx_pad", "sorted_table", "sort_keys",
            "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter",
            "tile_tv_stage1", "tile_tv_stage2", "tile_inertial", "tile_interp", "tile_interp_grad",
-           "inertial_direct", "interp", "rk2_direct_stage2", "rk2_direct_bwd")
+           "inertial_direct", "interp", "rk2_direct_stage2", "rk2_direct_bwd",
+           "rk2_direct_bwd_gather")
 
 
 def key_bytes(n):
@@ -128,6 +129,8 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step, vb=4):
         "interp": 3 * p3 * cb + np_ * (24 + 3 * vb),
         "rk2_direct_stage2": 3 * p3 * cb + np_ * (48 + 3 * vb),
         "rk2_direct_bwd": 2 * 3 * p3 * cb + 2 * 3 * p3 * 4 + np_ * (24 + 3 * vb + 48 + 96),
+        # x, lambda in; dL/dx_n, u0, ub0, ub1 out (for the tiled scatter)
+        "rk2_direct_bwd_gather": 3 * p3 * cb + np_ * (48 + 24 + 36),
     }
     return per_step[kernel]
 

@@ -49,6 +49,9 @@ pt_status rk2_backward(const pt_grid* g, const void* coeff, pt_dtype dtype, int6
                        double* xbs, hipStream_t s);
 pt_status scatter_back(int64_t np, const double* in, const int32_t* perm, double* out,
                        hipStream_t s);
+pt_status rk2_bwd_gather(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,
+                        double dt, const double* x, const double* lam, double* xbn, float* u0f,
+                        float* ub0f, float* ub1f, int* umax, hipStream_t s);
 pt_status rk2_correct(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np, double dt,
                       const double* x, const void* u0, double* x_out, hipStream_t s);
 // tile.hip
@@ -62,6 +65,11 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
                        float* u0, float* ub0, float* ub1, float* gcoeff, void* defer,
                        void* items_ws, bool check, hipStream_t s);
 size_t tile_defer_bytes(int64_t np);
+pt_status tile_defer_reset(void* defer, hipStream_t s);
+int* tile_umax_slots(void* defer);
+pt_status tile_scatter_only(const pt_grid* g, const int32_t* ls, int64_t np, double dt,
+                            const double* x, float* u0, float* ub0, float* ub1, float* gcoeff,
+                            void* defer, void* items_ws, bool check, hipStream_t s);
 pt_status tile_interp(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                       int64_t np, const double* x, int nout, float* out, void* defer,
                       void* items_ws, hipStream_t s);
@@ -583,6 +591,27 @@ pt_status pt_rk2_step_bwd(const pt_grid* grid, const void* coeff, pt_dtype dtype
   if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
   PT_TRY(ready());
   Rk2BwdWs w = carve_rk2_bwd(grid, np, dtype, ws);
+  if (sort != PT_UNSORTED && !tiled(dtype)) {
+    // FP64 storage: the gather half one thread per particle in FP64, then the
+    // column-tiled scatter on the same (sorted) order
+    const double* x = pos_n;
+    double* xbn = g_pos;  // PT_SORTED: in place
+    if (sort == PT_SORT) {
+      PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
+                            stream));
+      x = w.pos_sorted;
+      xbn = w.xbn;
+    } else {
+      PT_TRY(presorted_table(grid, np, pos_n, w.lstart, stream));
+    }
+    PT_TRY(tile_defer_reset(w.defer, stream));
+    PT_TRY(rk2_bwd_gather(grid, coeff, dtype, np, dt, x, g_pos, xbn, (float*)w.u0, w.ub0,
+                          (float*)w.xbs, tile_umax_slots(w.defer), stream));
+    if (g_coeff)
+      PT_TRY(tile_scatter_only(grid, w.lstart, np, dt, x, (float*)w.u0, w.ub0, (float*)w.xbs,
+                               g_coeff, w.defer, w.items, sort == PT_SORTED, stream));
+    return sort == PT_SORT ? scatter_back(np, w.xbn, w.perm, g_pos, stream) : PT_OK;
+  }
   if (sort == PT_SORT) {
     PT_TRY(sort_particles(grid, np, pos_n, w.pos_sorted, w.perm, nullptr, w.lstart, w.sort,
                           stream));

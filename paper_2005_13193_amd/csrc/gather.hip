@@ -263,6 +263,64 @@ __global__ __launch_bounds__(256) void rk2_bwd_n(GridDev g, const CT* __restrict
   if (gcoeff) spline_scatter(g, gcoeff, cl, ub);
 }
 
+// The gather half of a Heun step's adjoint, one thread per particle, for the
+// column-tiled scatter to finish: xbn = lam + xbs + J(x^n)^T ub0 (may alias
+// lam), and the stage-1 velocity and both stage adjoints in FP32 for the
+// scatter (ub1 = dt/2 lam, ub0 = dt/2 lam + dt xbs, xbs = J(x*)^T ub1); the
+// largest |ub| of each block goes to one of the 64 slots of `umax` (float
+// bits, compared as integers: all non-negative).
+template <typename CT>
+__global__ __launch_bounds__(256) void rk2_bwd_gather_direct(
+    GridDev g, const CT* __restrict__ coeff, int64_t np, double dt, const double* __restrict__ x,
+    const double* lam, double* xbn, float* __restrict__ u0f, float* __restrict__ ub0f,
+    float* __restrict__ ub1f, int* umax, int* err) {
+  using AT = typename AccOf<CT>::T;
+  __shared__ float s_max[4];
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float m = 0.0f;
+  if (p < np) {
+    double xn[3], l[3], xs[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xn[d] = x[d * np + p];
+      l[d] = lam[d * np + p];
+    }
+    const Cell<AT> c0 = locate<AT>(g, xn[0], xn[1], xn[2], err);
+    AT on[12], os[12];
+    spline_eval<CT, true>(g, coeff, c0, on);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xs[d] = xn[d] + dt * (double)on[d];
+    const Cell<AT> c1 = locate<AT>(g, xs[0], xs[1], xs[2], err);
+    spline_eval<CT, true>(g, coeff, c1, os);
+    AT ub1[3], ub0[3];
+    double xbs[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ub1[d] = (AT)(0.5 * dt * l[d]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xbs[d] = (double)(ub1[0] * os[3 + d] + ub1[1] * os[6 + d] + ub1[2] * os[9 + d]);
+      ub0[d] = (AT)(0.5 * dt * l[d] + dt * xbs[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xbn[d * np + p] =
+          l[d] + xbs[d] + (double)(ub0[0] * on[3 + d] + ub0[1] * on[6 + d] + ub0[2] * on[9 + d]);
+      u0f[d * np + p] = (float)on[d];
+      ub0f[d * np + p] = (float)ub0[d];
+      ub1f[d * np + p] = (float)ub1[d];
+      m = fmaxf(m, fmaxf(fabsf((float)ub0[d]), fabsf((float)ub1[d])));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(s_max[0], s_max[1]), fmaxf(s_max[2], s_max[3]));
+    atomicMax(umax + (blockIdx.x & 63), __float_as_int(m));
+  }
+}
+
 __global__ __launch_bounds__(256) void scatter_rows_f64(int64_t np, const double* __restrict__ in,
                                                         const int32_t* __restrict__ perm,
                                                         double* __restrict__ out) {
@@ -364,6 +422,18 @@ pt_status rk2_backward(const pt_grid* g, const void* coeff, pt_dtype dtype, int6
                        (const VT*)u0, lam, xbs, gcoeff, err);
     hipLaunchKernelGGL(rk2_bwd_n<CT>, grid, block, 0, s, gd, (const CT*)coeff, np, dt, x, lam,
                        xbs, out, gcoeff, err);
+  });
+}
+
+pt_status rk2_bwd_gather(const pt_grid* g, const void* coeff, pt_dtype dtype, int64_t np,
+                        double dt, const double* x, const double* lam, double* xbn, float* u0f,
+                        float* ub0f, float* ub1f, int* umax, hipStream_t s) {
+  const GridDev gd = make_grid_dev(g);
+  TimedLaunch t("rk2_direct_bwd_gather", s);
+  return with_ct(dtype, [&]<typename CT>() {
+    hipLaunchKernelGGL(rk2_bwd_gather_direct<CT>, dim3(grid_1d(np, 256)), dim3(256), 0, s, gd,
+                       (const CT*)coeff, np, dt, x, lam, xbn, u0f, ub0f, ub1f, umax,
+                       device_error_flag());
   });
 }
 

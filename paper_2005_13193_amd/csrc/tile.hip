@@ -1685,6 +1685,11 @@ pt_status tile_tv_stage2(const pt_grid* g, const void* coeff, pt_dtype dtype, in
   return launch_gather(g, a, dtype, TILE_TV_STAGE2, defer, items_ws, true, s);
 }
 
+static pt_status launch_scatter(const pt_grid* g, const int32_t* ls, int64_t np, double dt,
+                                const double* x, float* u0, float* ub0, float* ub1,
+                                float* gcoeff, void* defer, void* items_ws, bool check,
+                                hipStream_t s);
+
 // defer: tile_defer_bytes(np) bytes; items_ws: tile_items_bytes(g, np, false)
 // followed by tile_items_bytes(g, np, true) bytes.  The gather writes u0,
 // ub0 and ub1 for the scatter, which then needs neither lam nor xbn: xbn may
@@ -1703,7 +1708,47 @@ pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   a.ub1 = ub1;
   pt_status st = launch_gather(g, a, dtype, TILE_RK2_BWD_GRAD, defer, items_ws, check, s);
   if (st != PT_OK || !gcoeff) return st;
-  TileArgs b = tile_args(g, coeff, ls, np, dt, kScatterSeg);
+  return launch_scatter(g, ls, np, dt, x, u0, ub0, ub1, gcoeff, defer, items_ws, check, s);
+}
+
+// Header of a deferred list cleared: its length, the slots of the largest
+// |ub| and the table flag.
+pt_status tile_defer_reset(void* defer, hipStream_t s) {
+  hipLaunchKernelGGL(zero_int, dim3(1), dim3(128), 0, s, (int*)defer);
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
+// Slots of the largest |ub| in a deferred-list header (for a gather that
+// fills them itself before launch_scatter).
+int* tile_umax_slots(void* defer) { return (int*)defer + 1; }
+
+// The scatter alone, after a gather (tiled or not) has written u0, ub0, ub1
+// and the largest |ub| into the header of `defer` (cleared before it by
+// tile_defer_reset).  check: the table ls comes from positions that may not
+// be in cell order, checked here first.
+pt_status tile_scatter_only(const pt_grid* g, const int32_t* ls, int64_t np, double dt,
+                            const double* x, float* u0, float* ub0, float* ub1, float* gcoeff,
+                            void* defer, void* items_ws, bool check, hipStream_t s) {
+  if (check) {
+    // a table that fails is emptied (no work items), and launch_scatter then
+    // sends every stencil to the deferred list
+    const int64_t nl = tile_nlayers(g);
+    hipLaunchKernelGGL(check_table, dim3(grid_1d(nl + 1, 256)), dim3(256), 0, s, ls, nl, np,
+                       (int*)defer + kTableBad);
+    hipLaunchKernelGGL(table_fallback, dim3(kFallbackBlocks), dim3(256), 0, s, (int32_t*)ls, nl,
+                       np, (int*)defer, (int32_t*)((char*)defer + kDeferHeader));
+    PT_LAUNCH_CHECK();
+  }
+  return launch_scatter(g, ls, np, dt, x, u0, ub0, ub1, gcoeff, defer, items_ws, check, s);
+}
+
+static pt_status launch_scatter(const pt_grid* g, const int32_t* ls, int64_t np, double dt,
+                                const double* x, float* u0, float* ub0, float* ub1,
+                                float* gcoeff, void* defer, void* items_ws, bool check,
+                                hipStream_t s) {
+  pt_status st;
+  TileArgs b = tile_args(g, nullptr, ls, np, dt, kScatterSeg);
   b.x = x;
   b.u0 = u0;
   b.ub0 = ub0;
