@@ -407,7 +407,7 @@ const char *pt_status_string(pt_status status);
  * "tile_rk2_fwd",
  * "tile_rk2_bwd_gather", "tile_scatter", "tile_tv_stage1", "tile_tv_stage2",
  * "tile_inertial", "tile_interp", "tile_interp_grad", "inertial_direct",
- * "interp", "rk2_direct_stage2", "rk2_direct_bwd". */
+ * "interp", "rk2_direct_stage2", "rk2_direct_bwd", "rk2_direct_bwd_gather". */
 pt_status pt_timing_enable(int on);
 pt_status pt_timing_read(const char *kernel, double *total_ms, int64_t *launches);
 

@@ -841,10 +841,29 @@ constexpr int kSSlot = kSPlane + 1;        // slot pitch (64-bit words)
 // A slab touches planes zs-1 .. zs+5 and then frees zs-1 and zs, which the
 // next slab's planes zs+6 and zs+7 take over: 7 slots.
 constexpr int kSRing = 7;
-constexpr int kSTB = 512;
+// Loader waves read the particles of the chunk after next, locate both
+// stages of each particle (FP64 positions, one lane per particle) and leave a
+// ready-to-scatter record per particle in LDS; the compute waves only form
+// the weights and add the contributions.  The compute waves then issue no
+// global loads at all: a load into registers that a later pass reuses makes
+// the compiler wait for every memory operation in flight (the flush's atomics
+// included) before issuing it, a full memory round trip per pass.
+constexpr int kSCompute = 512;             // compute threads (8 waves)
+constexpr int kSLoaders = 2;               // loader waves
+constexpr int kSTB = kSCompute + 64 * kSLoaders;
 constexpr int kSLanes = 8;                 // lanes per particle
-constexpr int kSGroups = kSTB / kSLanes;   // 64
-constexpr int kSPer = (kSPlane + kSTB - 1) / kSTB;  // plane words per thread (5)
+constexpr int kSPer = (kSPlane + kSCompute - 1) / kSCompute;  // plane words per thread (5)
+constexpr int kSChunk = 64 * kSLoaders;    // particles per chunk, one per loader lane
+// Record of a particle in a chunk buffer (32-bit words [kSRec][kSChunk]):
+//   0: stage-1 stencil, ring row-column offset | first plane's slot << 12,
+//      or kSNoRing when the stencil is not in the ring (deferred)
+//   1-3: stage-1 local coordinates (FP32)
+//   4-7: the same for the stage-2 (predictor) point
+//   8-10: stage-1 velocity adjoint ub0 times the fixed-point scale
+//   11-13: stage-2 velocity adjoint ub1 times the scale
+//   14: particle index
+constexpr int kSRec = 15;
+constexpr uint32_t kSNoRing = 0xFFFFFFFFu;
 
 __device__ __forceinline__ int sslot(int P) { return (P + 2 * kSRing) % kSRing; }
 
@@ -856,21 +875,25 @@ __device__ __forceinline__ void selem(int e, int* c, int* y, int* x) {
   *x = r - *y * kSTW;
 }
 
-__device__ __forceinline__ void scatter_ring(long long* ring, const Pt& q, int X0, int Y0,
+// Adds the 64-point stencil of one stage of a particle to the ring.  word:
+// record word 0 or 4 (not kSNoRing); t: local coordinates; us: scaled
+// velocity adjoint.  lane = (i, kh): x-offset i, planes k = 2 kh, 2 kh + 1.
+__device__ __forceinline__ void scatter_ring(long long* ring, uint32_t word, const float t[3],
                                              int lane, const float us[3]) {
-  // lane = (i, kh): x-offset i, planes k = 2 kh, 2 kh + 1
   float wx[4], wy[4], wz[4];
-  bspline_w(q.t[0], wx);
-  bspline_w(q.t[1], wy);
-  bspline_w(q.t[2], wz);
+  bspline_w(t[0], wx);
+  bspline_w(t[1], wy);
+  bspline_w(t[2], wz);
   const int i = lane & 3, kh = lane >> 2;
   const float wxi = pick4(wx, i);
-  const int off = (q.b - Y0) * kSTW + (q.a - X0) + i;
+  const int off = (int)(word & 0xFFFu) + i, slot0 = (int)(word >> 12);
 #pragma unroll
   for (int kk = 0; kk < 2; ++kk) {
     const int k = 2 * kh + kk;
     const float wzk = kh == 0 ? (kk == 0 ? wz[0] : wz[1]) : (kk == 0 ? wz[2] : wz[3]);
-    long long* pl = ring + sslot(q.c + k) * kSSlot + off;
+    int slot = slot0 + k;
+    slot -= slot >= kSRing ? kSRing : 0;
+    long long* pl = ring + slot * kSSlot + off;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float w = wxi * wy[j] * wzk;
@@ -884,37 +907,67 @@ __device__ __forceinline__ void scatter_ring(long long* ring, const Pt& q, int X
   }
 }
 
-// Per-particle data of a scatter pass, kept as loaded: any arithmetic on a
-// loaded value here would make the wave wait for that load (and every older
-// one) at prefetch time.
-struct SData {
-  double x[3];
-  float u0[3];
-  float ub1[3];
-  float ub0[3];
-  int p;
-  bool ok;
+// A particle's inputs as loaded: x (lo, hi words of each component), u0,
+// ub0, ub1.
+struct SRaw {
+  uint32_t w[15];
 };
 
-__device__ __forceinline__ void load_sdata(const TileArgs& a, int64_t p, bool ok, SData* d) {
+__device__ __forceinline__ void load_sraw(const TileArgs& a, int64_t p, SRaw* r) {
   const int64_t np = a.np;
-  const int64_t i = ok ? p : 0;
-  d->ok = ok;
-  d->p = (int)p;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    d->x[c] = a.x[c * np + i];
-    d->u0[c] = a.u0[c * np + i];
-    d->ub1[c] = a.ub1[c * np + i];
-    d->ub0[c] = a.ub0[c * np + i];
+    const uint2 xw = *(const uint2*)(a.x + c * np + p);
+    r->w[2 * c] = xw.x;
+    r->w[2 * c + 1] = xw.y;
+    r->w[6 + c] = __float_as_uint(a.u0[c * np + p]);
+    r->w[9 + c] = __float_as_uint(a.ub0[c * np + p]);
+    r->w[12 + c] = __float_as_uint(a.ub1[c * np + p]);
   }
 }
 
+// Record word 0 or 4 of a located point: cells with tile-local index in
+// [0, kTileX + 2) x [0, kTileY/2 + 2) and layers zs-1 .. zs+kSlab have their
+// stencils inside the tile and the ring.
+__device__ __forceinline__ uint32_t ring_word(const Pt& q, int X0, int Y0, int zs) {
+  const int lx = q.a - X0, ly = q.b - Y0;
+  const bool in = lx >= 0 && lx < kTileX + 2 && ly >= 0 && ly < kTileY / 2 + 2 &&
+                  q.c >= zs - 1 && q.c <= zs + kSlab;
+  return in ? (uint32_t)(ly * kSTW + lx) | ((uint32_t)sslot(q.c) << 12) : kSNoRing;
+}
+
+// Builds the record of particle p of slab zs in slot l of chunk buffer pb.
+__device__ __forceinline__ void store_srec(const TileArgs& a, const SRaw& r, int64_t p, int X0,
+                                           int Y0, int zs, float scale, uint32_t* pb, int l,
+                                           int* lerr) {
+  double x[3], xs[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    x[c] = __longlong_as_double((long long)((uint64_t)r.w[2 * c] |
+                                            ((uint64_t)r.w[2 * c + 1] << 32)));
+    xs[c] = x[c] + a.dt * (double)__uint_as_float(r.w[6 + c]);
+  }
+  const Pt qn = locate_pt<0>(a.g, x, 0, 0, 0, -1, lerr);
+  const Pt qs = locate_pt<0>(a.g, xs, 0, 0, 0, -1, lerr);
+  uint32_t w[kSRec];
+  w[0] = ring_word(qn, X0, Y0, zs);
+  w[4] = ring_word(qs, X0, Y0, zs);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    w[1 + c] = __float_as_uint(qn.t[c]);
+    w[5 + c] = __float_as_uint(qs.t[c]);
+    w[8 + c] = __float_as_uint(__uint_as_float(r.w[9 + c]) * scale);
+    w[11 + c] = __float_as_uint(__uint_as_float(r.w[12 + c]) * scale);
+  }
+  w[14] = (uint32_t)p;
+#pragma unroll
+  for (int k = 0; k < kSRec; ++k) pb[k * kSChunk + l] = w[k];
+}
+
 // Deferred stencils (2 p + stage) collect in a small LDS list that the
-// workgroup copies to the global list at slab ends (see dump_deferred): a
-// global counter draw or store here would make the wave's next waits for its
-// particle loads wait for everything in flight.  Past the LDS capacity an
-// entry goes straight to the global list.
+// workgroup copies to the global list at slab ends (see dump_deferred), so
+// that the compute waves issue no global memory operation they would have to
+// wait for.  Past the LDS capacity an entry goes straight to the global list.
 constexpr int kSDefCap = 512;
 
 __device__ __forceinline__ void defer_stencil(const TileArgs& a, int* sdef_n, uint32_t* sdef,
@@ -938,45 +991,13 @@ __device__ __forceinline__ void dump_deferred(const TileArgs& a, int* sdef_n, ui
   const int n = min(*sdef_n, kSDefCap);
   if (n == 0 || (!force && n < kSDefCap / 2)) return;  // uniform
   if (threadIdx.x == 0) *s_base = atomicAdd(a.defer_count, n);
-  __syncthreads();
+  lds_barrier();
   const int64_t base = *s_base;
-  for (int i = threadIdx.x; i < n; i += kSTB)
-    if (base + i < 2 * a.np) a.defer[base + i] = sdef[i];
-  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kSCompute)
+    if (i < n && threadIdx.x < kSCompute && base + i < 2 * a.np) a.defer[base + i] = sdef[i];
+  lds_barrier();
   if (threadIdx.x == 0) *sdef_n = 0;
-  __syncthreads();
-}
-
-__device__ __forceinline__ void scatter_one(const TileArgs& a, long long* ring, const SData& d,
-                                            int X0, int Y0, int zz, int lane, float scale,
-                                            int* sdef_n, uint32_t* sdef, int* lerr) {
-  const GridDev& g = a.g;
-  double xs[3];
-  float s0[3], s1[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    xs[c] = d.x[c] + a.dt * (double)d.u0[c];
-    s0[c] = d.ub0[c] * scale;
-    s1[c] = d.ub1[c] * scale;
-  }
-  // cells with tile-local index in [0, kTileX + 2) x [0, kTileY/2 + 2) and
-  // layers zz-1 .. zz+2 have their stencils inside the tile and the ring
-  Pt qn = locate_pt<0>(g, d.x, X0, Y0, zz - 1, zz + kSlab, lerr);
-  {
-    const int lx = qn.a - X0, ly = qn.b - Y0;
-    qn.in_ring = lx >= 0 && lx < kTileX + 2 && ly >= 0 && ly < kTileY / 2 + 2 &&
-                 qn.c >= zz - 1 && qn.c <= zz + kSlab;
-  }
-  if (qn.in_ring) scatter_ring(ring, qn, X0, Y0, lane, s0);
-  else if (lane == 0) defer_stencil(a, sdef_n, sdef, d.p, 0);
-  Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
-  {
-    const int lx = qs.a - X0, ly = qs.b - Y0;
-    qs.in_ring = lx >= 0 && lx < kTileX + 2 && ly >= 0 && ly < kTileY / 2 + 2 &&
-                 qs.c >= zz - 1 && qs.c <= zz + kSlab;
-  }
-  if (qs.in_ring) scatter_ring(ring, qs, X0, Y0, lane, s1);
-  else if (lane == 0) defer_stencil(a, sdef_n, sdef, d.p, 1);
+  lds_barrier();
 }
 
 __device__ __forceinline__ float scatter_scale(const TileArgs& a) {
@@ -996,7 +1017,7 @@ __device__ __forceinline__ void flush_offsets(const GridDev& g, int X0, int Y0,
                                               int64_t off[kSPer]) {
 #pragma unroll
   for (int q = 0; q < kSPer; ++q) {
-    const int e = threadIdx.x + q * kSTB;
+    const int e = threadIdx.x + q * kSCompute;
     int c, y, x;
     selem(e, &c, &y, &x);
     const int X = X0 + x, Y = Y0 + y;
@@ -1016,42 +1037,58 @@ __device__ __forceinline__ float fixed_to_float(long long acc, float inv_scale) 
   return fmaf(hi, 4294967296.0f, lo) * inv_scale;
 }
 
-// Adds a finished plane of the ring to the gradient with one FP32 atomic add
-// per point (a single instruction instead of a load and a store; the colours
-// keep every other workgroup of the launch off these points, so the sums are
-// the same as a read-modify-write) and clears it for reuse.  The thread's LDS
-// reads are all issued before any conversion or global atomic.
-__device__ __forceinline__ void flush_splane(const TileArgs& a, long long* ring,
-                                             const int64_t off[kSPer], int P, float inv_scale) {
+// Adds finished planes P0 .. P0 + NP - 1 of the ring to the gradient with one
+// FP32 atomic add per point (a single instruction instead of a load and a
+// store; the colours keep every other workgroup of the launch off these
+// points, so the sums are the same as a read-modify-write) and clears them
+// for reuse.  All of the thread's LDS reads are issued before any conversion
+// or global atomic.  Planes outside the padded grid are skipped.
+template <int NP>
+__device__ __forceinline__ void flush_splanes(const TileArgs& a, long long* ring,
+                                              const int64_t off[kSPer], int P0, float inv_scale) {
   const GridDev& g = a.g;
-  if (P < 0 || P >= g.nz + 3) return;
-  long long* sl = ring + sslot(P) * kSSlot;
-  float* gp = a.gcoeff + (int64_t)P * g.plane;
-  long long acc[kSPer];
+  long long acc[NP][kSPer];
 #pragma unroll
-  for (int q = 0; q < kSPer; ++q) {
-    const int e = min((int)threadIdx.x + q * kSTB, kSPlane - 1);  // a word of the plane
-    acc[q] = sl[e];
+  for (int h = 0; h < NP; ++h) {
+    const long long* sl = ring + sslot(P0 + h) * kSSlot;
+#pragma unroll
+    for (int q = 0; q < kSPer; ++q) {
+      const int e = min((int)threadIdx.x + q * kSCompute, kSPlane - 1);  // a word of the plane
+      acc[h][q] = sl[e];
+    }
   }
 #pragma unroll
-  for (int q = 0; q < kSPer; ++q) {
-    const int e = threadIdx.x + q * kSTB;
-    if (e < kSPlane) sl[e] = 0;
+  for (int h = 0; h < NP; ++h) {
+    long long* sl = ring + sslot(P0 + h) * kSSlot;
+#pragma unroll
+    for (int q = 0; q < kSPer; ++q) {
+      const int e = threadIdx.x + q * kSCompute;
+      if (e < kSPlane) sl[e] = 0;
+    }
   }
 #pragma unroll
-  for (int q = 0; q < kSPer; ++q)
-    if (acc[q] != 0 && off[q] >= 0) atomicAdd(gp + off[q], fixed_to_float(acc[q], inv_scale));
+  for (int h = 0; h < NP; ++h) {
+    const int P = P0 + h;
+    if (P < 0 || P >= g.nz + 3) continue;
+    float* gp = a.gcoeff + (int64_t)P * g.plane;
+#pragma unroll
+    for (int q = 0; q < kSPer; ++q)
+      if (acc[h][q] != 0 && off[q] >= 0) atomicAdd(gp + off[q], fixed_to_float(acc[h][q], inv_scale));
+  }
 }
 
 __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   extern __shared__ long long ssm[];
   long long* ring = ssm;
-  int* lst = (int*)(ssm + kSRing * kSSlot);  // [2 (nl + 1)] half-layer starts
+  uint32_t* pbuf = (uint32_t*)(ssm + kSRing * kSSlot);  // [2][kSRec][kSChunk]
+  int* lst = (int*)(pbuf + 2 * kSRec * kSChunk);       // [2 (nl + 1)] half-layer starts
   int* sdef_n = lst + 2 * (kScatterSeg + 2);  // LDS deferred list: length, base, entries
   int* s_base = sdef_n + 1;
   uint32_t* sdef = (uint32_t*)(sdef_n + 4);
   const GridDev& g = a.g;
   const float scale = scatter_scale(a), inv_scale = 1.0f / scale;
+  const int wave = threadIdx.x >> 6;
+  const bool loader = wave >= kSCompute / 64;
   int lerr = 0;  // a non-finite position was met
   if (threadIdx.x == 0) *sdef_n = 0;  // published by the barrier in next_item
   int col, half, z0, z1, range_k = 0;
@@ -1059,7 +1096,7 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
   const int X0 = cx * kTileX - 1, Y0 = cy * kTileY + half * (kTileY / 2) - 1;
   int64_t foff[kSPer];
-  flush_offsets(g, X0, Y0, foff);
+  if (!loader) flush_offsets(g, X0, Y0, foff);
   const int lane = threadIdx.x & (kSLanes - 1), grp = threadIdx.x / kSLanes;
   const int nl = z1 - z0;
   // starts of this half and of the next half-layer, for layers z0 .. z1
@@ -1071,81 +1108,121 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   for (int e = threadIdx.x; e < kSRing * kSSlot; e += kSTB) ring[e] = 0;
   __syncthreads();
 
-  // particles of slab s: layer zs (half) then layer zs+1 (half); quad group
-  // grp takes the particles grp * npass + k of that virtual list, so that the
-  // groups of a pass are spread over the slab (fewer same-word adds in dense
-  // clusters)
-  auto slab_range = [&](int zs, int64_t* r0, int64_t* n0, int64_t* r1, int64_t* n1) {
-    *r0 = *n0 = *r1 = *n1 = 0;
-    if (zs >= z1) return;
+  // The particles of slab zs (layers zs, zs+1 of this half): one virtual list
+  // of n0 + n1, taken in chunks of kSChunk.  Chunks run in slab order, each
+  // slab taking at least one.
+  auto slab_count = [&](int zs, int64_t* r0, int64_t* n0, int64_t* r1) {
+    *r0 = *n0 = *r1 = 0;
+    if (zs >= z1) return (int64_t)0;
     const int i0 = zs - z0;
     *r0 = lst[2 * i0];
     *n0 = lst[2 * i0 + 1] - *r0;
+    int64_t n1 = 0;
     if (zs + 1 < z1) {
       *r1 = lst[2 * i0 + 2];
-      *n1 = lst[2 * i0 + 3] - *r1;
+      n1 = lst[2 * i0 + 3] - *r1;
+    }
+    return *n0 + n1;
+  };
+  auto nchunks = [](int64_t n) { return n > 0 ? (int)((n + kSChunk - 1) / kSChunk) : 1; };
+  auto advance = [&](int* zs, int* j) {
+    int64_t r0, n0, r1;
+    if (*j + 1 >= nchunks(slab_count(*zs, &r0, &n0, &r1))) {
+      *zs += kSlab;
+      *j = 0;
+    } else {
+      ++*j;
     }
   };
-  auto vidx = [&](int64_t v, int64_t r0, int64_t n0, int64_t r1) {
-    return v < n0 ? r0 + v : r1 + (v - n0);
+
+  // Loader side: raw inputs of this lane's particle of chunk (lzs, lj), in
+  // flight while the compute waves work on the chunk before it.
+  const int ll = threadIdx.x - kSCompute;  // loader lane 0 .. kSChunk-1
+  SRaw raw;
+  int64_t raw_p = -1;
+  int lzs = z0, lj = 0;
+  auto issue = [&]() {
+    int64_t r0, n0, r1;
+    const int64_t n = slab_count(lzs, &r0, &n0, &r1);
+    const int64_t v = (int64_t)lj * kSChunk + ll;
+    raw_p = v < n ? (v < n0 ? r0 + v : r1 + (v - n0)) : -1;
+    if (raw_p >= 0) load_sraw(a, raw_p, &raw);
   };
-  SData sd[2];
-  auto prefetch = [&](int set, int s) {
-    const int zs = z0 + s * kSlab;
-    int64_t r0, n0, r1, n1;
-    slab_range(zs, &r0, &n0, &r1, &n1);
-    const int64_t n = n0 + n1;
-    const int64_t npass = (n + kSGroups - 1) / kSGroups;
-    const int64_t v = grp * npass;
-    load_sdata(a, vidx(v, r0, n0, r1), v < n, &sd[set]);
+  auto finish = [&](int buf) {
+    if (raw_p >= 0)
+      store_srec(a, raw, raw_p, X0, Y0, lzs, scale, pbuf + buf * kSRec * kSChunk, ll, &lerr);
   };
-  prefetch(0, 0);
-  prefetch(1, 1);
-  for (int s0 = 0; z0 + s0 * kSlab < z1; s0 += 2) {
+  if (loader) {
+    issue();
+    finish(0);  // chunk 0
+    advance(&lzs, &lj);
+    issue();    // chunk 1
+  }
+  lds_barrier();
+  int zs = z0, j = 0, b = 0;
+  while (zs < z1) {  // uniform
+    int64_t r0, n0, r1;
+    const int64_t n = slab_count(zs, &r0, &n0, &r1);
+    const bool slab_end = j + 1 >= nchunks(n);
+    if (loader) {
+      // buffer b ^ 1 was last read before the previous barrier
+      finish(b ^ 1);  // chunk after this one
+      advance(&lzs, &lj);
+      issue();        // the one after that
+    } else {
+      const uint32_t* pb = pbuf + b * kSRec * kSChunk;
+      const int cnt = (int)min((int64_t)kSChunk, n - (int64_t)j * kSChunk);
+      // the wave's particles spaced cnt/8 apart in the chunk, so that in
+      // dense cells they do not all add to the same LDS words in one
+      // instruction
+      const int nslot = (cnt + 7) / 8, sub = grp & 7;
+      for (int r = wave; r < nslot; r += kSCompute / 64) {
+        const int q = sub * nslot + r;
+        if (q >= cnt) continue;
+        float t[3], s0[3], s1[3];
+        const uint32_t wn = pb[q], ws = pb[4 * kSChunk + q];
+        const uint32_t pq = pb[14 * kSChunk + q];
 #pragma unroll
-    for (int hf = 0; hf < 2; ++hf) {
-      const int s = s0 + hf;
-      const int zs = z0 + s * kSlab;
-      if (zs < z1) {
-        int64_t r0, n0, r1, n1;
-        slab_range(zs, &r0, &n0, &r1, &n1);
-        const int64_t n = n0 + n1;
-        const int64_t npass = (n + kSGroups - 1) / kSGroups;
-        // passes alternate between two register sets, the next pass loading
-        // into the set not in use (no copies between sets, which would make
-        // the wave wait for the loads in flight)
-        SData sb;
-        for (int64_t k = 0; k < npass; k += 2) {
-          const int64_t v = grp * npass + k;
-          if (k + 1 < npass) load_sdata(a, vidx(v + 1, r0, n0, r1), v + 1 < n, &sb);
-          if (sd[hf].ok) scatter_one(a, ring, sd[hf], X0, Y0, zs, lane, scale, sdef_n, sdef, &lerr);
-          if (k + 1 >= npass) break;
-          if (k + 2 < npass) load_sdata(a, vidx(v + 2, r0, n0, r1), v + 2 < n, &sd[hf]);
-          if (sb.ok) scatter_one(a, ring, sb, X0, Y0, zs, lane, scale, sdef_n, sdef, &lerr);
+        for (int c = 0; c < 3; ++c) {
+          s0[c] = __uint_as_float(pb[(8 + c) * kSChunk + q]);
+          s1[c] = __uint_as_float(pb[(11 + c) * kSChunk + q]);
         }
-        __syncthreads();
-        // Slab end: the only place with global stores.  Wait for everything
-        // first (the loads for the next slab were issued a slab ago), so that
-        // afterwards only these stores and the new prefetch are in flight.
-        PT_WAIT_VMCNT0();
-        // planes zs-1 and zs are complete: later particles sit in layers
-        // >= zs+2 and their predictor points in layers >= zs+1
-        flush_splane(a, ring, foff, zs - 1, inv_scale);
-        flush_splane(a, ring, foff, zs, inv_scale);
-        dump_deferred(a, sdef_n, sdef, s_base, false);
-        prefetch(hf, s + 2);
-        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t[c] = __uint_as_float(pb[(1 + c) * kSChunk + q]);
+        if (wn != kSNoRing) scatter_ring(ring, wn, t, lane, s0);
+        else if (lane == 0) defer_stencil(a, sdef_n, sdef, pq, 0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t[c] = __uint_as_float(pb[(5 + c) * kSChunk + q]);
+        if (ws != kSNoRing) scatter_ring(ring, ws, t, lane, s1);
+        else if (lane == 0) defer_stencil(a, sdef_n, sdef, pq, 1);
       }
     }
+    if (slab_end) {
+      lds_barrier();
+      // planes zs-1 and zs are complete: later particles sit in layers
+      // >= zs+2 and their predictor points in layers >= zs+1
+      if (!loader) flush_splanes<2>(a, ring, foff, zs - 1, inv_scale);
+      dump_deferred(a, sdef_n, sdef, s_base, false);
+    }
+    lds_barrier();  // the next chunk is in LDS
+    if (slab_end) {
+      zs += kSlab;
+      j = 0;
+    } else {
+      ++j;
+    }
+    b ^= 1;
   }
   // planes above the last flushed one: the last slab accepted cells up to
   // last_zs + kSlab, whose stencils reach plane last_zs + kSlab + 3 (z1 + 3
   // for an even item length, z1 + 4 for an odd one)
   const int last_zs = z0 + ((nl - 1) / kSlab) * kSlab;
-  for (int P = last_zs + 1; P <= last_zs + kSlab + 3; ++P) {
-    flush_splane(a, ring, foff, P, inv_scale);
-    __syncthreads();
+  static_assert(kSlab + 3 == 5, "end-of-item flush covers five planes");
+  if (!loader) {
+    flush_splanes<3>(a, ring, foff, last_zs + 1, inv_scale);
+    flush_splanes<2>(a, ring, foff, last_zs + 4, inv_scale);
   }
+  lds_barrier();
   }  // items
   __syncthreads();
   dump_deferred(a, sdef_n, sdef, s_base, true);
@@ -1769,9 +1846,9 @@ static pt_status launch_scatter(const pt_grid* g, const int32_t* ls, int64_t np,
                        b.defer_count, b.defer, np);
     PT_LAUNCH_CHECK();
   }
-  const size_t lds =
-      sizeof(long long) * (size_t)kSRing * kSSlot + sizeof(int) * 2 * (kScatterSeg + 2) +
-      sizeof(int) * (4 + (size_t)kSDefCap);
+  const size_t lds = sizeof(long long) * (size_t)kSRing * kSSlot +
+                     sizeof(uint32_t) * 2 * kSRec * kSChunk + sizeof(int) * 2 * (kScatterSeg + 2) +
+                     sizeof(int) * (4 + (size_t)kSDefCap);
   if (!allow_lds(tile_scatter, lds)) return PT_ERR_HIP;
   const unsigned blocks = item_blocks(it.bound);
   for (int color = 0; color < 8; ++color) {
