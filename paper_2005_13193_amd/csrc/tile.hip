@@ -877,7 +877,9 @@ __device__ __forceinline__ void selem(int e, int* c, int* y, int* x) {
 
 // Adds the 64-point stencil of one stage of a particle to the ring.  word:
 // record word 0 or 4 (not kSNoRing); t: local coordinates; us: scaled
-// velocity adjoint.  lane = (i, kh): x-offset i, planes k = 2 kh, 2 kh + 1.
+// velocity adjoint.  lane = (i, kh) of the particle's 16 / NK lanes:
+// x-offset i, planes k = NK kh .. NK kh + NK - 1.
+template <int NK>
 __device__ __forceinline__ void scatter_ring(long long* ring, uint32_t word, const float t[3],
                                              int lane, const float us[3]) {
   float wx[4], wy[4], wz[4];
@@ -888,9 +890,9 @@ __device__ __forceinline__ void scatter_ring(long long* ring, uint32_t word, con
   const float wxi = pick4(wx, i);
   const int off = (int)(word & 0xFFFu) + i, slot0 = (int)(word >> 12);
 #pragma unroll
-  for (int kk = 0; kk < 2; ++kk) {
-    const int k = 2 * kh + kk;
-    const float wzk = kh == 0 ? (kk == 0 ? wz[0] : wz[1]) : (kk == 0 ? wz[2] : wz[3]);
+  for (int kk = 0; kk < NK; ++kk) {
+    const int k = NK * kh + kk;
+    const float wzk = pick4(wz, k);
     int slot = slot0 + k;
     slot -= slot >= kSRing ? kSRing : 0;
     long long* pl = ring + slot * kSSlot + off;
@@ -900,6 +902,50 @@ __device__ __forceinline__ void scatter_ring(long long* ring, uint32_t word, con
 #pragma unroll
       for (int comp = 0; comp < 3; ++comp) {
         const int v = __float2int_rn(w * us[comp]);
+        atomicAdd((unsigned long long*)(pl + comp * kSComp + j * kSTW),
+                  (unsigned long long)(long long)v);
+      }
+    }
+  }
+}
+
+// Stage 1 of a particle, and stage 2 with it when both points share a cell
+// (pair): one atomic per point then adds w1 s0 + w2 s1, rounded once.  About
+// half of the particles at usual Courant numbers, so it saves a good part of
+// the LDS atomics, which bound the kernel.  word: record word 0 (not
+// kSNoRing); t1, t2: local coordinates of the two points; s0, s1: scaled
+// stage adjoints.
+template <int NK>
+__device__ __forceinline__ void scatter_ring2(long long* ring, uint32_t word, const float t1[3],
+                                              const float t2[3], bool pair, int lane,
+                                              const float s0[3], const float s1[3]) {
+  float wx[4], wy[4], wz[4], vx[4], vy[4], vz[4];
+  bspline_w(t1[0], wx);
+  bspline_w(t1[1], wy);
+  bspline_w(t1[2], wz);
+  bspline_w(t2[0], vx);
+  bspline_w(t2[1], vy);
+  bspline_w(t2[2], vz);
+  const int i = lane & 3, kh = lane >> 2;
+  const float wxi = pick4(wx, i), vxi = pick4(vx, i);
+  float u1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u1[c] = pair ? s1[c] : 0.0f;
+  const int off = (int)(word & 0xFFFu) + i, slot0 = (int)(word >> 12);
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk) {
+    const int k = NK * kh + kk;
+    const float wzk = pick4(wz, k), vzk = pick4(vz, k);
+    const float a1 = wxi * wzk, a2 = vxi * vzk;
+    int slot = slot0 + k;
+    slot -= slot >= kSRing ? kSRing : 0;
+    long long* pl = ring + slot * kSSlot + off;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float w1 = a1 * wy[j], w2 = a2 * vy[j];
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+        const int v = __float2int_rn(fmaf(w2, u1[comp], w1 * s0[comp]));
         atomicAdd((unsigned long long*)(pl + comp * kSComp + j * kSTW),
                   (unsigned long long)(long long)v);
       }
@@ -998,6 +1044,31 @@ __device__ __forceinline__ void dump_deferred(const TileArgs& a, int* sdef_n, ui
   lds_barrier();
   if (threadIdx.x == 0) *sdef_n = 0;
   lds_barrier();
+}
+
+// Both stages of staged particle q of chunk buffer pb, on the particle's
+// 16 / NK lanes (lane: this thread's index among them).
+template <int NK>
+__device__ __forceinline__ void scatter_particle(const TileArgs& a, long long* ring,
+                                                 const uint32_t* pb, int q, int lane, int* sdef_n,
+                                                 uint32_t* sdef) {
+  float tn[3], ts[3], s0[3], s1[3];
+  const uint32_t wn = pb[q], ws = pb[4 * kSChunk + q];
+  const uint32_t pq = pb[14 * kSChunk + q];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    s0[c] = __uint_as_float(pb[(8 + c) * kSChunk + q]);
+    s1[c] = __uint_as_float(pb[(11 + c) * kSChunk + q]);
+    tn[c] = __uint_as_float(pb[(1 + c) * kSChunk + q]);
+    ts[c] = __uint_as_float(pb[(5 + c) * kSChunk + q]);
+  }
+  const bool pair = wn == ws && wn != kSNoRing;
+  if (wn != kSNoRing) scatter_ring2<NK>(ring, wn, tn, ts, pair, lane, s0, s1);
+  else if (lane == 0) defer_stencil(a, sdef_n, sdef, pq, 0);
+  if (!pair) {
+    if (ws != kSNoRing) scatter_ring<NK>(ring, ws, ts, lane, s1);
+    else if (lane == 0) defer_stencil(a, sdef_n, sdef, pq, 1);
+  }
 }
 
 __device__ __forceinline__ float scatter_scale(const TileArgs& a) {
@@ -1141,11 +1212,15 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   SRaw raw;
   int64_t raw_p = -1;
   int lzs = z0, lj = 0;
+  // particle of this lane in chunk j of a slab (r0, n0, r1: slab_count), or -1
+  auto particle = [&](int j, int64_t n, int64_t r0, int64_t n0, int64_t r1) {
+    const int64_t v = (int64_t)j * kSChunk + ll;
+    return v < n ? (v < n0 ? r0 + v : r1 + (v - n0)) : (int64_t)-1;
+  };
   auto issue = [&]() {
     int64_t r0, n0, r1;
     const int64_t n = slab_count(lzs, &r0, &n0, &r1);
-    const int64_t v = (int64_t)lj * kSChunk + ll;
-    raw_p = v < n ? (v < n0 ? r0 + v : r1 + (v - n0)) : -1;
+    raw_p = particle(lj, n, r0, n0, r1);
     if (raw_p >= 0) load_sraw(a, raw_p, &raw);
   };
   auto finish = [&](int buf) {
@@ -1165,36 +1240,39 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
     const int64_t n = slab_count(zs, &r0, &n0, &r1);
     const bool slab_end = j + 1 >= nchunks(n);
     if (loader) {
-      // buffer b ^ 1 was last read before the previous barrier
-      finish(b ^ 1);  // chunk after this one
-      advance(&lzs, &lj);
-      issue();        // the one after that
+      // The slab bounds of the chunk after next are read first, while the
+      // LDS queue is short (right after the barrier, before the compute
+      // waves' atomics); then the chunk after this one is finished into
+      // buffer b ^ 1 (last read before the previous barrier) and the loads
+      // of the one after that are issued.
+      int nzs = lzs, nj = lj;
+      advance(&nzs, &nj);
+      int64_t nr0, nn0, nr1;
+      const int64_t nn = slab_count(nzs, &nr0, &nn0, &nr1);
+      const int64_t np2 = particle(nj, nn, nr0, nn0, nr1);
+      finish(b ^ 1);
+      lzs = nzs;
+      lj = nj;
+      raw_p = np2;
+      if (raw_p >= 0) load_sraw(a, raw_p, &raw);
     } else {
       const uint32_t* pb = pbuf + b * kSRec * kSChunk;
       const int cnt = (int)min((int64_t)kSChunk, n - (int64_t)j * kSChunk);
-      // the wave's particles spaced cnt/8 apart in the chunk, so that in
-      // dense cells they do not all add to the same LDS words in one
-      // instruction
-      const int nslot = (cnt + 7) / 8, sub = grp & 7;
-      for (int r = wave; r < nslot; r += kSCompute / 64) {
-        const int q = sub * nslot + r;
-        if (q >= cnt) continue;
-        float t[3], s0[3], s1[3];
-        const uint32_t wn = pb[q], ws = pb[4 * kSChunk + q];
-        const uint32_t pq = pb[14 * kSChunk + q];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          s0[c] = __uint_as_float(pb[(8 + c) * kSChunk + q]);
-          s1[c] = __uint_as_float(pb[(11 + c) * kSChunk + q]);
+      // Chunks of at most 32 particles (most slabs outside dense clusters)
+      // take 16 lanes per particle, so that all compute waves share the
+      // work; larger ones 8.  The wave's particles are spaced apart in the
+      // chunk, so that in dense cells they do not all add to the same LDS
+      // words in one instruction.
+      if (cnt <= kSCompute / 16) {
+        const int nslot = (cnt + 3) / 4, sub = (threadIdx.x & 63) >> 4;
+        if (wave < nslot && sub * nslot + wave < cnt)
+          scatter_particle<1>(a, ring, pb, sub * nslot + wave, threadIdx.x & 15, sdef_n, sdef);
+      } else {
+        const int nslot = (cnt + 7) / 8, sub = grp & 7;
+        for (int r = wave; r < nslot; r += kSCompute / 64) {
+          const int q = sub * nslot + r;
+          if (q < cnt) scatter_particle<2>(a, ring, pb, q, lane, sdef_n, sdef);
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) t[c] = __uint_as_float(pb[(1 + c) * kSChunk + q]);
-        if (wn != kSNoRing) scatter_ring(ring, wn, t, lane, s0);
-        else if (lane == 0) defer_stencil(a, sdef_n, sdef, pq, 0);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) t[c] = __uint_as_float(pb[(5 + c) * kSChunk + q]);
-        if (ws != kSNoRing) scatter_ring(ring, ws, t, lane, s1);
-        else if (lane == 0) defer_stencil(a, sdef_n, sdef, pq, 1);
       }
     }
     if (slab_end) {
