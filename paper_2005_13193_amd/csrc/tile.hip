@@ -104,6 +104,65 @@ __device__ __forceinline__ Pt locate_pt(const GridDev& g, const double p[3], int
   return q;
 }
 
+// Value of lane D of this lane's quad (one DPP move).
+template <int D>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, D * 0x55, 0xF, 0xF, true);
+}
+template <int D>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(quad_bcast<D>(__float_as_int(v)));
+}
+
+// v[i] for a lane-dependent i (i >= 2: v[2]) as two selects.  The values are
+// pinned in registers first (an empty asm statement): otherwise the compiler
+// may turn the choice into an indexed access, which moves the whole array to
+// scratch memory.
+template <typename T>
+__device__ __forceinline__ T pick3(const T v[3], int i) {
+  T a = v[0], b = v[1], c = v[2];
+  asm("" : "+v"(a), "+v"(b), "+v"(c));
+  return i == 0 ? a : i == 1 ? b : c;
+}
+
+// The grid axis a lane of a quad locates (lane d < 3: axis d; lane 3 repeats
+// axis 2).  Formed once per kernel: a lane-dependent choice between the
+// grid's fields inside a loop compiles to a memory load and a full wait.
+struct LaneAxis {
+  double cs;  // grid units per length
+  int n;      // points
+};
+
+__device__ __forceinline__ LaneAxis lane_axis(const GridDev& g, int lane) {
+  LaneAxis ax;
+  ax.cs = lane == 0 ? g.cs[0] : lane == 1 ? g.cs[1] : g.cs[2];
+  ax.n = lane == 0 ? g.nx : lane == 1 ? g.ny : g.nz;
+  return ax;
+}
+
+// locate_pt<0> run by the four lanes of a particle's quad together: each
+// lane locates its axis ax in FP64 (xd: that axis of the point) and the quad
+// shares the cells and local coordinates, instead of every lane locating all
+// three axes.  All four lanes of the quad must take part.
+__device__ __forceinline__ Pt locate_quad(const LaneAxis& ax, double xd, int X0, int Y0,
+                                          int zlo, int zhi, int* err) {
+  bool bad = false;
+  double t;
+  const int cell = cell_1d(xd, ax.cs, ax.n, &t, &bad);
+  if (bad) *err = 1;
+  const float tf = (float)t;
+  Pt q;
+  q.a = quad_bcast<0>(cell);
+  q.b = quad_bcast<1>(cell);
+  q.c = quad_bcast<2>(cell);
+  q.t[0] = quad_bcast<0>(tf);
+  q.t[1] = quad_bcast<1>(tf);
+  q.t[2] = quad_bcast<2>(tf);
+  const int lx = q.a - X0, ly = q.b - Y0;
+  q.in_ring = lx >= 0 && lx < kTileX && ly >= 0 && ly < kTileY && q.c >= zlo && q.c <= zhi;
+  return q;
+}
+
 // Value (GRAD: and gradient) of the three components at a point, read from
 // global memory (points whose stencil is not resident in LDS).
 template <typename CT, bool GRAD>
@@ -352,12 +411,15 @@ __device__ __forceinline__ void flush_pend(const TileArgs& a, Pend* o, DeferBatc
 template <typename CT, int MODE>
 __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t* ring,
                                               const PData& d, int X0, int Y0, int zz, int lane,
-                                              float* umax, Pend* o, int* lerr) {
+                                              const LaneAxis& ax, float* umax, Pend* o,
+                                              int* lerr) {
   const GridDev& g = a.g;
   const int64_t np = a.np, p = d.p;
   const double* xn = d.x;
+  // this lane's axis of x_n (lane 3: axis 2), for the quad-shared locates
+  const double xnl = pick3(xn, lane);
   // resident cells: layers zz-1 .. zz+kSlab (planes zz-1 .. zz+5)
-  const Pt qn = locate_pt<0>(g, xn, X0, Y0, zz - 1, zz + kSlab, lerr);
+  const Pt qn = locate_quad(ax, xnl, X0, Y0, zz - 1, zz + kSlab, lerr);
   if (!qn.in_ring) {  // cannot happen for a correctly sorted particle; kept safe
     if (lane == 0) o->defer = d.p;
     return;
@@ -375,10 +437,8 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
     }
   } else if (MODE == TILE_TV_STAGE2) {
     // x* = x + dt u^n (from stage 1), u^{n+1}(x*) from the ring
-    double xs[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)d.un[c];
-    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
+    const float unl = pick3(d.un, lane);
+    const Pt qs = locate_quad(ax, xnl + a.dt * (double)unl, X0, Y0, zz - 1, zz + kSlab, lerr);
     if (!qs.in_ring) {
       if (lane == 0) o->defer = d.p;
       return;
@@ -412,18 +472,17 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
   } else if (MODE == TILE_INERTIAL) {
     float u0[12], u1[12];
     eval_ring<CT, false>(ring, g, qn, X0, Y0, lane, u0);
-    double xs[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      xs[c] = inertial_predict(a.ik, xn[c], (double)d.un[c], (double)u0[c], d.lam[c]);
-    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
+    // this lane's axis (lane 3: axis 2) of the predictor point
+    const double xsl = inertial_predict(a.ik, xnl, (double)pick3(d.un, lane),
+                                        (double)pick3(u0, lane), pick3(d.lam, lane));
+    const Pt qs = locate_quad(ax, xsl, X0, Y0, zz - 1, zz + kSlab, lerr);
     if (!qs.in_ring) {
       if (lane == 0) o->defer = d.p;
       return;
     }
     eval_ring<CT, false>(ring, g, qs, X0, Y0, lane, u1);
     if (lane < 3) {
-      const double xl = lane == 0 ? xs[0] : lane == 1 ? xs[1] : xs[2];
+      const double xl = xsl;
       const double ua = lane == 0 ? u0[0] : lane == 1 ? u0[1] : u0[2];
       const double ub = lane == 0 ? u1[0] : lane == 1 ? u1[1] : u1[2];
       const double vl = lane == 0 ? d.un[0] : lane == 1 ? d.un[1] : d.un[2];
@@ -434,10 +493,8 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
   } else if (MODE == TILE_RK2_FWD) {
     float u0[12], u1[12];
     eval_ring<CT, false>(ring, g, qn, X0, Y0, lane, u0);
-    double xs[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)u0[c];
-    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
+    const float u0l = pick3(u0, lane);
+    const Pt qs = locate_quad(ax, xnl + a.dt * (double)u0l, X0, Y0, zz - 1, zz + kSlab, lerr);
     if (!qs.in_ring) {
       if (lane == 0) o->defer = d.p;
       return;
@@ -445,7 +502,7 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
     eval_ring<CT, false>(ring, g, qs, X0, Y0, lane, u1);
     if (lane < 3) {
       const double h = 0.5 * a.dt;
-      const double x0 = lane == 0 ? xn[0] : lane == 1 ? xn[1] : xn[2];
+      const double x0 = xnl;
       const float ua = lane == 0 ? u0[0] : lane == 1 ? u0[1] : u0[2];
       const float ub = lane == 0 ? u1[0] : lane == 1 ? u1[1] : u1[2];
       o->off = lane * np + p;
@@ -454,10 +511,8 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
   } else {
     float on[12], os[12];
     eval_ring<CT, true>(ring, g, qn, X0, Y0, lane, on);
-    double xs[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)on[c];
-    const Pt qs = locate_pt<0>(g, xs, X0, Y0, zz - 1, zz + kSlab, lerr);
+    const float onl = pick3(on, lane);
+    const Pt qs = locate_quad(ax, xnl + a.dt * (double)onl, X0, Y0, zz - 1, zz + kSlab, lerr);
     if (!qs.in_ring) {
       if (lane == 0) o->defer = d.p;
       return;
@@ -626,6 +681,7 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
   lds_barrier();
 
   const int lane = threadIdx.x & 3, grp = threadIdx.x >> 2;
+  const LaneAxis ax = lane_axis(g, lane);
   PData pd[2];
   auto prefetch = [&](int set, int s) {
     const int zs = z0 + s * kSlab;
@@ -671,7 +727,7 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
               load_pdata<MODE>(a, pn, pn < pe, &sb);
             }
             if (pd[half].ok)
-              ring_particle<CT, MODE>(a, ring, pd[half], X0, Y0, zs, lane, &umax, &pend, &lerr);
+              ring_particle<CT, MODE>(a, ring, pd[half], X0, Y0, zs, lane, ax, &umax, &pend, &lerr);
             if (k + 1 >= npass) break;
             PT_WAIT_VMCNT0();
             flush_pend<MODE>(a, &pend, &db, &lerr);
@@ -680,7 +736,7 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
               load_pdata<MODE>(a, pn, pn < pe, &pd[half]);
             }
             if (sb.ok)
-              ring_particle<CT, MODE>(a, ring, sb, X0, Y0, zs, lane, &umax, &pend, &lerr);
+              ring_particle<CT, MODE>(a, ring, sb, X0, Y0, zs, lane, ax, &umax, &pend, &lerr);
           }
           prefetch(half, s + 2);
         }
