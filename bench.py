@@ -595,9 +595,9 @@ def main():
         mark("sort", 0)
         B.pt_sort_particles(g, pos, pos_n, perm, ids, None, ws_s)
         mark("sort", 1)
-        pos.copy_(pos_n)
         mark("rk2_fwd", 0)
-        B.pt_rk2_step(g, coeff, dt, pos, None, B.PT_SORTED, ws_f)
+        # x_n stays in pos_n for the adjoint; x_{n+1} goes to pos
+        B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
         mark("rk2_fwd", 1)
         torch.mul(pos, 2.0, out=g_pos)  # dL/dx for L = sum |x|^2
         mark("rk2_bwd", 0)
@@ -800,9 +800,8 @@ def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
 
     def step():
         B.pt_sort_particles(g, pos, pos_n, perm, ids, None, ws_s)
-        pos.copy_(pos_n)
-        B.pt_interp_sorted(g, coeff, pos, out12, ws_i)
-        B.pt_rk2_step(g, coeff, dt, pos, None, B.PT_SORTED, ws_f)
+        B.pt_interp_sorted(g, coeff, pos_n, out12, ws_i)
+        B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
 
     for i in range(args.warmup):
         step()

@@ -233,6 +233,18 @@ pt_status pt_rk2_step(const pt_grid *grid, const void *coeff, pt_dtype dtype,
                       int64_t np, double dt, double *pos, int32_t *ids, int sort,
                       void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The same step out of place, for particles in any order (PT_UNSORTED) or in
+ * cell order (PT_SORTED), kept in it: pos_out = the step of pos_in, with the
+ * same kernels and the same results bit for bit as pt_rk2_step.  A caller
+ * that needs x_n after the step (an adjoint) keeps it without a copy.
+ * PT_SORT returns PT_ERR_ARG (it re-orders; use pt_rk2_step).
+ *   pos_in   in   double [3][np]
+ *   pos_out  out  double [3][np]; may be pos_in, else must not overlap it
+ *   ws            >= pt_workspace_bytes(PT_OP_RK2, ...) bytes */
+pt_status pt_rk2_step_out(const pt_grid *grid, const void *coeff, pt_dtype dtype,
+                          int64_t np, double dt, const double *pos_in, double *pos_out,
+                          int sort, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* The same step in a field that changes over the step, in two calls.  In the
  * paper's production runs (Sec. 4.3, Table 5) the particles are advanced at
  * each sub-step of the flow solver's second-order Runge-Kutta scheme, with

@@ -176,6 +176,17 @@ def rk2_step(grid, coeff, pos, dt, ids=None, sort=True, ws=None):
     return pos
 
 
+def rk2_step_out(grid, coeff, pos_in, dt, pos_out=None, sort=_b.PT_SORTED, ws=None):
+    """One Heun step out of place (PT_SORTED or PT_UNSORTED): returns pos_out
+    (allocated if None; may be pos_in), pos_in unchanged otherwise."""
+    if pos_out is None:
+        pos_out = torch.empty_like(pos_in)
+    if ws is None:
+        ws = workspace(_b.PT_OP_RK2, grid, pos_in.shape[1], coeff.dtype, pos_in.device)
+    _b.pt_rk2_step_out(grid, coeff, dt, pos_in, pos_out, sort, ws)
+    return pos_out
+
+
 def rk2_stage1(grid, coeff_n, pos, ids=None, sort=True, u_n=None, ws=None):
     """Stage 1 of a Heun step in a time-varying field: u_n = u^n(pos), after
     an optional cell sort of pos (and ids) in place.  Returns (u_n, ws); pass

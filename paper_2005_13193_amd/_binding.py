@@ -41,7 +41,7 @@ PT_UNSORTED, PT_SORT, PT_SORTED = 0, 1, 2  # sort argument of the RK2 steps
 EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_spline_coeffs_slab",
            "pt_sort_particles", "pt_slab_partition",
            "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_rk2_stage1", "pt_rk2_stage2",
-           "pt_inertial_step", "pt_rk2_step_noalloc", "pt_interp_sorted", "pt_tiled_deferred",
+           "pt_inertial_step", "pt_rk2_step_noalloc", "pt_rk2_step_out", "pt_interp_sorted", "pt_tiled_deferred",
            "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
            "pt_status_string", "pt_timing_enable", "pt_timing_read")
@@ -83,6 +83,7 @@ def _load():
         "pt_inertial_step": [g, vp, ctypes.c_int, i64, dbl, dbl, vp, vp, vp, vp, ctypes.c_int,
                              vp, sz, vp],
         "pt_rk2_step_noalloc": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp],
+        "pt_rk2_step_out": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
         "pt_interp_sorted": [g, vp, ctypes.c_int, i64, vp, ctypes.c_int, vp, vp, sz, vp],
         "pt_tiled_deferred": [ctypes.c_int, g, ctypes.c_int, i64, vp, ctypes.POINTER(i64)],
         "pt_interp_uvw_bwd": [g, vp, ctypes.c_int, i64, vp, vp, vp, vp, vp],
@@ -270,6 +271,17 @@ def pt_rk2_step(grid, coeff, dt, pos, ids, sort, ws, stream=None):
            LIB.pt_rk2_step(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
                            float(dt), _ptr(pos), _ptr(ids), int(sort), _ptr(ws),
                            ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pt_rk2_step_out(grid, coeff, dt, pos_in, pos_out, sort, ws, stream=None):
+    np_ = pos_in.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos_in, torch.float64, (3, np_), "pos_in")
+    _need(pos_out, torch.float64, (3, np_), "pos_out")
+    _check("pt_rk2_step_out",
+           LIB.pt_rk2_step_out(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                               float(dt), _ptr(pos_in), _ptr(pos_out), int(sort), _ptr(ws),
+                               ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def pt_rk2_stage1(grid, coeff_n, pos, ids, sort, u_n, ws, stream=None):

@@ -510,6 +510,32 @@ pt_status pt_rk2_step(const pt_grid* grid, const void* coeff, pt_dtype dtype, in
   return rk2_advance(grid, coeff, dtype, np, dt, pos, pos, w.u0, stream);
 }
 
+pt_status pt_rk2_step_out(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                          double dt, const double* pos_in, double* pos_out, int sort, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (!isfinite(dt)) return PT_ERR_ARG;
+  if (sort != PT_UNSORTED && sort != PT_SORTED) return PT_ERR_ARG;
+  if (sort == PT_SORTED) PT_TRY(check_tiled_np(np));
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos_in || !pos_out) return PT_ERR_NULL;
+  if (pos_out != pos_in && pos_out < pos_in + 3 * np && pos_in < pos_out + 3 * np)
+    return PT_ERR_ARG;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_RK2, grid, dtype, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  Rk2Ws w = carve_rk2(grid, np, dtype, ws);
+  if (sort == PT_SORTED && tiled(dtype)) {
+    PT_TRY(presorted_table(grid, np, pos_in, w.lstart, stream));
+    return tile_rk2_fwd(grid, coeff, dtype, w.lstart, np, dt, pos_in, pos_out, w.defer,
+                        w.items, true, stream);
+  }
+  return rk2_advance(grid, coeff, dtype, np, dt, pos_in, pos_out, w.u0, stream);
+}
+
 pt_status pt_rk2_stage1(const pt_grid* grid, const void* coeff_n, pt_dtype dtype, int64_t np,
                         double* pos, int32_t* ids, int sort, void* u_n, void* ws,
                         size_t ws_bytes, hipStream_t stream) {

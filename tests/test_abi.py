@@ -143,6 +143,25 @@ def test_invalid_arguments_rejected_before_launch(b):
              None) == b.PT_OK
 
 
+def test_step_out_arguments(b):
+    """pt_rk2_step_out: PT_SORT, overlapping (but not identical) buffers, a
+    null output, a short workspace and too many sorted particles are refused
+    before any launch; no particles is a no-op."""
+    L = b.LIB
+    g = _g(b)
+    vp = ctypes.c_void_p
+    fake, near = vp(0x1000), vp(0x1008)
+    f = L.pt_rk2_step_out
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, fake, b.PT_SORT, fake, 1 << 40, None) == b.PT_ERR_ARG
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, near, b.PT_SORTED, fake, 1 << 40, None) == b.PT_ERR_ARG
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, None, b.PT_SORTED, fake, 1 << 40, None) == b.PT_ERR_NULL
+    assert f(ctypes.byref(g), fake, 0, 10, float("nan"), fake, fake, 0, fake, 1 << 40, None) == b.PT_ERR_ARG
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, fake, b.PT_SORTED, fake, 8, None) == b.PT_ERR_WORKSPACE
+    assert f(ctypes.byref(g), fake, 0, 1 << 30, 0.1, fake, vp(0x1000 + (24 << 30)), b.PT_SORTED,
+             fake, 1 << 62, None) == b.PT_ERR_UNSUPPORTED
+    assert f(ctypes.byref(g), fake, 0, 0, 0.1, None, None, b.PT_SORTED, None, 0, None) == b.PT_OK
+
+
 def test_f64_workspaces_hold_fp64_values(b):
     """FP64 storage keeps velocities in FP64: its RK2 and inertial
     workspaces are larger than the FP32 ones by the 12 extra bytes per value

@@ -53,6 +53,31 @@ def test_presorted_step_and_adjoint(pt, shape, np_, clustered, cfl, in_order):
     assert pt.last_device_error() == 0
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("in_order", [True, False])
+def test_step_out_matches_the_step_in_place(pt, dtype, in_order):
+    """pt_rk2_step_out (pos_in -> pos_out, and with pos_out = pos_in) gives
+    the in-place pt_rk2_step bit for bit, for particles in cell order
+    (PT_SORTED) and in any order (PT_UNSORTED), and leaves pos_in alone."""
+    import torch
+    g, og, coeff, _, pos, dt = _setup(pt, (48, 40, 56), 20000, True, 1.0)
+    if dtype == "f64":
+        coeff = pt.spline_coeffs(g, dev(field_for(48, 40, 56, seed=3), torch.float32),
+                                 torch.float64)
+    if in_order:
+        pos, _, _ = oracle.sort_particles(og, pos, 32, 32)
+    for sort in (pt.PT_SORTED, pt.PT_UNSORTED):
+        ref = pt.rk2_step(g, coeff, dev(pos), dt, sort=sort)
+        pin = dev(pos)
+        out = pt.rk2_step_out(g, coeff, pin, dt, sort=sort)
+        assert torch.equal(out, ref), sort
+        assert torch.equal(pin, dev(pos))
+        same = dev(pos)
+        pt.rk2_step_out(g, coeff, same, dt, pos_out=same, sort=sort)
+        assert torch.equal(same, ref), sort
+    assert pt.last_device_error() == 0
+
+
 def test_presorted_matches_the_sorting_call(pt):
     """The same particles through PT_SORT and, sorted beforehand, through
     PT_SORTED: identical positions (the kernels' arithmetic is the same)."""
