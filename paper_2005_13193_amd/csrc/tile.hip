@@ -249,15 +249,6 @@ enum {
 
 __device__ __forceinline__ int gslot(int P) { return (P + kGRing) % kGRing; }
 
-template <typename CT>
-__device__ __forceinline__ float ring_val(const uint32_t* w);
-template <>
-__device__ __forceinline__ float ring_val<float>(const uint32_t* w) { return __uint_as_float(*w); }
-template <>
-__device__ __forceinline__ float ring_val<uint16_t>(const uint32_t* w) {
-  return __uint_as_float(*w << 16);
-}
-
 // Value (GRAD: and gradient) at a resident point; every lane of the quad
 // returns the full result.  Lane k of the quad takes plane k of the 4x4x4
 // stencil and reads its 12 x-runs of 4 words (3 components x 4 rows) as word
@@ -285,8 +276,8 @@ __device__ __forceinline__ void eval_ring(const uint32_t* ring, const GridDev& g
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t* r = base + comp * kGComp + j * kGTW;
-      const float v0 = ring_val<CT>(r), v1 = ring_val<CT>(r + 1);
-      const float v2 = ring_val<CT>(r + 2), v3 = ring_val<CT>(r + 3);
+      const float v0 = __uint_as_float(r[0]), v1 = __uint_as_float(r[1]);
+      const float v2 = __uint_as_float(r[2]), v3 = __uint_as_float(r[3]);
       const float sx = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
       A += wy[j] * sx;
       if (GRAD) {
@@ -589,15 +580,20 @@ __device__ __forceinline__ bool next_item(const TileArgs& a, int* range_k, int* 
 
 // Loader side: per lane the in-plane offsets of its chunks (same for every
 // plane and component), then one direct-to-LDS load per chunk.
+// BF16 values are copied as 2-byte values into the low halves of 32-bit ring
+// words (half the HBM bytes of FP32), then widened in place to FP32 words by
+// the loader lane that copied them, once they have arrived: the compute waves
+// always read FP32 words and pay no conversion per read.
 template <typename CT>
 struct RingLoader {
   static constexpr int kCopies = 3 * kGChunksPerLoader;  // direct-to-LDS copies per plane
   int rel[kGChunksPerLoader];
   bool act[kGChunksPerLoader];
-  int chunk0;
+  int chunk0, lane;
 
-  __device__ __forceinline__ void init(const GridDev& g, int X0, int Y0, int loader, int lane) {
+  __device__ __forceinline__ void init(const GridDev& g, int X0, int Y0, int loader, int l) {
     chunk0 = loader;
+    lane = l;
 #pragma unroll
     for (int m = 0; m < kGChunksPerLoader; ++m) {
       const int c = loader + kLoaders * m;
@@ -625,6 +621,24 @@ struct RingLoader {
           auto* dst = (__attribute__((address_space(3))) void*)(slot + comp * kGComp + 64 * c);
           if constexpr (sizeof(CT) == 4) __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
           else __builtin_amdgcn_global_load_lds(src, dst, 2, 0, 0);
+        }
+      }
+    }
+  }
+
+  // BF16: plane P's words of this lane, copied and arrived, to FP32 words.
+  __device__ __forceinline__ void widen(uint32_t* ring, int P) const {
+    if constexpr (sizeof(CT) == 2) {
+      uint32_t* slot = ring + gslot(P) * kGSlot;
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+#pragma unroll
+        for (int m = 0; m < kGChunksPerLoader; ++m) {
+          const int c = chunk0 + kLoaders * m;
+          if (c < kGChunks && act[m]) {
+            uint32_t* w = slot + comp * kGComp + 64 * c + lane;
+            *w = *w << 16;
+          }
         }
       }
     }
@@ -675,6 +689,7 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
     rl.init(g, X0, Y0, wave - kCompute / 64, threadIdx.x & 63);
     for (int P = z0 - 1; P <= z0 + 7; ++P) rl.load(coeff, g, ring, P);
     PT_WAIT_VMCNT(2 * RingLoader<CT>::kCopies);  // planes z0-1 .. z0+5 are in
+    for (int P = z0 - 1; P <= z0 + 5; ++P) rl.widen(ring, P);
   } else {
     for (int i = threadIdx.x; i <= nl; i += kCompute) lst[i] = ls[2 * i];
   }
@@ -709,6 +724,8 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
           rl.load(coeff, g, ring, zs + 8);
           rl.load(coeff, g, ring, zs + 9);
           PT_WAIT_VMCNT(2 * RingLoader<CT>::kCopies);
+          rl.widen(ring, zs + 6);
+          rl.widen(ring, zs + 7);
         } else {
           const int64_t pb = lst[zs - z0];
           const int64_t pe = lst[min(zs + kSlab, z1) - z0];
