@@ -159,7 +159,8 @@ __device__ __forceinline__ Pt locate_quad(const LaneAxis& ax, double xd, int X0,
   q.t[1] = quad_bcast<1>(tf);
   q.t[2] = quad_bcast<2>(tf);
   const int lx = q.a - X0, ly = q.b - Y0;
-  q.in_ring = lx >= 0 && lx < kTileX && ly >= 0 && ly < kTileY && q.c >= zlo && q.c <= zhi;
+  q.in_ring =
+      lx >= 0 && lx < kTileX + 2 && ly >= 0 && ly < kTileY + 2 && q.c >= zlo && q.c <= zhi;
   return q;
 }
 
@@ -211,16 +212,19 @@ __device__ __forceinline__ void eval_global(const CT* __restrict__ coeff, const 
 }
 
 // ------------------------------------------------------- gather kernels ---
-// The gather ring holds kGRing dense planes [3][kTileY+3][kTileX+3] of 32-bit
-// words (FP32 values, or BF16 bits in the low half).  Four loader waves fill
+// The gather ring holds kGRing dense planes [3][kTileY+5][kTileX+5] of 32-bit
+// words (FP32 values; BF16 values widened on arrival).  Four loader waves fill
 // it with direct global-to-LDS loads; eight compute waves only read it.  The
 // load queue of a wave retires in order, so keeping the plane loads in waves
 // of their own means the compute waves never wait on them, and the loaders
 // wait for exactly their own loads before the barrier that publishes them.
-constexpr int kGRing = 11;  // planes zs-1 .. zs+5 in use, zs+6 .. zs+9 in flight
-constexpr int kGTW = kTileX + 3, kGTH = kTileY + 3;
-constexpr int kGComp = kGTW * kGTH;            // 1225 words per component
-constexpr int kGSlot = 3 * kGComp + 13;        // slot pitch (words), 40 mod 64
+// A one-cell margin around the column, so that predictor points that moved
+// one cell out of it still find their stencil in the ring: 9 slots, planes
+// zs-1 .. zs+5 in use and zs+6, zs+7 in flight during slab zs.
+constexpr int kGRing = 9;
+constexpr int kGTW = kTileX + 5, kGTH = kTileY + 5;
+constexpr int kGComp = kGTW * kGTH;            // 1369 words per component
+constexpr int kGSlot = 3 * kGComp + 29;        // slot pitch (words), 40 mod 64
 static_assert(kGSlot % 64 == 40, "planes of one stencil in distinct LDS banks");
 constexpr int kCompute = 512;                  // compute threads (8 waves)
 // Loader waves: a wave has at most 63 memory operations in flight, so the
@@ -601,7 +605,9 @@ struct RingLoader {
       act[m] = c < kGChunks && r < kGComp;
       const int rr = min(r, kGComp - 1);
       const int y = rr / kGTW, x = rr - y * kGTW;
-      const int X = min(X0 + x, g.px - 1), Y = min(Y0 + y, g.py - 1);
+      // ring words outside the padded grid (the margin of the first and last
+      // columns) are never read by a cell of the grid: any valid address
+      const int X = min(max(X0 + x, 0), g.px - 1), Y = min(max(Y0 + y, 0), g.py - 1);
       rel[m] = Y * g.px + X;
     }
   }
@@ -679,7 +685,7 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
   int col, half_unused, z0, z1, range_k = 0;
   while (next_item(a, &range_k, &col, &half_unused, &z0, &z1)) {
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
-  const int X0 = cx * kTileX, Y0 = cy * kTileY;
+  const int X0 = cx * kTileX - 1, Y0 = cy * kTileY - 1;  // ring origin: one-cell margin
   const int nl = z1 - z0;
   const int32_t* ls = a.lstart + 2 * ((int64_t)col * g.nz + z0);
   const CT* coeff = (const CT*)a.coeff;
@@ -687,8 +693,8 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
   RingLoader<CT> rl;
   if (loader) {
     rl.init(g, X0, Y0, wave - kCompute / 64, threadIdx.x & 63);
-    for (int P = z0 - 1; P <= z0 + 7; ++P) rl.load(coeff, g, ring, P);
-    PT_WAIT_VMCNT(2 * RingLoader<CT>::kCopies);  // planes z0-1 .. z0+5 are in
+    for (int P = z0 - 1; P <= z0 + 5; ++P) rl.load(coeff, g, ring, P);
+    PT_WAIT_VMCNT0();  // planes z0-1 .. z0+5 are in
     for (int P = z0 - 1; P <= z0 + 5; ++P) rl.widen(ring, P);
   } else {
     for (int i = threadIdx.x; i <= nl; i += kCompute) lst[i] = ls[2 * i];
@@ -718,12 +724,11 @@ __global__ __launch_bounds__(kGTB) void tile_gather(TileArgs a) {
       const int zs = z0 + s * kSlab;
       if (zs < z1) {
         if (loader) {
-          // planes of the slab after next go into the slots of zs-3, zs-2
-          // (free since the previous step); wait for the ones of the next
-          // slab, issued one step ago
-          rl.load(coeff, g, ring, zs + 8);
-          rl.load(coeff, g, ring, zs + 9);
-          PT_WAIT_VMCNT(2 * RingLoader<CT>::kCopies);
+          // the planes the next slab adds go into the slots of zs-3, zs-2
+          // (free since the previous step) while this slab is evaluated
+          rl.load(coeff, g, ring, zs + 6);
+          rl.load(coeff, g, ring, zs + 7);
+          PT_WAIT_VMCNT0();
           rl.widen(ring, zs + 6);
           rl.widen(ring, zs + 7);
         } else {
