@@ -128,7 +128,9 @@ def test_spline_coeffs_parity(pt, shape, dtype):
 
 @pytest.mark.parametrize("shape,np_", [((32, 32, 32), 4096), ((64, 64, 64), 20011),
                                        ((45, 37, 20), 3001), ((2048, 2048, 2048), 50000),
-                                       ((4, 4, 4), 1), ((1024, 1024, 1024), 70000)])
+                                       ((4, 4, 4), 1), ((1024, 1024, 1024), 70000),
+                                       ((256, 256, 256), 300007),
+                                       ((1024, 1024, 1024), (1 << 20) + 333)])
 def test_sort_bit_exact(pt, shape, np_):
     nx, ny, nz = shape
     g = pt.Grid(nx, ny, nz)
