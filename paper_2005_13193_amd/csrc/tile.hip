@@ -1186,12 +1186,70 @@ __device__ __forceinline__ float fixed_to_float(long long acc, float inv_scale) 
   return fmaf(hi, 4294967296.0f, lo) * inv_scale;
 }
 
+// The plane flush at a slab's end is a read-modify-write of the gradient
+// without atomics: the colours keep every other workgroup of the launch off
+// these points, and this workgroup writes them only in that flush, so values
+// loaded at the slab before's end are still current, and the stores cost
+// far less than atomics.  Lanes and planes outside the padded grid load a
+// valid word they then ignore, so that every slab end issues the same loads.
+struct SPre {
+  float v[2][kSPer];
+};
+
+__device__ __forceinline__ void prefetch_splanes(const TileArgs& a, const int64_t off[kSPer],
+                                                 int P0, SPre* pre) {
+  const GridDev& g = a.g;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int P = min(max(P0 + h, 0), g.nz + 2);
+    const float* gp = a.gcoeff + (int64_t)P * g.plane;
+#pragma unroll
+    for (int q = 0; q < kSPer; ++q) pre->v[h][q] = gp[off[q] >= 0 ? off[q] : 0];
+  }
+}
+
+// Reads planes P0, P0 + 1 of the ring and clears them for reuse (all of the
+// thread's LDS reads issued before any conversion), then writes prefetched
+// value + plane sum back to the gradient.  Planes outside the padded grid
+// are skipped.
+__device__ __forceinline__ void flush_splanes_rmw(const TileArgs& a, long long* ring,
+                                                  const int64_t off[kSPer], int P0,
+                                                  float inv_scale, const SPre& pre) {
+  const GridDev& g = a.g;
+  long long acc[2][kSPer];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const long long* sl = ring + sslot(P0 + h) * kSSlot;
+#pragma unroll
+    for (int q = 0; q < kSPer; ++q)
+      acc[h][q] = sl[min((int)threadIdx.x + q * kSCompute, kSPlane - 1)];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    long long* sl = ring + sslot(P0 + h) * kSSlot;
+#pragma unroll
+    for (int q = 0; q < kSPer; ++q) {
+      const int e = threadIdx.x + q * kSCompute;
+      if (e < kSPlane) sl[e] = 0;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int P = P0 + h;
+    if (P < 0 || P >= g.nz + 3) continue;
+    float* gp = a.gcoeff + (int64_t)P * g.plane;
+#pragma unroll
+    for (int q = 0; q < kSPer; ++q)
+      if (acc[h][q] != 0 && off[q] >= 0)
+        gp[off[q]] = pre.v[h][q] + fixed_to_float(acc[h][q], inv_scale);
+  }
+}
+
 // Adds finished planes P0 .. P0 + NP - 1 of the ring to the gradient with one
-// FP32 atomic add per point (a single instruction instead of a load and a
-// store; the colours keep every other workgroup of the launch off these
-// points, so the sums are the same as a read-modify-write) and clears them
-// for reuse.  All of the thread's LDS reads are issued before any conversion
-// or global atomic.  Planes outside the padded grid are skipped.
+// FP32 atomic add per point (the planes past a work item's last slab) and
+// clears them for reuse.  All of the thread's LDS reads are issued before
+// any conversion or global atomic.  Planes outside the padded grid are
+// skipped.
 template <int NP>
 __device__ __forceinline__ void flush_splanes(const TileArgs& a, long long* ring,
                                               const int64_t off[kSPer], int P0, float inv_scale) {
@@ -1236,7 +1294,8 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   uint32_t* sdef = (uint32_t*)(sdef_n + 4);
   const GridDev& g = a.g;
   const float scale = scatter_scale(a), inv_scale = 1.0f / scale;
-  const int wave = threadIdx.x >> 6;
+  // the wave index in a scalar register: loader / compute branches are uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool loader = wave >= kSCompute / 64;
   int lerr = 0;  // a non-finite position was met
   if (threadIdx.x == 0) *sdef_n = 0;  // published by the barrier in next_item
@@ -1245,7 +1304,11 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
   const int cy = col / a.ncx, cx = col - cy * a.ncx;
   const int X0 = cx * kTileX - 1, Y0 = cy * kTileY + half * (kTileY / 2) - 1;
   int64_t foff[kSPer];
-  if (!loader) flush_offsets(g, X0, Y0, foff);
+  SPre pre;  // the gradient values of the next flush
+  if (!loader) {
+    flush_offsets(g, X0, Y0, foff);
+    prefetch_splanes(a, foff, z0 - 1, &pre);
+  }
   const int lane = threadIdx.x & (kSLanes - 1), grp = threadIdx.x / kSLanes;
   const int nl = z1 - z0;
   // starts of this half and of the next half-layer, for layers z0 .. z1
@@ -1356,8 +1419,12 @@ __global__ __launch_bounds__(kSTB) void tile_scatter(TileArgs a) {
     if (slab_end) {
       lds_barrier();
       // planes zs-1 and zs are complete: later particles sit in layers
-      // >= zs+2 and their predictor points in layers >= zs+1
-      if (!loader) flush_splanes<2>(a, ring, foff, zs - 1, inv_scale);
+      // >= zs+2 and their predictor points in layers >= zs+1.  The next
+      // slab flushes planes zs+1 and zs+2.
+      if (!loader) {
+        flush_splanes_rmw(a, ring, foff, zs - 1, inv_scale, pre);
+        prefetch_splanes(a, foff, zs + 1, &pre);
+      }
       dump_deferred(a, sdef_n, sdef, s_base, false);
     }
     lds_barrier();  // the next chunk is in LDS
