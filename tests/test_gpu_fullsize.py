@@ -26,7 +26,9 @@ full with the plain oracle.
     same points) and one sorted Heun step, sampled, and one
     device's 256-plane slab solve of the same field, sampled;
   256^3, 1M particles: L = sum |x(8)|^2 through TrackParticles (checkpoints
-    every 2 steps) against the oracle's hand adjoint, all outputs.
+    every 2 steps) against the oracle's hand adjoint, all outputs, and
+    against central finite differences of the GPU forward itself (64
+    particles, and one random direction in the field).
 """
 import sys
 
@@ -517,3 +519,65 @@ def test_c4_256_adjoint_k8(pt):
     assert abs(loss.item() - ref_loss) <= 1e-6 * ref_loss
     assert normwise(p.grad.cpu().numpy(), ref_gpos) < F32_TOL
     assert normwise(f.grad.reshape(3, -1).cpu().numpy(), ref_gfield.reshape(3, -1)) < F32_TOL
+
+
+def test_c4_256_finite_differences(pt):
+    """The differentiation workload's own check: the adjoint of
+    L = sum |x(8)|^2 (256^3 FP32 field, 1M particles, checkpoints every 2
+    steps) against central differences of the GPU forward.  Particles move
+    independently, so perturbing 64 particles at once, each along its own
+    axis, gives 64 per-particle derivatives d|x_i(8)|^2 / dx_i(0) from two
+    forward runs; the field gradient is checked along one smooth random
+    direction (a spectral field with k <= 20, max 1).  Step sizes sit well
+    above what FP32 velocities resolve (1e-4 of a position, a field change
+    of 3e-2 at most against values of order 1) and small enough for the
+    central difference's O(eps^2) term (measured: a white-noise direction,
+    whose spline wiggles at the grid scale, needs steps near 3e-3 and then
+    agrees to 1e-3; the smooth one agrees to 1e-5 at 3e-2)."""
+    import torch
+    from paper_2005_13193_amd.autograd import TrackParticles
+    n, np_, kmax, K = 256, 2 ** 20, 85, 8
+    dev = torch.device("cuda:0")
+    g = pt.Grid(n)
+    field = synth.spectral_field_torch(n, kmax, seed=0, device=dev)
+    dt = synth.cfl_dt(max_abs(field), n)
+    pos0 = synth.uniform_particles_torch(np_, seed=1, device=dev)
+    f = field.clone().requires_grad_(True)
+    p = pos0.clone().requires_grad_(True)
+    pos_k, _ids = TrackParticles.apply(f, p, g, dt, K)
+    (pos_k * pos_k).sum().backward()
+    assert pt.last_device_error() == 0
+    gpos = p.grad.detach()
+    gfield = f.grad.detach()
+
+    def final_sq(fld, pp):
+        """|x_i(8)|^2 of every particle, in the input order."""
+        with torch.no_grad():
+            xk, idk = TrackParticles.apply(fld, pp.contiguous(), g, dt, K)
+        sq = torch.empty(np_, dtype=torch.float64, device=dev)
+        sq[idk.long()] = (xk * xk).sum(0)
+        return sq
+
+    rng = np.random.default_rng(64)
+    idx = rng.choice(np_, 64, replace=False)
+    axis = rng.integers(0, 3, 64)
+    eps = 1e-4
+    dp = torch.zeros_like(pos0)
+    dp[torch.from_numpy(axis).to(dev), torch.from_numpy(idx).to(dev)] = eps
+    sp, sm = final_sq(field, pos0 + dp), final_sq(field, pos0 - dp)
+    fd = ((sp - sm) / (2 * eps))[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    ad = gpos[torch.from_numpy(axis).to(dev), torch.from_numpy(idx).to(dev)].cpu().numpy()
+    err_p = np.max(np.abs(fd - ad) / np.maximum(1.0, np.abs(ad)))
+    log(f"c4: finite differences at 64 particles, max rel error {err_p:.3e}")
+    assert err_p < 1e-3, err_p
+
+    dirn = synth.spectral_field_torch(n, 20, seed=7, device=dev)
+    dirn = dirn / max_abs(dirn)
+    eps_f = 3e-2
+    lp = final_sq(field + eps_f * dirn, pos0).sum().item()
+    lm = final_sq(field - eps_f * dirn, pos0).sum().item()
+    fd_f = (lp - lm) / (2 * eps_f)
+    ad_f = float((gfield.double() * dirn.double()).sum())
+    err_f = abs(fd_f - ad_f) / abs(ad_f)
+    log(f"c4: field direction: finite difference {fd_f:.6e}, adjoint {ad_f:.6e}, rel {err_f:.3e}")
+    assert err_f < 5e-4, (fd_f, ad_f)
