@@ -923,9 +923,10 @@ constexpr int kSRing = 7;
 // stages of each particle (FP64 positions, one lane per particle) and leave a
 // ready-to-scatter record per particle in LDS; the compute waves only form
 // the weights and add the contributions.  The compute waves then issue no
-// global loads at all: a load into registers that a later pass reuses makes
-// the compiler wait for every memory operation in flight (the flush's atomics
-// included) before issuing it, a full memory round trip per pass.
+// global loads in their passes (only, at a slab's end, those of the next
+// flush's gradient values): a load into registers that a later pass reuses
+// makes the compiler wait for every memory operation in flight before
+// issuing it, a full memory round trip per pass.
 constexpr int kSCompute = 512;             // compute threads (8 waves)
 constexpr int kSLoaders = 2;               // loader waves
 constexpr int kSTB = kSCompute + 64 * kSLoaders;
@@ -990,7 +991,7 @@ __device__ __forceinline__ void scatter_ring(long long* ring, uint32_t word, con
 // Stage 1 of a particle, and stage 2 with it when both points share a cell
 // (pair): one atomic per point then adds w1 s0 + w2 s1, rounded once.  About
 // half of the particles at usual Courant numbers, so it saves a good part of
-// the LDS atomics, which bound the kernel.  word: record word 0 (not
+// the LDS atomics.  word: record word 0 (not
 // kSNoRing); t1, t2: local coordinates of the two points; s0, s1: scaled
 // stage adjoints.
 template <int NK>
