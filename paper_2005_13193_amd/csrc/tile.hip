@@ -1603,13 +1603,18 @@ __device__ __forceinline__ int unit_layer_count(const int32_t* hs, int nz, int u
   return hs[b + 1] - hs[b];
 }
 
+// One wave per unit: the lanes load the unit's layer counts 64 at a time
+// (coalesced), and the greedy cut then runs over them in layer order, every
+// lane holding the same state (the counts taken with readlane), so that the
+// cuts are those of a sequential pass over the layers.
 template <bool WRITE>
 __global__ __launch_bounds__(256) void build_items(const int32_t* __restrict__ hs, int nunits,
                                                    int nz, int ncx, ItemCfg cfg,
                                                    int* __restrict__ offsets,
                                                    int4* __restrict__ items, int64_t capacity) {
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u >= nunits) return;
+  const int lane = threadIdx.x & 63;
+  const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (u >= nunits) return;  // the whole wave
   const bool sc = cfg.scatter != 0;
   if (!sc) {
     // gather: the layers of one z-block of one column
@@ -1619,55 +1624,59 @@ __global__ __launch_bounds__(256) void build_items(const int32_t* __restrict__ h
     int n = 0, z0 = zs, acc = 0;
     const int o = WRITE ? offsets[u] : 0;
     if (real) {
-      for (int z = zs; z < ze; ++z) {
-        const int c = unit_layer_count(hs, nz, col, z, false);
-        if (z > z0 && z - z0 >= cfg.lmin && acc + c > cfg.pmax) {
-          if (WRITE && o + n < capacity) items[o + n] = make_int4(col, 0, z0, z);
-          ++n;
-          z0 = z;
-          acc = 0;
+      for (int zc = zs; zc < ze; zc += 64) {
+        const int cl = zc + lane < ze ? unit_layer_count(hs, nz, col, zc + lane, false) : 0;
+        const int m = min(64, ze - zc);
+        for (int jj = 0; jj < m; ++jj) {
+          const int z = zc + jj;
+          const int c = __builtin_amdgcn_readlane(cl, jj);
+          if (z > z0 && z - z0 >= cfg.lmin && acc + c > cfg.pmax) {
+            if (WRITE && lane == 0 && o + n < capacity) items[o + n] = make_int4(col, 0, z0, z);
+            ++n;
+            z0 = z;
+            acc = 0;
+          }
+          acc += c;
         }
-        acc += c;
       }
-      if (WRITE && o + n < capacity) items[o + n] = make_int4(col, 0, z0, ze);
+      if (WRITE && lane == 0 && o + n < capacity) items[o + n] = make_int4(col, 0, z0, ze);
       ++n;
     }
-    if (!WRITE) offsets[u] = n;
+    if (!WRITE && lane == 0) offsets[u] = n;
     return;
   }
   const int col = u >> 1, half = u & 1;
   const int cx = col % ncx, hy = 2 * (col / ncx) + half;
-  const int base = sc ? ((cx & 1) | ((hy & 1) << 1)) : 0;
+  const int base = (cx & 1) | ((hy & 1) << 1);
   int n_even = 0, n_odd = 0, k = 0, z0 = 0, acc = 0;
   const int o_even = WRITE ? offsets[base * nunits + u] : 0;
-  const int o_odd = WRITE && sc ? offsets[(base | 4) * nunits + u] : 0;
+  const int o_odd = WRITE ? offsets[(base | 4) * nunits + u] : 0;
   auto emit = [&](int za, int zb) {
-    const bool odd = sc && (k & 1);
+    const bool odd = k & 1;
     const int at = odd ? o_odd + n_odd : o_even + n_even;
-    if (WRITE && at < capacity) items[at] = make_int4(col, half, za, zb);
+    if (WRITE && lane == 0 && at < capacity) items[at] = make_int4(col, half, za, zb);
     if (odd) ++n_odd;
     else ++n_even;
     ++k;
   };
-  for (int z = 0; z < nz; ++z) {
-    const int c = unit_layer_count(hs, nz, u, z, sc);
-    const int len = z - z0;
-    if (len > 0 && (len >= cfg.lmax || (len >= cfg.lmin && acc + c > cfg.pmax))) {
-      emit(z0, z);
-      z0 = z;
-      acc = 0;
+  for (int zc = 0; zc < nz; zc += 64) {
+    const int cl = zc + lane < nz ? unit_layer_count(hs, nz, u, zc + lane, true) : 0;
+    const int m = min(64, nz - zc);
+    for (int jj = 0; jj < m; ++jj) {
+      const int z = zc + jj;
+      const int c = __builtin_amdgcn_readlane(cl, jj);
+      const int len = z - z0;
+      if (len > 0 && (len >= cfg.lmax || (len >= cfg.lmin && acc + c > cfg.pmax))) {
+        emit(z0, z);
+        z0 = z;
+        acc = 0;
+      }
+      acc += c;
     }
-    acc += c;
   }
   emit(z0, nz);
-  if (!WRITE) {
-    if (sc) {
-      for (int cc = 0; cc < 8; ++cc)
-        offsets[cc * nunits + u] = cc == base ? n_even : cc == (base | 4) ? n_odd : 0;
-    } else {
-      offsets[u] = n_even;
-    }
-  }
+  if (!WRITE && lane < 8)
+    offsets[lane * nunits + u] = lane == base ? n_even : lane == (base | 4) ? n_odd : 0;
 }
 
 // Exclusive scan of n counts in one workgroup; range[c] = first item of
@@ -1815,7 +1824,7 @@ static pt_status build_tile_items(const pt_grid* g, int64_t np, const int32_t* h
   int* ctr = (int*)(p + 64);  // [8 colours][8 XCD ranges]
   int* offsets = (int*)(p + kItemsHeader);
   int4* items = (int4*)(p + kItemsHeader + 4 * (size_t)(8 * nunits));
-  const unsigned blocks = (unsigned)((nunits + 255) / 256);
+  const unsigned blocks = (unsigned)((nunits + 3) / 4);  // a wave per unit
   const int64_t bound = scatter ? item_bound(nunits, g->nz, np, lmax)
                                 : nunits + 2 * ((np + kItemPmax - 1) / kItemPmax) + 8;
   hipLaunchKernelGGL(build_items<false>, dim3(blocks), dim3(256), 0, s, hs, nunits, g->nz, ncx,
