@@ -1,7 +1,8 @@
 // Particle ordering by spline cell (the one-device counterpart of the
 // position-based particle-to-process mapping of Sec. 3): cell keys in FP64,
 // a stable least-significant-digit radix sort of (key, index) with 8-bit
-// digits, and the permutation of the particle arrays.
+// digits (a lone top bit joins the last digit: 33-bit keys take passes of 8,
+// 8, 8 and 9 bits), and the permutation of the particle arrays.
 //
 // Radix pass structure: the input is cut into block tiles of kSortTile
 // consecutive elements (8 waves x 16 rounds x 64 lanes).  A histogram kernel
@@ -10,7 +11,7 @@
 // kernel re-reads each tile, ranks equal digits in input order (wave ballots
 // within a round, running per-wave counts across rounds, wave prefixes
 // across the tile), reorders the tile by digit in LDS, and writes each
-// digit's run contiguously (about 32 elements per digit and tile).
+// digit's run contiguously (about 32 elements per 8-bit digit and tile).
 #include <hip/hip_runtime.h>
 
 #include "pt_common.h"
@@ -85,12 +86,13 @@ __global__ __launch_bounds__(256) void sorted_layer_table(GridDev g, int64_t np,
   for (int64_t L = lprev + 1; L <= lcur && L <= nlayers; ++L) ls[L] = (int32_t)i;
 }
 
-// Lanes holding the same 8-bit digit: AND of the ballots of each bit (or of
+// Lanes holding the same DB-bit digit: AND of the ballots of each bit (or of
 // their complements), restricted to the valid lanes.
+template <int DB>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
   uint64_t peers = valid;
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < DB; ++b) {
     const int bit = (d >> b) & 1;
     const uint64_t bal = __ballot(bit);
     peers &= bit ? bal : ~bal;
@@ -99,14 +101,15 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
 }
 
 // Digit counts of one tile: counts[d * ntiles + tile].
-template <typename K>
+template <typename K, int DB>
 __global__ __launch_bounds__(kSortThreads) void radix_hist(const K* __restrict__ keys, int64_t n,
                                                            int shift,
                                                            uint32_t* __restrict__ counts,
                                                            int64_t ntiles) {
-  __shared__ uint32_t h[kSortWaves][256];
+  constexpr int kBins = 1 << DB;
+  __shared__ uint32_t h[kSortWaves][kBins];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int i = lane; i < 256; i += 64) h[wave][i] = 0;
+  for (int i = lane; i < kBins; i += 64) h[wave][i] = 0;
   const int64_t tile = blockIdx.x;
   const int64_t base = tile * kSortTile + (int64_t)wave * kWaveItems;
   const uint64_t lt = (1ull << lane) - 1;
@@ -114,43 +117,57 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist(const K* __restrict__
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     const int64_t idx = base + r * 64 + lane;
-    d[r] = idx < n ? (uint32_t)((keys[idx] >> shift) & 255) : 256u;
+    d[r] = idx < n ? (uint32_t)((keys[idx] >> shift) & (kBins - 1)) : (uint32_t)kBins;
   }
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
-    const bool ok = d[r] < 256u;
-    const uint64_t peers = match_digit(d[r] & 255u, __ballot(ok));
+    const bool ok = d[r] < (uint32_t)kBins;
+    const uint64_t peers = match_digit<DB>(d[r] & (kBins - 1), __ballot(ok));
     if (ok && (peers & lt) == 0) h[wave][d[r]] += (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  if (tid < 256) {
+  for (int dd = tid; dd < kBins; dd += kSortThreads) {
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < kSortWaves; ++w) c += h[w][tid];
-    counts[(int64_t)tid * ntiles + tile] = c;
+    for (int w = 0; w < kSortWaves; ++w) c += h[w][dd];
+    counts[(int64_t)dd * ntiles + tile] = c;
   }
 }
 
+// LDS of the scatter kernel: the tile's keys and values, per-wave digit
+// counts, per digit its start in the reordered tile and its global offset,
+// and the wave sums of the digit scan.
+template <typename K, int DB>
+constexpr size_t radix_scatter_lds() {
+  return (size_t)kSortTile * (sizeof(K) + 4) +
+         4 * ((size_t)kSortWaves * (1 << DB) + 2 * (size_t)(1 << DB) + kSortWaves);
+}
+
 // Stable scatter of one tile to the offsets of the scanned count table.
-template <typename K>
+template <typename K, int DB>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, int64_t n, int shift, const uint32_t* __restrict__ offsets,
     int64_t ntiles) {
+  constexpr int kBins = 1 << DB;
+  // the scan over digits: a scan thread takes a contiguous run of kDpt
+  constexpr int kDpt = kBins > kSortThreads ? kBins / kSortThreads : 1;
+  constexpr int kScanThreads = kBins / kDpt;
   extern __shared__ __align__(16) unsigned char smem[];
   K* tk = (K*)smem;                                          // [kSortTile]
   uint32_t* tv = (uint32_t*)(tk + kSortTile);                // [kSortTile]
-  uint32_t* h = tv + kSortTile;                              // [kSortWaves][256]
-  uint32_t* dstart = h + kSortWaves * 256;                   // [256]
-  uint32_t* goff = dstart + 256;                             // [256]
-  uint32_t* wsum = goff + 256;                               // [4]
+  uint32_t* h = tv + kSortTile;                              // [kSortWaves][kBins]
+  uint32_t* dstart = h + kSortWaves * kBins;                 // [kBins]
+  uint32_t* goff = dstart + kBins;                           // [kBins]
+  uint32_t* wsum = goff + kBins;                             // [kSortWaves]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t tile = blockIdx.x;
   const int64_t tbase = tile * kSortTile;
   const int tile_n = (int)min((int64_t)kSortTile, n - tbase);
   const int64_t base = tbase + (int64_t)wave * kWaveItems;
-  for (int i = lane; i < 256; i += 64) h[wave * 256 + i] = 0;
-  if (tid < 256) goff[tid] = offsets[(int64_t)tid * ntiles + tile];
+  for (int i = lane; i < kBins; i += 64) h[wave * kBins + i] = 0;
+  for (int dd = tid; dd < kBins; dd += kSortThreads)
+    goff[dd] = offsets[(int64_t)dd * ntiles + tile];
 
   K k[kSortRounds];
   uint32_t v[kSortRounds];
@@ -167,38 +184,49 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     const bool ok = base + r * 64 + lane < n;
-    const uint32_t d = (uint32_t)((k[r] >> shift) & 255);
-    const uint64_t peers = match_digit(d, __ballot(ok));
-    const uint32_t start = ok ? h[wave * 256 + d] : 0u;
+    const uint32_t d = (uint32_t)((k[r] >> shift) & (kBins - 1));
+    const uint64_t peers = match_digit<DB>(d, __ballot(ok));
+    const uint32_t start = ok ? h[wave * kBins + d] : 0u;
     dr[r] = (d << 16) | (start + (uint32_t)__popcll(peers & lt));
     // the lowest lane of each digit group advances the running count; its
     // new value depends on the value it read, so the read completes first
-    if (ok && (peers & lt) == 0) h[wave * 256 + d] = start + (uint32_t)__popcll(peers);
+    if (ok && (peers & lt) == 0) h[wave * kBins + d] = start + (uint32_t)__popcll(peers);
   }
   __syncthreads();
   // per digit: exclusive prefixes over the waves, then over the digits
-  if (tid < 256) {
-    uint32_t run = 0;
+  uint32_t tot[kDpt];
+  uint32_t mine = 0;
+  if (tid < kScanThreads) {
 #pragma unroll
-    for (int w = 0; w < kSortWaves; ++w) {
-      const uint32_t c = h[w * 256 + tid];
-      h[w * 256 + tid] = run;
-      run += c;
-    }
-    uint32_t incl = run;
+    for (int q = 0; q < kDpt; ++q) {
+      const int dd = tid * kDpt + q;
+      uint32_t run = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
+      for (int w = 0; w < kSortWaves; ++w) {
+        const uint32_t c = h[w * kBins + dd];
+        h[w * kBins + dd] = run;
+        run += c;
+      }
+      tot[q] = run;
+      mine += run;
     }
-    if (lane == 63) wsum[wave] = incl;
-    dstart[tid] = incl - run;  // exclusive within the wave for now
   }
+  uint32_t incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wave] = incl;
   __syncthreads();
-  if (tid < 256) {
-    uint32_t woff = 0;
-    for (int w = 0; w < wave; ++w) woff += wsum[w];
-    dstart[tid] += woff;
+  if (tid < kScanThreads) {
+    uint32_t off = incl - mine;  // exclusive within the wave
+    for (int w = 0; w < wave; ++w) off += wsum[w];
+#pragma unroll
+    for (int q = 0; q < kDpt; ++q) {
+      dstart[tid * kDpt + q] = off;
+      off += tot[q];
+    }
   }
   __syncthreads();
   // reorder the tile by digit in LDS
@@ -206,7 +234,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(
   for (int r = 0; r < kSortRounds; ++r) {
     if (base + r * 64 + lane < n) {
       const uint32_t d = dr[r] >> 16;
-      const uint32_t lp = dstart[d] + h[wave * 256 + d] + (dr[r] & 0xffffu);
+      const uint32_t lp = dstart[d] + h[wave * kBins + d] + (dr[r] & 0xffffu);
       tk[lp] = k[r];
       tv[lp] = v[r];
     }
@@ -218,7 +246,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(
     const int i = r * kSortThreads + tid;
     if (i < tile_n) {
       const K key = tk[i];
-      const uint32_t d = (uint32_t)((key >> shift) & 255);
+      const uint32_t d = (uint32_t)((key >> shift) & (kBins - 1));
       const uint32_t dst = goff[d] + ((uint32_t)i - dstart[d]);
       if (dst < (uint64_t)n) {  // always true for consistent counts; guards the store
         kout[dst] = key;
@@ -362,9 +390,23 @@ struct SortWs {
 
 static int64_t sort_tiles(int64_t np) { return (np + kSortTile - 1) / kSortTile; }
 
+// Digits of the radix passes: 8 bits each; a lone top bit (bits % 8 == 1,
+// bits > 8) joins the last digit, which then has 9 bits (one pass fewer).
+static int sort_passes(int bits, int* last_db) {
+  const int passes = (bits + 7) / 8;
+  if (passes > 1 && bits % 8 == 1) {
+    *last_db = 9;
+    return passes - 1;
+  }
+  *last_db = 8;
+  return passes;
+}
+
 size_t sort_ws_bytes(const pt_grid* g, int64_t np) {
   const size_t kb = key_bits(g) > 32 ? 8 : 4;
-  const size_t ncount = (size_t)sort_tiles(np) * 256;
+  int last_db = 8;
+  sort_passes(key_bits(g), &last_db);
+  const size_t ncount = (size_t)sort_tiles(np) << last_db;
   return 2 * align256(kb * (size_t)np) + align256(4 * (size_t)np) + align256(4 * ncount) +
          align256(4 * scan_scratch_words((int64_t)ncount));
 }
@@ -377,7 +419,9 @@ static SortWs carve_sort_ws(const pt_grid* g, int64_t np, void* ws) {
   w.keys[0] = p; p += align256(kb * (size_t)np);
   w.keys[1] = p; p += align256(kb * (size_t)np);
   w.vals0 = (uint32_t*)p; p += align256(4 * (size_t)np);
-  w.counts = (uint32_t*)p; p += align256(4 * (size_t)nt * 256);
+  int last_db = 8;
+  sort_passes(key_bits(g), &last_db);
+  w.counts = (uint32_t*)p; p += align256(4 * ((size_t)nt << last_db));
   w.scan = (uint32_t*)p;
   return w;
 }
@@ -385,18 +429,38 @@ static SortWs carve_sort_ws(const pt_grid* g, int64_t np, void* ws) {
 pt_status build_layer_table(const pt_grid* g, int64_t np, const void* keys, int key_bytes,
                             int32_t* ls, hipStream_t s);
 
+// One radix pass of DB-bit digits at bit `shift`, keys and values from
+// buffer src to the other.
+template <typename K, int DB>
+static pt_status radix_pass(K* const kbuf[2], uint32_t* const vbuf[2], int src, int shift,
+                            int64_t np, const SortWs& w, hipStream_t s) {
+  const int64_t nt = sort_tiles(np);
+  constexpr size_t lds = radix_scatter_lds<K, DB>();
+  static_assert(lds <= 160 * 1024, "radix_scatter LDS");
+  if (hipFuncSetAttribute((const void*)radix_scatter<K, DB>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return PT_ERR_HIP;
+  const int dst = src ^ 1;
+  TimedLaunch t("sort_pass", s);
+  hipLaunchKernelGGL((radix_hist<K, DB>), dim3((unsigned)nt), dim3(kSortThreads), 0, s,
+                     kbuf[src], np, shift, w.counts, nt);
+  PT_LAUNCH_CHECK();
+  pt_status st = exclusive_scan(w.counts, nt << DB, w.scan, s);
+  if (st != PT_OK) return st;
+  hipLaunchKernelGGL((radix_scatter<K, DB>), dim3((unsigned)nt), dim3(kSortThreads), lds, s,
+                     kbuf[src], vbuf[src], kbuf[dst], vbuf[dst], np, shift, w.counts, nt);
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
 template <typename K>
 static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int32_t* perm,
                            uint64_t* keys_out, int32_t* lstart, void* ws, hipStream_t s) {
   const GridDev gd = make_grid_dev(g);
   SortWs w = carve_sort_ws(g, np, ws);
   const int bits = key_bits(g);
-  const int passes = (bits + 7) / 8;
-  const int64_t nt = sort_tiles(np);
-  const size_t lds = (size_t)kSortTile * (sizeof(K) + 4) + 4 * (kSortWaves * 256 + 512 + 4);
-  if (hipFuncSetAttribute((const void*)radix_scatter<K>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return PT_ERR_HIP;
+  int last_db = 8;
+  const int passes = sort_passes(bits, &last_db);
   K* kbuf[2] = {(K*)w.keys[0], (K*)w.keys[1]};
   // pass i writes value buffer (passes - 1 - i) & 1: 0 = perm, 1 = scratch,
   // so that the last pass lands in perm.
@@ -411,17 +475,11 @@ static pt_status sort_impl(const pt_grid* g, int64_t np, const double* pos, int3
   PT_LAUNCH_CHECK();
   int src = src0;
   for (int p = 0; p < passes; ++p) {
-    const int dst = src ^ 1;
-    TimedLaunch t("sort_pass", s);
-    hipLaunchKernelGGL(radix_hist<K>, dim3((unsigned)nt), dim3(kSortThreads), 0, s, kbuf[src],
-                       np, 8 * p, w.counts, nt);
-    PT_LAUNCH_CHECK();
-    pt_status st = exclusive_scan(w.counts, nt * 256, w.scan, s);
+    const pt_status st = p + 1 == passes && last_db == 9
+                             ? radix_pass<K, 9>(kbuf, vbuf, src, 8 * p, np, w, s)
+                             : radix_pass<K, 8>(kbuf, vbuf, src, 8 * p, np, w, s);
     if (st != PT_OK) return st;
-    hipLaunchKernelGGL(radix_scatter<K>, dim3((unsigned)nt), dim3(kSortThreads), lds, s,
-                       kbuf[src], vbuf[src], kbuf[dst], vbuf[dst], np, 8 * p, w.counts, nt);
-    PT_LAUNCH_CHECK();
-    src = dst;
+    src ^= 1;
   }
   if (keys_out) {
     hipLaunchKernelGGL(widen_keys<K>, dim3(grid_1d(np, 256)), dim3(256), 0, s, np, kbuf[src],
