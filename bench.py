@@ -30,7 +30,10 @@ the 12-output gather of (u, v, w) and the nine velocity gradients at every
 particle (column-tiled), and the Heun step on the sorted particles.
 
 --dtype f64 runs the FP64 form of the same step (FP64 solves and gathers),
-the baseline the FP32 and BF16 forms are compared with.
+the baseline the FP32 and BF16 forms are compared with. The default run (FP32
+coefficients) also times, after its timed steps and outside them, three steps
+of the same path with BF16 and with FP64 coefficients on the same inputs
+("forms" in the JSON line).
 
     python bench.py [--steps K] [--warmup W] [--config c3] [--dtype f32|bf16|f64]
                     [--workload fwd_adjoint|tv|slab|inertial|c5] [--no-overlap]
@@ -679,6 +682,18 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] timing the 256^3 / 1M / K=8 fwd+adjoint (checkpoints every 2 steps)")
         out["c4_fwd_adjoint_k8_ms"] = c4_adjoint_time(torch, pt, synth)
+        if args.dtype == "f32":
+            # the same step with the other coefficient storages, on the same
+            # field and particles (after the timed steps, outside them)
+            out["forms"] = {}
+            for other in ("bf16", "f64"):
+                log(f"[bench] the same step with {other} coefficients")
+                ms_o = other_form_step_ms(torch, pt, B, g, field, pos, ids, dt, other)
+                out["forms"][other] = {"ms_per_step": ms_o,
+                                       "value": 2.0 * np_ / (ms_o * 1e-3),
+                                       "steps": 3, "warmup": 1,
+                                       "what": "the same fwd+adjoint step with "
+                                               f"{other} coefficients, same inputs"}
     if not args.no_cpu_baseline:
         if uvw is not None:
             log("[bench] sampled error against the FP64 oracle")
@@ -687,6 +702,50 @@ def main():
         log("[bench] timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(n, np_, clustered)
     print(json.dumps(out), flush=True)
+
+
+def other_form_step_ms(torch, pt, B, g, field, pos, ids, dt, dtype_name, steps=3):
+    """ms per fwd+adjoint step (the benchmark's step: solve, sort, Heun
+    step, its adjoint, solve adjoint) with another coefficient storage, on
+    the given field and particles; buffers of its own (x and the labels
+    included: the caller's are left as they were), freed on return."""
+    dev = pos.device
+    cdt = getattr(torch, DTYPES[dtype_name][0])
+    np_ = pos.shape[1]
+    pos, ids = pos.clone(), ids.clone()
+    coeff = torch.empty(g.padded_shape, dtype=cdt, device=dev)
+    g_coeff = torch.zeros(g.padded_shape, dtype=torch.float32, device=dev)
+    g_field = torch.empty(g.field_shape, dtype=torch.float32, device=dev)
+    pos_n = torch.empty_like(pos)
+    perm = torch.empty(np_, dtype=torch.int32, device=dev)
+    g_pos = torch.empty_like(pos)
+    ws_sp = pt.workspace(B.PT_OP_SPLINE, g, 0, cdt, dev)
+    ws_spb = pt.workspace(B.PT_OP_SPLINE_BWD, g, 0, torch.float32, dev)
+    ws_s = pt.workspace(B.PT_OP_SORT, g, np_, cdt, dev)
+    ws_f = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
+    ws_b = pt.workspace(B.PT_OP_RK2_BWD, g, np_, cdt, dev)
+
+    def step():
+        B.pt_spline_coeffs(g, field, coeff, ws_sp)
+        B.pt_sort_particles(g, pos, pos_n, perm, ids, None, ws_s)
+        B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
+        torch.mul(pos, 2.0, out=g_pos)
+        B.pt_rk2_step_bwd(g, coeff, dt, pos_n, B.PT_SORTED, g_pos, g_coeff, ws_b)
+        B.pt_spline_coeffs_bwd(g, g_coeff, g_field, ws_spb)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    status = B.pt_last_device_error()
+    if status != 0:
+        raise RuntimeError(f"device error flag set: {B.status_string(status)}")
+    del pos, ids, coeff, g_coeff, g_field, pos_n, perm, g_pos, ws_sp, ws_spb, ws_s, ws_f, ws_b
+    torch.cuda.empty_cache()
+    return ms
 
 
 def run_inertial(args, torch, pt, B, synth, n, np_, kmax, clustered, desc, cdt, cb):
