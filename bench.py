@@ -77,7 +77,8 @@ def log(*a):
 
 
 KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold",
-           "spline_y_carry", "spline_yx_pad", "sorted_table", "sort_keys",
+           "spline_y_carry", "spline_yx_pad", "spline_fold_y_carry", "spline_fyx",
+           "sorted_table", "sort_keys",
            "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter",
            "tile_tv_stage1", "tile_tv_stage2", "tile_inertial", "tile_interp", "tile_interp_grad",
            "inertial_direct", "interp", "rk2_direct_stage2", "rk2_direct_bwd",
@@ -104,6 +105,11 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step, vb=4):
         # written by the first pass and read by the second
         "spline_y_carry": 4 * n3 + 8 * n3 // 16,
         "spline_yx_pad": 4 * n3 + 8 * n3 // 16 + cb * p3,
+        # the adjoint's fused fold + y + x: carries of the folded y lines
+        # (padded gradient read, carries written), then the padded gradient
+        # and the carries read and the plain field written
+        "spline_fold_y_carry": 4 * p3 + 8 * n3 // 16,
+        "spline_fyx": 4 * p3 + 8 * n3 // 16 + 4 * n3,
         "sort_keys": np_ * (24 + kb + 4),
         "sort_pass": np_ * 2 * (kb + 4),
         "sort_permute": np_ * (4 + 24 + 24),

@@ -328,8 +328,11 @@ pt_status pt_interp_uvw_bwd(const pt_grid *grid, const void *coeff, pt_dtype dty
 
 /* Adjoint of pt_spline_coeffs.  Each padded coefficient gradient is folded
  * onto the grid line it copies, then the transposed line solves are applied
- * (the 1-4-1 periodic matrix is symmetric, so they are the same solves) in the
- * order x (fused with the fold), y, z.  g_coeff float [3][nz+3][ny+3][nx+3] in (not modified);
+ * (the 1-4-1 periodic matrix is symmetric, so they are the same solves; they
+ * commute): fold, y and x in one pass where rows have 256, 512 or 1024 points
+ * and the y lines split into whole chunks, else x (fused with the fold) and
+ * y; then z.  g_coeff float [3][nz+3][ny+3][nx+3] in (not modified; must not
+ * overlap g_field, which also holds intermediate values during the call);
  * g_field float [3][nz][ny][nx] out (overwritten). */
 pt_status pt_spline_coeffs_bwd(const pt_grid *grid, const float *g_coeff, float *g_field,
                                void *ws, size_t ws_bytes, hipStream_t stream);
@@ -414,7 +417,9 @@ const char *pt_status_string(pt_status status);
  * pass that writes the padded coefficients), "spline_x_fold" (the adjoint's
  * x pass that reads the padded gradient), "spline_y_carry" and
  * "spline_yx_pad" (the forward's fused y + x pass and the y pass that feeds
- * it its carries), "sort_keys", "sort_pass", "sort_permute",
+ * it its carries), "spline_fold_y_carry" and "spline_fyx" (the adjoint's
+ * fused fold + y + x pass and the folded y pass that feeds it its carries),
+ * "sort_keys", "sort_pass", "sort_permute",
  * "sorted_table" (the particle table of PT_SORTED), "slab_partition",
  * "tile_rk2_fwd",
  * "tile_rk2_bwd_gather", "tile_scatter", "tile_tv_stage1", "tile_tv_stage2",

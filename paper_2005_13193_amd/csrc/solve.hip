@@ -357,7 +357,50 @@ struct LineArgs {
   float* carry;   // non-null: write only the carries entering each run of
                   // 16 points, [b][na / 16][2][nx] (causal, anti-causal),
                   // for solve_yx (whole chunks of a multiple of 16 points)
+  int nbf;        // FOLD input (y lines of the padded adjoint): grid planes
 };
+
+// The fold of the adjoint: grid point (x, y, z) sums every padded copy that
+// holds it, index m + 1 along each axis plus pad_extra(m) where it exists.
+// fold_rows adds to v[i] the x copies (x + 1, and xe) of row i * stride of
+// the padded rows at p (the caller picks the y and z copies).
+template <int Q>
+__device__ __forceinline__ void fold_rows(float* v, const float* p, int64_t stride, int x,
+                                          int xe) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) v[i] += p[i * stride + x + 1];
+  if (xe >= 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] += p[i * stride + xe];
+  }
+}
+
+// Folded values of Q consecutive grid rows y0 .. y0 + Q - 1 (Q >= 3) at
+// column x of grid plane z into v, from the padded gradient in (px, py: the
+// padded row length and rows per plane; ny, nz: grid extents): the rows' own
+// padded copies, then the wrapped copies of grid rows 0, 1 and ny - 1 (only
+// i = 0, 1 and Q - 1 can hold them) and of planes 0, 1 and nz - 1.
+template <int Q>
+__device__ __forceinline__ void fold_column(float* v, const float* in, int px, int64_t py,
+                                            int nx, int ny, int nz, int x, int y0, int z) {
+  static_assert(Q >= 3, "rows 0 and 1 and the last must be distinct slots");
+  const int xe = pad_extra(x, nx), ze = pad_extra(z, nz);
+  const int64_t pl = py * px;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) v[i] = 0.0f;
+  fold_rows<Q>(v, in + (z + 1) * pl + (int64_t)(y0 + 1) * px, px, x, xe);
+  if (ze >= 0) fold_rows<Q>(v, in + ze * pl + (int64_t)(y0 + 1) * px, px, x, xe);
+  constexpr int kI[3] = {0, 1, Q - 1};
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int ye = pad_extra(y0 + kI[t], ny);
+    if (ye < 0) continue;
+    float c = 0.0f;
+    fold_rows<1>(&c, in + (z + 1) * pl + (int64_t)ye * px, 0, x, xe);
+    if (ze >= 0) fold_rows<1>(&c, in + ze * pl + (int64_t)ye * px, 0, x, xe);
+    v[kI[t]] += c;
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ T chunk_gain(const LineArgs& a, int k) {
@@ -368,24 +411,44 @@ __device__ __forceinline__ T chunk_gain(const LineArgs& a, int k) {
 // FULL: every thread of the launch holds a whole chunk of Q = L points
 // (launched only on x-blocks inside nx, with K * L = na).
 // CARRY: write only the run carries to a.carry (FULL launches only).
+// FOLD: y lines (axis A = y, B = z) of the folded padded gradient (FULL and
+// CARRY only): the carries of the adjoint's fused y + x pass.
 // TI: input type; T: arithmetic and output type (float, float or float,
 // double or double, double).
-template <int Q, bool FULL, bool CARRY = false, typename TI = float, typename T = float>
+template <int Q, bool FULL, bool CARRY = false, typename TI = float, typename T = float,
+          bool FOLD = false>
 __global__ __launch_bounds__(1024) void solve_lines(LineArgs a) {
+  static_assert(!FOLD || (FULL && CARRY && std::is_same<T, float>::value),
+                "the folded input feeds the carries-only FP32 pass");
   __shared__ T s_e[1024];
   __shared__ T s_f[1024];
   const T kGain = gainc<T>();
   const int lane = threadIdx.x & 63;
   const int xg = lane & (a.G - 1);
   const int k = (threadIdx.x >> 6) * (64 / a.G) + lane / a.G;
-  const int x = (blockIdx.x + a.bx0) * a.G + xg;
-  const int b = blockIdx.y;
+  int bx = blockIdx.x, b = blockIdx.y;
+  if constexpr (FOLD) {
+    // Padded rows start off 128-byte lines, so two neighbouring x-blocks share
+    // a line at their border.  Workgroups go to the 8 XCDs round-robin by
+    // linear index: renumbered, each XCD takes whole planes (all x-blocks of
+    // a plane at once) and fetches a shared line into its L2 once.
+    const int nbx = gridDim.x, total = nbx * gridDim.y;
+    if (total % 8 == 0) {
+      const int id = blockIdx.y * nbx + blockIdx.x;
+      const int l = (id % 8) * (total / 8) + id / 8;
+      bx = l % nbx;
+      b = l / nbx;
+    }
+  }
+  const int x = (bx + a.bx0) * a.G + xg;
   const int m0 = k * a.L;
   const int len = FULL ? Q : (x < a.nx ? min(max(a.na - m0, 0), a.L) : 0);
   const int last = max(len - 1, 0);
 
   T v[Q];
-  {
+  if constexpr (FOLD) {
+    fold_column<Q>(v, (const float*)a.in, a.nx + 3, a.na + 3, a.nx, a.na, a.nbf, x, m0, b);
+  } else {
     // clamped addresses keep every load in bounds; selects zero the rest
     const TI* in = (const TI*)a.in;
     const TI* src = len > 0 ? in + x + (int64_t)b * a.sb + (int64_t)m0 * a.sa : in;
@@ -587,6 +650,104 @@ __global__ __launch_bounds__(1024) void solve_yx(YXArgs a) {
   }
 }
 
+// ------------------------------------------ fused fold + y + x (adjoint) ---
+// The first passes of the adjoint in one read of the padded gradient and one
+// write of the plain field: the fold, the y solve and the x solve (the solves
+// commute, so y may go first).  A carries-only pass over the folded y lines
+// (solve_lines with FOLD) has stored the states entering every run of QY
+// rows; a workgroup of nx = 64 W threads takes one run of one plane: thread x
+// folds its column of the run and solves it along y in registers from the
+// stored states, and the rows go through LDS W at a time, one wave per row,
+// for the periodic x solve and contiguous plain stores.
+struct FYXArgs {
+  const float* in;     // padded gradient [nz+3][ny+3][nx+3]
+  const float* carry;  // [nz][K][2][nx] from the folded carries-only y pass
+  float* out;          // plain [nz][ny][nx]
+  int nx, ny, nz;
+  int K;               // runs per y line (QY rows each)
+  int pitch;           // LDS floats per row slot
+};
+
+template <int W, int QY>
+__global__ __launch_bounds__(1024) void solve_fyx(FYXArgs a) {
+  const float kZ1 = z1c<float>(), kGain = gainc<float>();
+  extern __shared__ float lds[];
+  constexpr int QX = W;  // x points per lane: nx = 64 W
+  const int x = threadIdx.x, lane = x & 63, wid = x >> 6;
+  const int k = blockIdx.x, z = blockIdx.y;
+  const int nx = a.nx;
+
+  float v[QY];
+  {
+    fold_column<QY>(v, a.in, nx + 3, a.ny + 3, nx, a.ny, a.nz, x, k * QY, z);
+    const float* cr = a.carry + ((int64_t)z * a.K + k) * 2 * nx + x;
+    const float cin = cr[0], din = cr[nx];
+    causal_local<QY, true>(v, QY);
+    causal_carry<QY, true>(v, QY, cin);
+    anticausal_local<QY>(v);
+    anticausal_carry<QY, true>(v, QY, din);
+  }
+
+  float* L = lds + wid * a.pitch;
+  const int m0 = lane * QX;
+#pragma unroll
+  for (int bt = 0; bt < QY / W; ++bt) {
+#pragma unroll
+    for (int r = 0; r < W; ++r) lds[r * a.pitch + lds_ix(x)] = kGain * v[bt * W + r];
+    __syncthreads();
+    const int y = k * QY + bt * W + wid;
+
+    // the periodic x solve of row (y, z), as in solve_rows
+    float u[QX];
+#pragma unroll
+    for (int i = 0; i < QX; ++i) u[i] = L[lds_ix(m0 + i)];
+    float a_len = 1.0f;
+#pragma unroll
+    for (int i = 0; i < QX; ++i) a_len *= kZ1;
+    const float e = causal_local<QX, false>(u, QX);
+    float sa = a_len, se = e;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const float pa = __shfl_up(sa, d), pe = __shfl_up(se, d);
+      if (lane >= d) {
+        se = sa * pe + se;
+        sa = sa * pa;
+      }
+    }
+    {
+      const float A = __shfl(sa, 63), B = __shfl(se, 63);
+      const float C0 = B / (1.0f - A);
+      const float pa = __shfl_up(sa, 1), pe = __shfl_up(se, 1);
+      causal_carry<QX, false>(u, QX, lane == 0 ? C0 : pa * C0 + pe);
+    }
+    const float f = anticausal_local<QX>(u);
+    sa = a_len;
+    float sf = f;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const float pa = __shfl_down(sa, d), pf = __shfl_down(sf, d);
+      if (lane + d < 64) {
+        sf = sa * pf + sf;
+        sa = sa * pa;
+      }
+    }
+    {
+      const float A = __shfl(sa, 0), B = __shfl(sf, 0);
+      const float D0 = B / (1.0f - A);
+      const float pa = __shfl_down(sa, 1), pf = __shfl_down(sf, 1);
+      anticausal_carry<QX, false>(u, QX, lane == 63 ? D0 : pa * D0 + pf);
+    }
+    // each lane writes back only its own chunk: no barrier before the writes
+#pragma unroll
+    for (int i = 0; i < QX; ++i) L[lds_ix(m0 + i)] = kGain * u[i];
+    __syncthreads();
+    float* row = a.out + ((int64_t)z * a.ny + y) * nx;
+#pragma unroll
+    for (int j = 0; j < QX; ++j) row[lane + 64 * j] = L[lds_ix(lane + 64 * j)];
+    __syncthreads();  // the slots are refilled by the next batch
+  }
+}
+
 // ------------------------------------------------------------ launchers ---
 
 template <typename F>
@@ -667,16 +828,19 @@ static bool line_shape(int na, int* Q, int* G, int* waves) {
 // first pass of an FP64 solve), FP64 in and out.
 enum { LINES_F32 = 0, LINES_F32_F64 = 1, LINES_F64 = 2 };
 
-// axis 1 = y, axis 2 = z; plain layout in and out.
+// axis 1 = y, axis 2 = z; plain layout in and out.  fold (with carry, axis
+// 1): the input is the padded adjoint, read folded.
 static pt_status pass_lines(const void* in, void* out, int nx, int ny, int nz, int axis,
                             hipStream_t s, int open = 0, float* carry = nullptr,
-                            int prec = LINES_F32) {
+                            int prec = LINES_F32, bool fold = false) {
   LineArgs a;
   a.in = in;
   a.out = out;
   a.nx = nx;
   a.open = open;
   a.carry = carry;
+  a.nbf = nz;
+  if (fold && (!carry || axis != 1 || open)) return PT_ERR_UNSUPPORTED;
   int nb;
   if (axis == 1) {
     a.na = ny; nb = nz;
@@ -704,7 +868,9 @@ static pt_status pass_lines(const void* in, void* out, int nx, int ny, int nz, i
   const int xblocks = (nx + G - 1) / G;
   const int full_x = (a.L == Q && a.K * a.L == a.na) ? nx / G : 0;
   const dim3 block(64 * waves);
-  TimedLaunch t(carry ? "spline_y_carry" : (axis == 2 ? "spline_z" : "spline_y"), s);
+  TimedLaunch t(fold ? "spline_fold_y_carry"
+                     : (carry ? "spline_y_carry" : (axis == 2 ? "spline_z" : "spline_y")),
+                s);
   if (prec != LINES_F32) {
     if (carry) return PT_ERR_UNSUPPORTED;
 #define PT_LINES64(QQ, FF, TI)                                                              \
@@ -734,6 +900,16 @@ static pt_status pass_lines(const void* in, void* out, int nx, int ny, int nz, i
   if (carry) {
     if (full_x != xblocks) return PT_ERR_UNSUPPORTED;
     a.bx0 = 0;
+    if (fold) {
+      if (Q == 32)
+        hipLaunchKernelGGL((solve_lines<32, true, true, float, float, true>), dim3(full_x, nb),
+                           block, 0, s, a);
+      else
+        hipLaunchKernelGGL((solve_lines<64, true, true, float, float, true>), dim3(full_x, nb),
+                           block, 0, s, a);
+      PT_LAUNCH_CHECK();
+      return PT_OK;
+    }
     if (Q == 32)
       hipLaunchKernelGGL((solve_lines<32, true, true>), dim3(full_x, nb), block, 0, s, a);
     else
@@ -820,6 +996,39 @@ static pt_status pass_yx(const float* in, float* carry, void* out, bool bf16, in
   else PT_YX_W(16, float);
 #undef PT_YX_W
 #undef PT_YX
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
+// fold + y + x of the padded adjoint gin into the plain out: the folded
+// carries-only y pass into carry (n3 / 8 floats), then solve_fyx.
+static pt_status pass_fyx(const float* gin, float* carry, float* out, int nx, int ny, int nz,
+                          hipStream_t s) {
+  int K = 0, QY = 0;
+  if (!yx_shape(nx, ny, &K, &QY) || QY != 16) return PT_ERR_UNSUPPORTED;
+  pt_status st = pass_lines(gin, nullptr, nx, ny, nz, 1, s, 0, carry, LINES_F32, true);
+  if (st != PT_OK) return st;
+  FYXArgs a;
+  a.in = gin;
+  a.carry = carry;
+  a.out = out;
+  a.nx = nx; a.ny = ny; a.nz = nz;
+  a.K = K;
+  const int px = nx + 3;
+  a.pitch = px + (px >> 4) + 1;
+  const int W = nx / 64;
+  const size_t lds = (size_t)W * a.pitch * 4;
+  const dim3 grid(K, nz);
+  TimedLaunch t("spline_fyx", s);
+#define PT_FYX(WW)                                                              \
+  do {                                                                          \
+    if (!allow_lds(solve_fyx<WW, 16>, lds)) return PT_ERR_HIP;                  \
+    hipLaunchKernelGGL((solve_fyx<WW, 16>), grid, dim3(nx), lds, s, a);         \
+  } while (0)
+  if (W == 4) PT_FYX(4);
+  else if (W == 8) PT_FYX(8);
+  else PT_FYX(16);
+#undef PT_FYX
   PT_LAUNCH_CHECK();
   return PT_OK;
 }
@@ -939,14 +1148,25 @@ pt_status spline_slab_fwd(const pt_grid* g, int nzl, int W, const float* field, 
 
 // Adjoint.  The forward map is pad(A_x^-1 A_y^-1 A_z^-1 g); its transpose is
 // A_z^-1 A_y^-1 A_x^-1 fold(S_bar) (A symmetric): the same solves in reverse
-// axis order, the first one reading and folding the padded gradient.
+// axis order, the first one reading and folding the padded gradient.  Where
+// the fused pass applies (rows of 256 to 1024 points), fold, y and x run as
+// one pass (the axis solves commute), with the y carries stored in the
+// component's output block until the z pass writes it.
 pt_status spline_bwd(const pt_grid* g, const float* gcoeff, float* gfield, float* ws,
                      hipStream_t s) {
   const int nx = g->nx, ny = g->ny, nz = g->nz;
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int64_t p3 = (int64_t)(nx + 3) * (ny + 3) * (nz + 3);
+  const bool fused = yx_carry_floats(g, nz) > 0;
   for (int c = 0; c < 3; ++c) {
     float* o = gfield + c * n3;
+    if (fused) {
+      pt_status st = pass_fyx(gcoeff + c * p3, o, ws, nx, ny, nz, s);  // fold + y + x
+      if (st != PT_OK) return st;
+      st = pass_lines(ws, o, nx, ny, nz, 2, s);  // z
+      if (st != PT_OK) return st;
+      continue;
+    }
     pt_status st = pass_rows(gcoeff + c * p3, o, nx, ny, nz, ROW_FOLD, s);  // fold + x
     if (st != PT_OK) return st;
     st = pass_lines(o, ws, nx, ny, nz, 1, s);  // y

@@ -40,6 +40,10 @@ def test_solve_pass_bytes_read_and_write_the_field_once():
     # (2 floats per 16 rows), written by the carries pass and read back
     assert bench.launch_bytes("spline_yx_pad", n, 0, 4, 3) == 4 * n3 + n3 // 2 + 4 * p3
     assert bench.launch_bytes("spline_y_carry", n, 0, 4, 3) == 4 * n3 + n3 // 2
+    # the adjoint's fused pass: the padded gradient read by both of its
+    # launches, the carries written and read back, the plain field written
+    assert bench.launch_bytes("spline_fold_y_carry", n, 0, 4, 3) == 4 * p3 + n3 // 2
+    assert bench.launch_bytes("spline_fyx", n, 0, 4, 3) == 4 * p3 + n3 // 2 + 4 * n3
 
 
 def test_scatter_bytes_are_split_over_the_colour_launches():
