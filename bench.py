@@ -79,7 +79,8 @@ def log(*a):
 KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold",
            "spline_y_carry", "spline_yx_pad", "spline_fold_y_carry", "spline_fyx",
            "sorted_table", "sort_keys",
-           "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_bwd_gather", "tile_scatter",
+           "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_fwd_save", "rk2_bwd_saved",
+           "tile_rk2_bwd_gather", "tile_scatter",
            "tile_tv_stage1", "tile_tv_stage2", "tile_inertial", "tile_interp", "tile_interp_grad",
            "inertial_direct", "interp", "rk2_direct_stage2", "rk2_direct_bwd",
            "rk2_direct_bwd_gather")
@@ -117,6 +118,12 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step, vb=4):
         "sorted_table": np_ * 24,
         # x in, x_out out; field once
         "tile_rk2_fwd": 3 * p3 * cb + np_ * 48,
+        # x in; x_out, u0 and the velocity gradients at both stage points
+        # (21 floats) out
+        "tile_rk2_fwd_save": 3 * p3 * cb + np_ * (48 + 84),
+        # lambda and both gradients in; dL/dx_n and the adjoints of both
+        # stage velocities out
+        "rk2_bwd_saved": np_ * (24 + 72 + 24 + 24),
         # x, lambda in; dL/dx_n, stage-1 velocity and the adjoints of both
         # stage velocities out
         "tile_rk2_bwd_gather": 3 * p3 * cb + np_ * 108,
@@ -508,6 +515,11 @@ def main():
                          "sampled oracle error after the timed steps")
     ap.add_argument("--workload", default="fwd_adjoint",
                     choices=["fwd_adjoint", "tv", "slab", "inertial", "c5"])
+    ap.add_argument("--no-save", action="store_true",
+                    help="fwd_adjoint: the forward step keeps nothing and the adjoint "
+                         "gathers the velocity gradients itself (pt_rk2_step_out + "
+                         "pt_rk2_step_bwd instead of pt_rk2_step_save + "
+                         "pt_rk2_step_bwd_saved)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="tv: run the solves on the main stream (no overlap)")
     ap.add_argument("--uniform", action="store_true",
@@ -583,6 +595,10 @@ def main():
     ws_s = pt.workspace(B.PT_OP_SORT, g, np_, cdt, dev)
     ws_f = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
     ws_b = pt.workspace(B.PT_OP_RK2_BWD, g, np_, cdt, dev)
+    # the forward keeps u0 and both stages' velocity gradients for the
+    # adjoint (the tiled FP32 / BF16 forms)
+    save = args.dtype != "f64" and not args.no_save
+    saved = torch.empty((21, np_), dtype=torch.float32, device=dev) if save else None
     torch.cuda.synchronize()
     log(f"[bench] inputs ready: dt={dt:.3e}, |u|max={umax:.3f}, "
         f"mem={torch.cuda.memory_allocated() / 2**30:.1f} GiB")
@@ -606,11 +622,17 @@ def main():
         mark("sort", 1)
         mark("rk2_fwd", 0)
         # x_n stays in pos_n for the adjoint; x_{n+1} goes to pos
-        B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
+        if save:
+            B.pt_rk2_step_save(g, coeff, dt, pos_n, pos, saved, ws_f)
+        else:
+            B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
         mark("rk2_fwd", 1)
         torch.mul(pos, 2.0, out=g_pos)  # dL/dx for L = sum |x|^2
         mark("rk2_bwd", 0)
-        B.pt_rk2_step_bwd(g, coeff, dt, pos_n, B.PT_SORTED, g_pos, g_coeff, ws_b)
+        if save:
+            B.pt_rk2_step_bwd_saved(g, dt, pos_n, saved, g_pos, g_coeff, ws_b)
+        else:
+            B.pt_rk2_step_bwd(g, coeff, dt, pos_n, B.PT_SORTED, g_pos, g_coeff, ws_b)
         mark("rk2_bwd", 1)
         mark("spline_bwd", 0)
         B.pt_spline_coeffs_bwd(g, g_coeff, g_field, ws_spb)
@@ -650,13 +672,16 @@ def main():
         "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": desc + f", {args.dtype} coefficients, FP64 positions, "
                    "fwd+adjoint Heun step with cell sort", "grid": n, "particles": np_,
-                   "kmax": kmax, "dt": dt, "coeff_dtype": args.dtype},
+                   "kmax": kmax, "dt": dt, "coeff_dtype": args.dtype,
+                   "adjoint": ("from the forward's saved gradients" if save
+                               else "gathers its own gradients")},
         "breakdown_ms": per,
         "kernels": kstats,
         "roofline": roofline(kstats, n, np_, cb, args.config, args.dtype, clustered),
     }
     if args.dtype != "f64":
         out["deferred_particles"] = B.pt_tiled_deferred(B.PT_OP_RK2, g, pt._code(cdt), np_, ws_f)
+    del saved
     uvw = None
     if not args.no_extras:
         # after the timed steps: (u, v, w) alone at the last step's sorted x_n
@@ -730,13 +755,21 @@ def other_form_step_ms(torch, pt, B, g, field, pos, ids, dt, dtype_name, steps=3
     ws_s = pt.workspace(B.PT_OP_SORT, g, np_, cdt, dev)
     ws_f = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
     ws_b = pt.workspace(B.PT_OP_RK2_BWD, g, np_, cdt, dev)
+    save = dtype_name != "f64"  # as the timed steps: the tiled forms keep the gradients
+    saved = torch.empty((21, np_), dtype=torch.float32, device=dev) if save else None
 
     def step():
         B.pt_spline_coeffs(g, field, coeff, ws_sp)
         B.pt_sort_particles(g, pos, pos_n, perm, ids, None, ws_s)
-        B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
+        if save:
+            B.pt_rk2_step_save(g, coeff, dt, pos_n, pos, saved, ws_f)
+        else:
+            B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
         torch.mul(pos, 2.0, out=g_pos)
-        B.pt_rk2_step_bwd(g, coeff, dt, pos_n, B.PT_SORTED, g_pos, g_coeff, ws_b)
+        if save:
+            B.pt_rk2_step_bwd_saved(g, dt, pos_n, saved, g_pos, g_coeff, ws_b)
+        else:
+            B.pt_rk2_step_bwd(g, coeff, dt, pos_n, B.PT_SORTED, g_pos, g_coeff, ws_b)
         B.pt_spline_coeffs_bwd(g, g_coeff, g_field, ws_spb)
 
     step()
@@ -750,6 +783,7 @@ def other_form_step_ms(torch, pt, B, g, field, pos, ids, dt, dtype_name, steps=3
     if status != 0:
         raise RuntimeError(f"device error flag set: {B.status_string(status)}")
     del pos, ids, coeff, g_coeff, g_field, pos_n, perm, g_pos, ws_sp, ws_spb, ws_s, ws_f, ws_b
+    del saved
     torch.cuda.empty_cache()
     return ms
 

@@ -349,6 +349,38 @@ pt_status pt_rk2_step_bwd(const pt_grid *grid, const void *coeff, pt_dtype dtype
                           double *g_pos, float *g_coeff, void *ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* The Heun step of eq. (dxdt) (Sec. 4.3) on particles in cell order, as
+ * pt_rk2_step_out with PT_SORTED, that also keeps what its adjoint needs, for
+ * a caller that runs the adjoint after it (not in the paper): the velocity
+ * u0 = u(x_n) and the velocity gradients du_c/dx_d (the 64-term sums of
+ * Operation 3 of Sec. 2.2) at x_n and at the predictor x* = x_n + dt u0.
+ * The forward then evaluates values and gradients at both stage points and
+ * pt_rk2_step_bwd_saved needs no gather of its own.  pos_out equals the
+ * output of pt_rk2_step_out to rounding (the same formulas; the values come
+ * from the gradient evaluation).  PT_F32 and PT_BF16 coefficients only
+ * (PT_ERR_UNSUPPORTED for PT_F64).
+ *   pos_in   in   double [3][np], in cell order
+ *   pos_out  out  double [3][np]; may be pos_in, else must not overlap it
+ *   saved    out  float [21][np]: rows 0-2 u0; row 3 + 3c + d du_c/dx_d at
+ *                 x_n; row 12 + 3c + d du_c/dx_d at x*; must not overlap
+ *                 pos_in or pos_out
+ *   ws            >= pt_workspace_bytes(PT_OP_RK2, ...) bytes */
+pt_status pt_rk2_step_save(const pt_grid *grid, const void *coeff, pt_dtype dtype,
+                           int64_t np, double dt, const double *pos_in, double *pos_out,
+                           float *saved, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of pt_rk2_step_save from what it kept: the arithmetic of
+ * pt_rk2_step_bwd with PT_SORTED (same formulas, with J(x^n) and J(x*) read
+ * from saved instead of gathered); no coefficients are read.
+ *   pos_n   in      double [3][np]: pos_in of the forward call (cell order)
+ *   saved   in      float [21][np] written by that call
+ *   g_pos   in/out  double [3][np]: dL/d(pos_out) in, dL/d(pos_n) out
+ *   g_coeff in/out  float [3][nz+3][ny+3][nx+3], accumulates dL/dS (may be NULL)
+ *   ws              >= pt_workspace_bytes(PT_OP_RK2_BWD, grid, PT_F32, np) bytes */
+pt_status pt_rk2_step_bwd_saved(const pt_grid *grid, int64_t np, double dt,
+                                const double *pos_n, const float *saved, double *g_pos,
+                                float *g_coeff, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* pt_rk2_step for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same step, with the same kernels and results, without a caller
@@ -419,7 +451,8 @@ const char *pt_status_string(pt_status status);
  * "spline_yx_pad" (the forward's fused y + x pass and the y pass that feeds
  * it its carries), "spline_fold_y_carry" and "spline_fyx" (the adjoint's
  * fused fold + y + x pass and the folded y pass that feeds it its carries),
- * "sort_keys", "sort_pass", "sort_permute",
+ * "tile_rk2_fwd_save" and "rk2_bwd_saved" (pt_rk2_step_save and the first
+ * kernel of pt_rk2_step_bwd_saved), "sort_keys", "sort_pass", "sort_permute",
  * "sorted_table" (the particle table of PT_SORTED), "slab_partition",
  * "tile_rk2_fwd",
  * "tile_rk2_bwd_gather", "tile_scatter", "tile_tv_stage1", "tile_tv_stage2",

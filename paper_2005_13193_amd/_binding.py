@@ -41,7 +41,8 @@ PT_UNSORTED, PT_SORT, PT_SORTED = 0, 1, 2  # sort argument of the RK2 steps
 EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_spline_coeffs_slab",
            "pt_sort_particles", "pt_slab_partition",
            "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_rk2_stage1", "pt_rk2_stage2",
-           "pt_inertial_step", "pt_rk2_step_noalloc", "pt_rk2_step_out", "pt_interp_sorted", "pt_tiled_deferred",
+           "pt_inertial_step", "pt_rk2_step_noalloc", "pt_rk2_step_out", "pt_rk2_step_save",
+           "pt_rk2_step_bwd_saved", "pt_interp_sorted", "pt_tiled_deferred",
            "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
            "pt_status_string", "pt_timing_enable", "pt_timing_read")
@@ -84,6 +85,8 @@ def _load():
                              vp, sz, vp],
         "pt_rk2_step_noalloc": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp],
         "pt_rk2_step_out": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
+        "pt_rk2_step_save": [g, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, sz, vp],
+        "pt_rk2_step_bwd_saved": [g, i64, dbl, vp, vp, vp, vp, vp, sz, vp],
         "pt_interp_sorted": [g, vp, ctypes.c_int, i64, vp, ctypes.c_int, vp, vp, sz, vp],
         "pt_tiled_deferred": [ctypes.c_int, g, ctypes.c_int, i64, vp, ctypes.POINTER(i64)],
         "pt_interp_uvw_bwd": [g, vp, ctypes.c_int, i64, vp, vp, vp, vp, vp],
@@ -282,6 +285,30 @@ def pt_rk2_step_out(grid, coeff, dt, pos_in, pos_out, sort, ws, stream=None):
            LIB.pt_rk2_step_out(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
                                float(dt), _ptr(pos_in), _ptr(pos_out), int(sort), _ptr(ws),
                                ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pt_rk2_step_save(grid, coeff, dt, pos_in, pos_out, saved, ws, stream=None):
+    np_ = pos_in.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos_in, torch.float64, (3, np_), "pos_in")
+    _need(pos_out, torch.float64, (3, np_), "pos_out")
+    _need(saved, torch.float32, (21, np_), "saved")
+    _check("pt_rk2_step_save",
+           LIB.pt_rk2_step_save(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                                float(dt), _ptr(pos_in), _ptr(pos_out), _ptr(saved), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pt_rk2_step_bwd_saved(grid, dt, pos_n, saved, g_pos, g_coeff, ws, stream=None):
+    np_ = pos_n.shape[1]
+    _need(pos_n, torch.float64, (3, np_), "pos_n")
+    _need(saved, torch.float32, (21, np_), "saved")
+    _need(g_pos, torch.float64, (3, np_), "g_pos")
+    _need(g_coeff, torch.float32, grid.padded_shape, "g_coeff")
+    _check("pt_rk2_step_bwd_saved",
+           LIB.pt_rk2_step_bwd_saved(ctypes.byref(_grid(grid)), np_, float(dt), _ptr(pos_n),
+                                     _ptr(saved), _ptr(g_pos), _ptr(g_coeff), _ptr(ws),
+                                     ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def pt_rk2_stage1(grid, coeff_n, pos, ids, sort, u_n, ws, stream=None):

@@ -60,6 +60,14 @@ pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
                        int64_t np, double dt, const double* x, double* x_out, void* defer,
                        void* items_ws, bool check, hipStream_t s);
 size_t tile_items_bytes(const pt_grid* g, int64_t np, bool scatter);
+pt_status tile_rk2_fwd_save(const pt_grid* g, const void* coeff, pt_dtype dtype,
+                            const int32_t* ls, int64_t np, double dt, const double* x,
+                            double* x_out, float* saved, void* defer, void* items_ws, bool check,
+                            hipStream_t s);
+pt_status tile_rk2_bwd_saved(const pt_grid* g, const int32_t* ls, int64_t np, double dt,
+                             const double* x, const float* saved, double* lam, float* ub0,
+                             float* ub1, float* gcoeff, void* defer, void* items_ws,
+                             hipStream_t s);
 pt_status tile_rk2_bwd(const pt_grid* g, const void* coeff, pt_dtype dtype, const int32_t* ls,
                        int64_t np, double dt, const double* x, const double* lam, double* xbn,
                        float* u0, float* ub0, float* ub1, float* gcoeff, void* defer,
@@ -534,6 +542,55 @@ pt_status pt_rk2_step_out(const pt_grid* grid, const void* coeff, pt_dtype dtype
                         w.items, true, stream);
   }
   return rk2_advance(grid, coeff, dtype, np, dt, pos_in, pos_out, w.u0, stream);
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char *pa = (const char*)a, *pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+pt_status pt_rk2_step_save(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                           double dt, const double* pos_in, double* pos_out, float* saved,
+                           void* ws, size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (!isfinite(dt)) return PT_ERR_ARG;
+  PT_TRY(check_tiled_np(np));
+  if (!tiled(dtype)) return PT_ERR_UNSUPPORTED;
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos_in || !pos_out || !saved) return PT_ERR_NULL;
+  const size_t pb = 24 * (size_t)np, sb = 84 * (size_t)np;
+  if ((pos_out != pos_in && overlaps(pos_out, pb, pos_in, pb)) ||
+      overlaps(saved, sb, pos_in, pb) || overlaps(saved, sb, pos_out, pb))
+    return PT_ERR_ARG;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_RK2, grid, dtype, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  Rk2Ws w = carve_rk2(grid, np, dtype, ws);
+  PT_TRY(presorted_table(grid, np, pos_in, w.lstart, stream));
+  return tile_rk2_fwd_save(grid, coeff, dtype, w.lstart, np, dt, pos_in, pos_out, saved, w.defer,
+                           w.items, true, stream);
+}
+
+pt_status pt_rk2_step_bwd_saved(const pt_grid* grid, int64_t np, double dt, const double* pos_n,
+                                const float* saved, double* g_pos, float* g_coeff, void* ws,
+                                size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_np(np));
+  if (!isfinite(dt)) return PT_ERR_ARG;
+  PT_TRY(check_tiled_np(np));
+  if (np == 0) return PT_OK;
+  if (!pos_n || !saved || !g_pos) return PT_ERR_NULL;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_RK2_BWD, grid, PT_F32, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  Rk2BwdWs w = carve_rk2_bwd(grid, np, PT_F32, ws);
+  PT_TRY(presorted_table(grid, np, pos_n, w.lstart, stream));
+  return tile_rk2_bwd_saved(grid, w.lstart, np, dt, pos_n, saved, g_pos, w.ub0, (float*)w.xbs,
+                            g_coeff, w.defer, w.items, stream);
 }
 
 pt_status pt_rk2_stage1(const pt_grid* grid, const void* coeff_n, pt_dtype dtype, int64_t np,

@@ -60,6 +60,8 @@ struct TileArgs {
   float* vel_out;         // inertial: new particle velocities [3][np] or null
   InertialCoef ik;        // inertial: step coefficients
   float* out;             // interpolation modes: [3][np] or [12][np]
+  float* saved;           // fwd save: [21][np] rows u0 (0-2), du_c/dx_d at x_n
+                          // (3 + 3c + d) and at x* (12 + 3c + d)
   float* gcoeff;          // scatter target (padded FP32)
   uint32_t* defer;        // scatter: deferred stencils (2 p + stage)
   int* defer_count;
@@ -248,7 +250,9 @@ enum {
   TILE_TV_STAGE2 = 3,
   TILE_INERTIAL = 4,
   TILE_INTERP3 = 5,   // (u, v, w) at the particles
-  TILE_INTERP12 = 6   // (u, v, w) and the nine velocity gradients
+  TILE_INTERP12 = 6,  // (u, v, w) and the nine velocity gradients
+  TILE_RK2_FWD_SAVE = 7  // the Heun step from values and gradients at both
+                         // stage points, keeping u0 and the gradients
 };
 
 __device__ __forceinline__ int gslot(int P) { return (P + kGRing) % kGRing; }
@@ -340,9 +344,12 @@ __device__ __forceinline__ void load_pdata(const TileArgs& a, int64_t p, bool ok
 // load a wait for everything, including the loads just issued for the next
 // pass, so stores must not sit between the loads and their use.
 struct Pend {
-  int64_t off;  // c * np + p for lane c < 3 of the quad, or -1
+  int64_t off;  // c * np + p for lane c < 3 of the quad (fwd save: p for
+                // every lane), or -1
   double d;     // x_out (forward modes) or dL/dx_n (backward)
-  float f0, f1, f2; // stage 1: u_n; backward: u0, ub0, ub1
+  float f0, f1, f2; // stage 1: u_n; backward: u0, ub0, ub1; fwd save: row c
+                    // of the gradient at x_n (lane 3: u0)
+  float g0, g1, g2; // fwd save: row c of the gradient at x*
   int defer;    // quad lane 0: particle to redo from global memory, or -1
 };
 
@@ -373,6 +380,20 @@ __device__ __forceinline__ void flush_pend(const TileArgs& a, Pend* o, DeferBatc
       a.out[r * np + o->off] = o->f0;
       a.out[(r + 1) * np + o->off] = o->f1;
       a.out[(r + 2) * np + o->off] = o->f2;
+    } else if (MODE == TILE_RK2_FWD_SAVE) {
+      const int q = lane64 & 3;
+      const int64_t p = o->off;
+      float* ra = a.saved + (int64_t)(q < 3 ? 3 + 3 * q : 0) * np + p;
+      ra[0] = o->f0;
+      ra[np] = o->f1;
+      ra[2 * np] = o->f2;
+      if (q < 3) {
+        a.x_out[q * np + p] = o->d;
+        float* rb = a.saved + (int64_t)(12 + 3 * q) * np + p;
+        rb[0] = o->g0;
+        rb[np] = o->g1;
+        rb[2 * np] = o->g2;
+      }
     } else if (MODE == TILE_RK2_BWD_GRAD) {
       a.xbn[o->off] = o->d;
       a.u0[o->off] = o->f0;
@@ -503,6 +524,27 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
       o->off = lane * np + p;
       o->d = x0 + h * ((double)ua + (double)ub);
     }
+  } else if (MODE == TILE_RK2_FWD_SAVE) {
+    float on[12], os[12];
+    eval_ring<CT, true>(ring, g, qn, X0, Y0, lane, on);
+    const float onl = pick3(on, lane);
+    const Pt qs = locate_quad(ax, xnl + a.dt * (double)onl, X0, Y0, zz - 1, zz + kSlab, lerr);
+    if (!qs.in_ring) {
+      if (lane == 0) o->defer = d.p;
+      return;
+    }
+    eval_ring<CT, true>(ring, g, qs, X0, Y0, lane, os);
+    // lane c < 3: x_out[c] and row c of both gradients; lane 3: u0
+    const float ua = lane == 0 ? on[0] : lane == 1 ? on[1] : on[2];
+    const float ub = lane == 0 ? os[0] : lane == 1 ? os[1] : os[2];
+    o->off = p;
+    o->d = xnl + 0.5 * a.dt * ((double)ua + (double)ub);
+    o->f0 = lane == 0 ? on[3] : lane == 1 ? on[6] : lane == 2 ? on[9] : on[0];
+    o->f1 = lane == 0 ? on[4] : lane == 1 ? on[7] : lane == 2 ? on[10] : on[1];
+    o->f2 = lane == 0 ? on[5] : lane == 1 ? on[8] : lane == 2 ? on[11] : on[2];
+    o->g0 = lane == 0 ? os[3] : lane == 1 ? os[6] : os[9];
+    o->g1 = lane == 0 ? os[4] : lane == 1 ? os[7] : os[10];
+    o->g2 = lane == 0 ? os[5] : lane == 1 ? os[8] : os[11];
   } else {
     float on[12], os[12];
     eval_ring<CT, true>(ring, g, qn, X0, Y0, lane, on);
@@ -845,6 +887,17 @@ __global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
           a.vel_out[c * np + p] =
               (float)inertial_velocity(a.ik, vn[c], (double)u0[c], (double)u1[c]);
       }
+    } else if (MODE == TILE_RK2_FWD_SAVE) {
+      float on[12], os[12];
+      eval_global<CT, true>(coeff, g, qn, on);
+      double xs[3];
+      for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)on[c];
+      const Pt qs = locate_pt<0>(g, xs, 0, 0, 0, -1, a.err);
+      eval_global<CT, true>(coeff, g, qs, os);
+      for (int c = 0; c < 3; ++c)
+        a.x_out[c * np + p] = xn[c] + 0.5 * a.dt * ((double)on[c] + (double)os[c]);
+      for (int r = 0; r < 12; ++r) a.saved[r * np + p] = on[r];
+      for (int r = 3; r < 12; ++r) a.saved[(r + 9) * np + p] = os[r];
     } else if (MODE == TILE_RK2_FWD) {
       float u0[12], u1[12];
       eval_global<CT, false>(coeff, g, qn, u0);
@@ -1871,6 +1924,7 @@ static const char* gather_name(int mode) {
     case TILE_INERTIAL: return "tile_inertial";
     case TILE_INTERP3: return "tile_interp";
     case TILE_INTERP12: return "tile_interp_grad";
+    case TILE_RK2_FWD_SAVE: return "tile_rk2_fwd_save";
     default: return "tile_tv_stage2";
   }
 }
@@ -1918,6 +1972,7 @@ static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int
       case TILE_INERTIAL: PT_TG(CT, TILE_INERTIAL); break; \
       case TILE_INTERP3: PT_TG(CT, TILE_INTERP3); break; \
       case TILE_INTERP12: PT_TG(CT, TILE_INTERP12); break; \
+      case TILE_RK2_FWD_SAVE: PT_TG(CT, TILE_RK2_FWD_SAVE); break; \
       default: PT_TG(CT, TILE_TV_STAGE2); break;          \
     }                                                     \
   } while (0)
@@ -1940,6 +1995,20 @@ pt_status tile_rk2_fwd(const pt_grid* g, const void* coeff, pt_dtype dtype, cons
   a.x = x;
   a.x_out = x_out;
   return launch_gather(g, a, dtype, TILE_RK2_FWD, defer, items_ws, check, s);
+}
+
+// The same step keeping, per particle, u0 and the velocity gradients at x_n
+// and at x* in saved ([21][np] floats, rows as TileArgs::saved) for
+// tile_rk2_bwd_saved.  x_out may alias x.
+pt_status tile_rk2_fwd_save(const pt_grid* g, const void* coeff, pt_dtype dtype,
+                            const int32_t* ls, int64_t np, double dt, const double* x,
+                            double* x_out, float* saved, void* defer, void* items_ws, bool check,
+                            hipStream_t s) {
+  TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
+  a.x = x;
+  a.x_out = x_out;
+  a.saved = saved;
+  return launch_gather(g, a, dtype, TILE_RK2_FWD_SAVE, defer, items_ws, check, s);
 }
 
 // Inertial / diffusive step on sorted particles x (table ls, checked on the
@@ -2051,6 +2120,79 @@ pt_status tile_scatter_only(const pt_grid* g, const int32_t* ls, int64_t np, dou
     PT_LAUNCH_CHECK();
   }
   return launch_scatter(g, ls, np, dt, x, u0, ub0, ub1, gcoeff, defer, items_ws, check, s);
+}
+
+// The step adjoint from what tile_rk2_fwd_save kept, one thread per
+// particle: with lam = dL/dx_{n+1} and J0, J1 the velocity gradients at x_n
+// and x*,
+//   ub1 = dt/2 lam,  ub0 = dt/2 lam + dt J1^T ub1,
+//   dL/dx_n = lam + J1^T ub1 + J0^T ub0  (written over lam),
+// the arithmetic of the adjoint gather; the largest |ub| of each block goes
+// to one of the kMaxSlots slots for the scatter's fixed-point scale.
+__global__ __launch_bounds__(256) void rk2_bwd_saved(const float* __restrict__ saved, int64_t np,
+                                                     double dt, double* __restrict__ lam_xb,
+                                                     float* __restrict__ ub0,
+                                                     float* __restrict__ ub1, int* umax) {
+  __shared__ float smax[4];
+  float m = 0.0f;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < np;
+       p += (int64_t)gridDim.x * 256) {
+    double lam[3];
+    float j0[9], j1[9], b0[3], b1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lam[c] = lam_xb[c * np + p];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      j0[r] = saved[(3 + r) * np + p];
+      j1[r] = saved[(12 + r) * np + p];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b1[c] = (float)(0.5 * dt * lam[c]);
+    double xbs[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xbs[c] = (double)(b1[0] * j1[c] + b1[1] * j1[3 + c] + b1[2] * j1[6 + c]);
+      b0[c] = (float)(0.5 * dt * lam[c] + dt * xbs[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lam_xb[c * np + p] =
+          lam[c] + xbs[c] + (double)(b0[0] * j0[c] + b0[1] * j0[3 + c] + b0[2] * j0[6 + c]);
+      ub0[c * np + p] = b0[c];
+      ub1[c * np + p] = b1[c];
+      m = fmaxf(m, fmaxf(fabsf(b0[c]), fabsf(b1[c])));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(umax + (blockIdx.x & (kMaxSlots - 1)),
+              __float_as_int(fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]))));
+}
+
+// dL/dx_n (in place of lam) and the coefficient gradient (accumulated into
+// gcoeff, if not null) of a Heun step on sorted particles x (table ls,
+// checked on the device) whose forward kept saved (tile_rk2_fwd_save).  ub0
+// and ub1: [3][np] floats of workspace.
+pt_status tile_rk2_bwd_saved(const pt_grid* g, const int32_t* ls, int64_t np, double dt,
+                             const double* x, const float* saved, double* lam, float* ub0,
+                             float* ub1, float* gcoeff, void* defer, void* items_ws,
+                             hipStream_t s) {
+  pt_status st = tile_defer_reset(defer, s);
+  if (st != PT_OK) return st;
+  {
+    TimedLaunch t("rk2_bwd_saved", s);
+    const unsigned blocks = grid_1d(np, 256) < 8192u ? grid_1d(np, 256) : 8192u;
+    hipLaunchKernelGGL(rk2_bwd_saved, dim3(blocks), dim3(256), 0, s, saved, np, dt, lam,
+                       ub0, ub1, tile_umax_slots(defer));
+    PT_LAUNCH_CHECK();
+  }
+  if (!gcoeff) return PT_OK;
+  // the scatter reads u0 from the saved rows 0..2 ([3][np], read only)
+  return tile_scatter_only(g, ls, np, dt, x, const_cast<float*>(saved), ub0, ub1, gcoeff, defer,
+                           items_ws, true, s);
 }
 
 static pt_status launch_scatter(const pt_grid* g, const int32_t* ls, int64_t np, double dt,

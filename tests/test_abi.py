@@ -162,6 +162,37 @@ def test_step_out_arguments(b):
     assert f(ctypes.byref(g), fake, 0, 0, 0.1, None, None, b.PT_SORTED, None, 0, None) == b.PT_OK
 
 
+def test_saved_step_arguments(b):
+    """pt_rk2_step_save / pt_rk2_step_bwd_saved: FP64 coefficients (no tiled
+    form), saved overlapping a position array, null buffers, short
+    workspaces and too many particles are refused before any launch; no
+    particles is a no-op."""
+    L = b.LIB
+    g = _g(b)
+    vp = ctypes.c_void_p
+    fake, other, near = vp(0x1000), vp(0x10000000), vp(0x1008)
+    f = L.pt_rk2_step_save
+    assert f(ctypes.byref(g), fake, b.PT_F64, 10, 0.1, fake, other, vp(0x20000000), fake,
+             1 << 40, None) == b.PT_ERR_UNSUPPORTED
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, other, None, fake, 1 << 40,
+             None) == b.PT_ERR_NULL
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, other, near, fake, 1 << 40,
+             None) == b.PT_ERR_ARG
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, near, vp(0x20000000), fake, 1 << 40,
+             None) == b.PT_ERR_ARG
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, other, vp(0x20000000), fake, 8,
+             None) == b.PT_ERR_WORKSPACE
+    assert f(ctypes.byref(g), fake, 0, 1 << 30, 0.1, fake, fake, vp(1 << 45), fake, 1 << 62,
+             None) == b.PT_ERR_UNSUPPORTED
+    assert f(ctypes.byref(g), fake, 0, 0, 0.1, None, None, None, None, 0, None) == b.PT_OK
+    h = L.pt_rk2_step_bwd_saved
+    assert h(ctypes.byref(g), 10, 0.1, fake, None, fake, None, fake, 1 << 40, None) == b.PT_ERR_NULL
+    assert h(ctypes.byref(g), 10, float("inf"), fake, fake, fake, None, fake, 1 << 40,
+             None) == b.PT_ERR_ARG
+    assert h(ctypes.byref(g), 10, 0.1, fake, fake, fake, None, fake, 8, None) == b.PT_ERR_WORKSPACE
+    assert h(ctypes.byref(g), 0, 0.1, None, None, None, None, None, 0, None) == b.PT_OK
+
+
 def test_f64_workspaces_hold_fp64_values(b):
     """FP64 storage keeps velocities in FP64: its RK2 and inertial
     workspaces are larger than the FP32 ones by the 12 extra bytes per value
