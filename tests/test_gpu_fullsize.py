@@ -14,8 +14,10 @@ full with the plain oracle.
     of the whole 1024^3 field on the host), each step launched as the
     benchmark launches it (one sort, then the step on the sorted particles);
     for FP32, the adjoint of the last step at 256 sampled particles and 64
-    sampled coefficient points, and the adjoint of the solve at 200 sampled
-    grid points;
+    sampled coefficient points, both as pt_rk2_step_bwd gathers it and from
+    the gradients pt_rk2_step_save kept (the benchmark's default step; the
+    two also compared on every particle), and the adjoint of the solve at 200
+    sampled grid points;
   1024^3, the time-varying step (two fields, the two stages) at 256 sampled
     particles;
   512^3, 16M uniform particles, FP32: one fwd+adjoint step launched as the
@@ -233,12 +235,30 @@ def _c3_adjoint_of_last_step(pt, B, g, coeff, pos_n, pos, dt):
     ws_b = pt.workspace(B.PT_OP_RK2_BWD, g, np_, torch.float32, dev)
     B.pt_rk2_step_bwd(g, coeff, dt, pos_n, B.PT_SORTED, g_pos, gco, ws_b)
     assert pt.last_device_error() == 0
-    del ws_b
+    # the same step and adjoint as the benchmark's default step launches
+    # them: the forward keeps u0 and both gradients, the adjoint reads them
+    saved = torch.empty((21, np_), dtype=torch.float32, device=dev)
+    x1 = torch.empty_like(pos)
+    ws_f = pt.workspace(B.PT_OP_RK2, g, np_, coeff.dtype, dev)
+    B.pt_rk2_step_save(g, coeff, dt, pos_n, x1, saved, ws_f)
+    del ws_f
+    g_pos2 = lam.clone()
+    gco2 = torch.zeros_like(gco)
+    B.pt_rk2_step_bwd_saved(g, dt, pos_n, saved, g_pos2, gco2, ws_b)
+    assert pt.last_device_error() == 0
+    del ws_b, saved
+    for c in range(3):  # every particle: the kept-gradient path against the gathering one
+        disp = max_abs(pos[c] - pos_n[c])
+        assert max_abs(x1[c] - pos[c]) / disp < 1e-6, c
+        assert max_abs(g_pos2[c] - g_pos[c]) / max_abs(g_pos[c]) < 1e-6, c
+        assert max_abs(gco2[c] - gco[c]) / max_abs(gco[c]) < 1e-6, c
+    del x1
+    log("saved-gradient step and adjoint agree with the gathering ones on all particles")
     rng = np.random.default_rng(21)
     part = torch.from_numpy(rng.choice(np_, 256, replace=False)).to(dev)
     out = {"x": pos_n[:, part].cpu().numpy(), "lam": lam[:, part].cpu().numpy(),
-           "gx": g_pos[:, part].cpu().numpy()}
-    del g_pos
+           "gx": g_pos[:, part].cpu().numpy(), "gx_saved": g_pos2[:, part].cpu().numpy()}
+    del g_pos, g_pos2
     h = 2 * np.pi / n
     cell = torch.floor(torch.remainder(pos_n, 2 * np.pi) / h).long().clamp_(0, n - 1)
     at = cell[:, torch.from_numpy(rng.choice(np_, 32, replace=False)).to(dev)].cpu().numpy() + 1
@@ -254,9 +274,11 @@ def _c3_adjoint_of_last_step(pt, B, g, coeff, pos_n, pos, dt):
     out["near_x"] = pos_n[:, idx].cpu().numpy()
     out["near_lam"] = lam[:, idx].cpu().numpy()
     out["pts"] = pts
-    out["gco"] = gco[:, torch.from_numpy(pts[2]).to(dev), torch.from_numpy(pts[1]).to(dev),
-                     torch.from_numpy(pts[0]).to(dev)].double().cpu().numpy()
-    del lam, gco, cell, near
+    ix = (torch.from_numpy(pts[2]).to(dev), torch.from_numpy(pts[1]).to(dev),
+          torch.from_numpy(pts[0]).to(dev))
+    out["gco"] = gco[:, ix[0], ix[1], ix[2]].double().cpu().numpy()
+    out["gco_saved"] = gco2[:, ix[0], ix[1], ix[2]].double().cpu().numpy()
+    del lam, gco, gco2, cell, near
     torch.cuda.empty_cache()
     log(f"adjoint done; {idx.numel()} particles near the sampled coefficients")
     return out
@@ -267,6 +289,9 @@ def _check_c3_adjoint(og, rc, dt, adj):
     err = normwise(adj["gx"], gx)
     log(f"adjoint dL/dx_n error (256 particles) {err:.3e}")
     assert err < F32_TOL
+    err = normwise(adj["gx_saved"], gx)
+    log(f"adjoint dL/dx_n error, kept gradients (256 particles) {err:.3e}")
+    assert err < F32_TOL
     gfull = np.zeros_like(rc)
     oracle.rk2_step_bwd(og, rc, adj["near_x"], dt, adj["near_lam"], gfull)
     pts = adj["pts"]
@@ -275,6 +300,9 @@ def _check_c3_adjoint(og, rc, dt, adj):
     assert np.abs(ref).max() > 0
     err = normwise(adj["gco"], ref)
     log(f"adjoint dL/dS error (64 sampled coefficients) {err:.3e}")
+    assert err < F32_TOL
+    err = normwise(adj["gco_saved"], ref)
+    log(f"adjoint dL/dS error, kept gradients (64 sampled coefficients) {err:.3e}")
     assert err < F32_TOL
 
 
