@@ -871,7 +871,9 @@ def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
     """2048^3 grid, 256M uniform particles: per step the cell sort, the
     column-tiled 12-output gather at x_n and the Heun step on the sorted
     particles; the coefficients of the frozen field are computed once before
-    (and timed once, reported apart)."""
+    (and timed once, reported apart).  The gather and the step are one pass
+    (pt_rk2_step_save, whose rows 0-11 are the 12 outputs at x_n) unless
+    --no-save, which runs pt_interp_sorted and pt_rk2_step_out."""
     dev = torch.device("cuda:0")
     g = pt.Grid(n)
     field = synth.spectral_field_torch_chunked(n, kmax, seed=0, device=dev)
@@ -889,9 +891,15 @@ def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
     pos_n = torch.empty_like(pos)
     perm = torch.empty(np_, dtype=torch.int32, device=dev)
     ids = torch.arange(np_, dtype=torch.int32, device=dev)
-    out12 = torch.empty((12, np_), dtype=B.value_dtype(coeff), device=dev)
+    save = args.dtype != "f64" and not args.no_save
+    if save:
+        # rows 0-11: (u, v, w) and the nine gradients at x_n; 12-20: the
+        # gradients at the predictor point
+        saved = torch.empty((21, np_), dtype=torch.float32, device=dev)
+    else:
+        out12 = torch.empty((12, np_), dtype=B.value_dtype(coeff), device=dev)
+        ws_i = pt.workspace(B.PT_OP_INTERP_SORTED, g, np_, cdt, dev)
     ws_s = pt.workspace(B.PT_OP_SORT, g, np_, cdt, dev)
-    ws_i = pt.workspace(B.PT_OP_INTERP_SORTED, g, np_, cdt, dev)
     ws_f = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
     torch.cuda.synchronize()
     log(f"[bench] c5 inputs ready: solve {solve_ms:.1f} ms, "
@@ -899,8 +907,11 @@ def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
 
     def step():
         B.pt_sort_particles(g, pos, pos_n, perm, ids, None, ws_s)
-        B.pt_interp_sorted(g, coeff, pos_n, out12, ws_i)
-        B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
+        if save:
+            B.pt_rk2_step_save(g, coeff, dt, pos_n, pos, saved, ws_f)
+        else:
+            B.pt_interp_sorted(g, coeff, pos_n, out12, ws_i)
+            B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
 
     for i in range(args.warmup):
         step()
@@ -925,15 +936,18 @@ def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": desc + f", {args.dtype} coefficients of a frozen field, per "
-                   "step: cell sort, 12-output gather (u,v,w and 9 gradients), Heun step",
+                   "step: cell sort, 12-output gather (u,v,w and 9 gradients), Heun step"
+                   + (" (the gather fused into the step)" if save else ""),
                    "grid": n, "particles": np_, "dt": dt, "solve_ms_once": solve_ms},
         "kernels": kstats,
         "roofline": roofline(kstats, n, np_, cb, "c5", args.dtype, False),
     }
-    if "tile_interp_grad" in kstats:
-        kb = launch_bytes("tile_interp_grad", n, np_, cb, 1)
-        k_ms = kstats["tile_interp_grad"]["avg_launch_ms"]
-        out["grad_gather"] = {"kernel": "tile_interp_grad", "ms": k_ms,
+    for kname in ("tile_interp_grad", "tile_rk2_fwd_save"):
+        if kname not in kstats:
+            continue
+        kb = launch_bytes(kname, n, np_, cb, 1)
+        k_ms = kstats[kname]["avg_launch_ms"]
+        out["grad_gather"] = {"kernel": kname, "ms": k_ms,
                               "interpolations_per_s": np_ / (k_ms * 1e-3),
                               "algorithmic_bytes": kb,
                               "hbm_frac": kb / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}

@@ -25,7 +25,9 @@ full with the plain oracle.
     against the windowed and the full FP64 oracle;
   2048^3, 256M uniform particles (64-bit sort keys): sort, the 12-output
     gather on the sorted particles (FP32, and BF16-stored coefficients at the
-    same points) and one sorted Heun step, sampled, and one
+    same points) and one sorted Heun step, sampled; the saved-gradient step
+    (the c5 benchmark's fused gather + step) against both on every particle
+    and against the oracle on samples; and one
     device's 256-plane slab solve of the same field, sampled;
   256^3, 1M particles: L = sum |x(8)|^2 through TrackParticles (checkpoints
     every 2 steps) against the oracle's hand adjoint, all outputs, and
@@ -487,10 +489,32 @@ def test_c5_2048_sampled(pt):
     inv = torch.empty_like(perm)
     inv[perm.long()] = torch.arange(np_, dtype=perm.dtype, device=dev)
     got = out12[:, inv[sample].long()].double().cpu().numpy()
-    del ps, perm, out12, inv
+    # the step that keeps u0 and the gradients (the c5 benchmark's fused
+    # gather + step): its rows 0-11 are the 12 outputs at x_n
+    saved = torch.empty((21, np_), dtype=torch.float32, device=dev)
+    x1 = torch.empty_like(ps)
+    B.pt_rk2_step_save(g, coeff, dt, ps, x1, saved,
+                       pt.workspace(B.PT_OP_RK2, g, np_, torch.float32, dev))
+    assert pt.last_device_error() == 0
+    # every particle, against the 12-output gather: the values per row, the
+    # gradient rows relative to the largest gradient entry (a derivative's
+    # rounding scales with |S| / h); both are FP32 sums of the same 64 terms
+    # (the deferred particles' from global memory, in another order)
+    e_v = max(max_abs(saved[r] - out12[r]) / max_abs(out12[r]) for r in range(3))
+    e_g = (max(max_abs(saved[r] - out12[r]) for r in range(3, 12))
+           / max(max_abs(out12[r]) for r in range(3, 12)))
+    log(f"c5: saved-gradient step rows 0-11 against the 12-output gather, every particle: "
+        f"values {e_v:.3e}, gradients {e_g:.3e}")
+    assert e_v < 1e-6 and e_g < F32_TOL
+    got_s = saved[:12, inv[sample].long()].double().cpu().numpy()
+    fin_s = x1[:, inv[sample].long()].cpu().numpy()
+    del ps, perm, out12, inv, saved, x1
     torch.cuda.empty_cache()
     err = normwise(got, ref12)
     log(f"c5 f32: tiled 12-output gather error (128 particles) {err:.3e}")
+    assert err < F32_TOL
+    err = normwise(got_s, ref12)
+    log(f"c5 f32: 12 outputs kept by the saved-gradient step (128 particles) {err:.3e}")
     assert err < F32_TOL
     log("c5: sorted 12-output gather ok")
     ids = torch.arange(np_, dtype=torch.int32, device=dev)
@@ -500,6 +524,9 @@ def test_c5_2048_sampled(pt):
     ref = oracle.rk2_window(og, fh, pos0, dt, 1)
     err = normwise(fin - pos0, ref - pos0)
     log(f"c5: step displacement error {err:.3e}")
+    assert err < F32_TOL
+    err = normwise(fin_s - pos0, ref - pos0)
+    log(f"c5: saved-gradient step displacement error {err:.3e}")
     assert err < F32_TOL
     del pos, ids, coeff
     torch.cuda.empty_cache()
