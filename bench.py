@@ -80,6 +80,7 @@ KERNELS = ("spline_x", "spline_y", "spline_z", "spline_x_pad", "spline_x_fold",
            "spline_y_carry", "spline_yx_pad", "spline_fold_y_carry", "spline_fyx",
            "sorted_table", "sort_keys",
            "sort_pass", "sort_permute", "tile_rk2_fwd", "tile_rk2_fwd_save", "rk2_bwd_saved",
+           "tile_rk2_fwd_grad",
            "tile_rk2_bwd_gather", "tile_scatter",
            "tile_tv_stage1", "tile_tv_stage2", "tile_inertial", "tile_interp", "tile_interp_grad",
            "inertial_direct", "interp", "rk2_direct_stage2", "rk2_direct_bwd",
@@ -121,6 +122,8 @@ def launch_bytes(kernel, n, np_, cb, launches_per_step, vb=4):
         # x in; x_out, u0 and the velocity gradients at both stage points
         # (21 floats) out
         "tile_rk2_fwd_save": 3 * p3 * cb + np_ * (48 + 84),
+        # x in; x_out and the 12 values at x_n out
+        "tile_rk2_fwd_grad": 3 * p3 * cb + np_ * (48 + 48),
         # lambda and both gradients in; dL/dx_n and the adjoints of both
         # stage velocities out
         "rk2_bwd_saved": np_ * (24 + 72 + 24 + 24),
@@ -872,8 +875,8 @@ def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
     column-tiled 12-output gather at x_n and the Heun step on the sorted
     particles; the coefficients of the frozen field are computed once before
     (and timed once, reported apart).  The gather and the step are one pass
-    (pt_rk2_step_save, whose rows 0-11 are the 12 outputs at x_n) unless
-    --no-save, which runs pt_interp_sorted and pt_rk2_step_out."""
+    (pt_rk2_step_grad: the 12 outputs at x_n and the step) unless --no-save,
+    which runs pt_interp_sorted and pt_rk2_step_out."""
     dev = torch.device("cuda:0")
     g = pt.Grid(n)
     field = synth.spectral_field_torch_chunked(n, kmax, seed=0, device=dev)
@@ -891,13 +894,9 @@ def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
     pos_n = torch.empty_like(pos)
     perm = torch.empty(np_, dtype=torch.int32, device=dev)
     ids = torch.arange(np_, dtype=torch.int32, device=dev)
-    save = args.dtype != "f64" and not args.no_save
-    if save:
-        # rows 0-11: (u, v, w) and the nine gradients at x_n; 12-20: the
-        # gradients at the predictor point
-        saved = torch.empty((21, np_), dtype=torch.float32, device=dev)
-    else:
-        out12 = torch.empty((12, np_), dtype=B.value_dtype(coeff), device=dev)
+    fused = args.dtype != "f64" and not args.no_save
+    out12 = torch.empty((12, np_), dtype=B.value_dtype(coeff), device=dev)
+    if not fused:
         ws_i = pt.workspace(B.PT_OP_INTERP_SORTED, g, np_, cdt, dev)
     ws_s = pt.workspace(B.PT_OP_SORT, g, np_, cdt, dev)
     ws_f = pt.workspace(B.PT_OP_RK2, g, np_, cdt, dev)
@@ -907,8 +906,8 @@ def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
 
     def step():
         B.pt_sort_particles(g, pos, pos_n, perm, ids, None, ws_s)
-        if save:
-            B.pt_rk2_step_save(g, coeff, dt, pos_n, pos, saved, ws_f)
+        if fused:
+            B.pt_rk2_step_grad(g, coeff, dt, pos_n, pos, out12, ws_f)
         else:
             B.pt_interp_sorted(g, coeff, pos_n, out12, ws_i)
             B.pt_rk2_step_out(g, coeff, dt, pos_n, pos, B.PT_SORTED, ws_f)
@@ -937,12 +936,12 @@ def run_c5(args, torch, pt, B, synth, n, np_, kmax, desc, cdt, cb):
         "data": "synthetic",
         "config": {"workload": desc + f", {args.dtype} coefficients of a frozen field, per "
                    "step: cell sort, 12-output gather (u,v,w and 9 gradients), Heun step"
-                   + (" (the gather fused into the step)" if save else ""),
+                   + (" (the gather fused into the step)" if fused else ""),
                    "grid": n, "particles": np_, "dt": dt, "solve_ms_once": solve_ms},
         "kernels": kstats,
         "roofline": roofline(kstats, n, np_, cb, "c5", args.dtype, False),
     }
-    for kname in ("tile_interp_grad", "tile_rk2_fwd_save"):
+    for kname in ("tile_interp_grad", "tile_rk2_fwd_grad"):
         if kname not in kstats:
             continue
         kb = launch_bytes(kname, n, np_, cb, 1)

@@ -369,6 +369,22 @@ pt_status pt_rk2_step_save(const pt_grid *grid, const void *coeff, pt_dtype dtyp
                            int64_t np, double dt, const double *pos_in, double *pos_out,
                            float *saved, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The Heun step of eq. (dxdt) (Sec. 4.3) on particles in cell order, as
+ * pt_rk2_step_out with PT_SORTED, that also returns (u, v, w) and the nine
+ * velocity gradients at x_n (Operations 2 and 3 of Sec. 2.2: the velocity
+ * gradients need the twice-differentiable interpolant) from the same pass
+ * over the coefficients, as pt_interp_sorted with nout = 12 would.  pos_out
+ * equals the output of pt_rk2_step_out to rounding.  PT_F32 and PT_BF16
+ * coefficients only (PT_ERR_UNSUPPORTED for PT_F64).
+ *   pos_in   in   double [3][np], in cell order
+ *   pos_out  out  double [3][np]; may be pos_in, else must not overlap it
+ *   out      out  float [12][np]: rows u, v, w, then du_c/dx_d at 3 + 3c + d;
+ *                 must not overlap pos_in or pos_out
+ *   ws            >= pt_workspace_bytes(PT_OP_RK2, ...) bytes */
+pt_status pt_rk2_step_grad(const pt_grid *grid, const void *coeff, pt_dtype dtype,
+                           int64_t np, double dt, const double *pos_in, double *pos_out,
+                           float *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Adjoint of pt_rk2_step_save from what it kept: the arithmetic of
  * pt_rk2_step_bwd with PT_SORTED (same formulas, with J(x^n) and J(x*) read
  * from saved instead of gathered); no coefficients are read.
@@ -452,7 +468,8 @@ const char *pt_status_string(pt_status status);
  * it its carries), "spline_fold_y_carry" and "spline_fyx" (the adjoint's
  * fused fold + y + x pass and the folded y pass that feeds it its carries),
  * "tile_rk2_fwd_save" and "rk2_bwd_saved" (pt_rk2_step_save and the first
- * kernel of pt_rk2_step_bwd_saved), "sort_keys", "sort_pass", "sort_permute",
+ * kernel of pt_rk2_step_bwd_saved), "tile_rk2_fwd_grad" (pt_rk2_step_grad),
+ * "sort_keys", "sort_pass", "sort_permute",
  * "sorted_table" (the particle table of PT_SORTED), "slab_partition",
  * "tile_rk2_fwd",
  * "tile_rk2_bwd_gather", "tile_scatter", "tile_tv_stage1", "tile_tv_stage2",

@@ -42,7 +42,8 @@ EXPORTS = ("pt_workspace_bytes", "pt_key_layout", "pt_spline_coeffs", "pt_spline
            "pt_sort_particles", "pt_slab_partition",
            "pt_interp_uvw", "pt_interp_grad", "pt_rk2_step", "pt_rk2_stage1", "pt_rk2_stage2",
            "pt_inertial_step", "pt_rk2_step_noalloc", "pt_rk2_step_out", "pt_rk2_step_save",
-           "pt_rk2_step_bwd_saved", "pt_interp_sorted", "pt_tiled_deferred",
+           "pt_rk2_step_bwd_saved", "pt_rk2_step_grad", "pt_interp_sorted",
+           "pt_tiled_deferred",
            "pt_interp_uvw_bwd",
            "pt_spline_coeffs_bwd", "pt_rk2_step_bwd", "pt_last_device_error",
            "pt_status_string", "pt_timing_enable", "pt_timing_read")
@@ -86,6 +87,7 @@ def _load():
         "pt_rk2_step_noalloc": [g, vp, ctypes.c_int, i64, dbl, vp, ctypes.c_int, vp],
         "pt_rk2_step_out": [g, vp, ctypes.c_int, i64, dbl, vp, vp, ctypes.c_int, vp, sz, vp],
         "pt_rk2_step_save": [g, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, sz, vp],
+        "pt_rk2_step_grad": [g, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, sz, vp],
         "pt_rk2_step_bwd_saved": [g, i64, dbl, vp, vp, vp, vp, vp, sz, vp],
         "pt_interp_sorted": [g, vp, ctypes.c_int, i64, vp, ctypes.c_int, vp, vp, sz, vp],
         "pt_tiled_deferred": [ctypes.c_int, g, ctypes.c_int, i64, vp, ctypes.POINTER(i64)],
@@ -296,6 +298,18 @@ def pt_rk2_step_save(grid, coeff, dt, pos_in, pos_out, saved, ws, stream=None):
     _check("pt_rk2_step_save",
            LIB.pt_rk2_step_save(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
                                 float(dt), _ptr(pos_in), _ptr(pos_out), _ptr(saved), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pt_rk2_step_grad(grid, coeff, dt, pos_in, pos_out, out, ws, stream=None):
+    np_ = pos_in.shape[1]
+    _need(coeff, None, grid.padded_shape, "coeff")
+    _need(pos_in, torch.float64, (3, np_), "pos_in")
+    _need(pos_out, torch.float64, (3, np_), "pos_out")
+    _need(out, torch.float32, (12, np_), "out")
+    _check("pt_rk2_step_grad",
+           LIB.pt_rk2_step_grad(ctypes.byref(_grid(grid)), _ptr(coeff), _dtype_code(coeff), np_,
+                                float(dt), _ptr(pos_in), _ptr(pos_out), _ptr(out), _ptr(ws),
                                 ws.numel() * ws.element_size(), _stream(stream)))
 
 

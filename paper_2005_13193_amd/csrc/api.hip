@@ -64,6 +64,10 @@ pt_status tile_rk2_fwd_save(const pt_grid* g, const void* coeff, pt_dtype dtype,
                             const int32_t* ls, int64_t np, double dt, const double* x,
                             double* x_out, float* saved, void* defer, void* items_ws, bool check,
                             hipStream_t s);
+pt_status tile_rk2_fwd_grad(const pt_grid* g, const void* coeff, pt_dtype dtype,
+                            const int32_t* ls, int64_t np, double dt, const double* x,
+                            double* x_out, float* out, void* defer, void* items_ws, bool check,
+                            hipStream_t s);
 pt_status tile_rk2_bwd_saved(const pt_grid* g, const int32_t* ls, int64_t np, double dt,
                              const double* x, const float* saved, double* lam, float* ub0,
                              float* ub1, float* gcoeff, void* defer, void* items_ws,
@@ -571,6 +575,31 @@ pt_status pt_rk2_step_save(const pt_grid* grid, const void* coeff, pt_dtype dtyp
   Rk2Ws w = carve_rk2(grid, np, dtype, ws);
   PT_TRY(presorted_table(grid, np, pos_in, w.lstart, stream));
   return tile_rk2_fwd_save(grid, coeff, dtype, w.lstart, np, dt, pos_in, pos_out, saved, w.defer,
+                           w.items, true, stream);
+}
+
+pt_status pt_rk2_step_grad(const pt_grid* grid, const void* coeff, pt_dtype dtype, int64_t np,
+                           double dt, const double* pos_in, double* pos_out, float* out,
+                           void* ws, size_t ws_bytes, hipStream_t stream) {
+  PT_TRY(check_grid(grid));
+  PT_TRY(check_dtype(dtype));
+  PT_TRY(check_np(np));
+  if (!isfinite(dt)) return PT_ERR_ARG;
+  PT_TRY(check_tiled_np(np));
+  if (!tiled(dtype)) return PT_ERR_UNSUPPORTED;
+  if (np == 0) return PT_OK;
+  if (!coeff || !pos_in || !pos_out || !out) return PT_ERR_NULL;
+  const size_t pb = 24 * (size_t)np, ob = 48 * (size_t)np;
+  if ((pos_out != pos_in && overlaps(pos_out, pb, pos_in, pb)) ||
+      overlaps(out, ob, pos_in, pb) || overlaps(out, ob, pos_out, pb))
+    return PT_ERR_ARG;
+  size_t need = 0;
+  PT_TRY(pt_workspace_bytes(PT_OP_RK2, grid, dtype, np, &need));
+  if (!ws || ws_bytes < need) return PT_ERR_WORKSPACE;
+  PT_TRY(ready());
+  Rk2Ws w = carve_rk2(grid, np, dtype, ws);
+  PT_TRY(presorted_table(grid, np, pos_in, w.lstart, stream));
+  return tile_rk2_fwd_grad(grid, coeff, dtype, w.lstart, np, dt, pos_in, pos_out, out, w.defer,
                            w.items, true, stream);
 }
 

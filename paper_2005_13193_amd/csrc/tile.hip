@@ -251,8 +251,10 @@ enum {
   TILE_INERTIAL = 4,
   TILE_INTERP3 = 5,   // (u, v, w) at the particles
   TILE_INTERP12 = 6,  // (u, v, w) and the nine velocity gradients
-  TILE_RK2_FWD_SAVE = 7  // the Heun step from values and gradients at both
-                         // stage points, keeping u0 and the gradients
+  TILE_RK2_FWD_SAVE = 7,  // the Heun step from values and gradients at both
+                          // stage points, keeping u0 and the gradients
+  TILE_RK2_FWD_GRAD12 = 8  // the Heun step, writing also (u, v, w) and the
+                           // nine gradients at x_n
 };
 
 __device__ __forceinline__ int gslot(int P) { return (P + kGRing) % kGRing; }
@@ -375,11 +377,13 @@ __device__ __forceinline__ void flush_pend(const TileArgs& a, Pend* o, DeferBatc
   if (o->off >= 0) {
     if (MODE == TILE_INTERP3) {
       a.out[(int64_t)(lane64 & 3) * np + o->off] = o->f0;
-    } else if (MODE == TILE_INTERP12) {
-      const int64_t r = 3 * (lane64 & 3);
+    } else if (MODE == TILE_INTERP12 || MODE == TILE_RK2_FWD_GRAD12) {
+      const int q = lane64 & 3;
+      const int64_t r = 3 * q;
       a.out[r * np + o->off] = o->f0;
       a.out[(r + 1) * np + o->off] = o->f1;
       a.out[(r + 2) * np + o->off] = o->f2;
+      if (MODE == TILE_RK2_FWD_GRAD12 && q < 3) a.x_out[q * np + o->off] = o->d;
     } else if (MODE == TILE_RK2_FWD_SAVE) {
       const int q = lane64 & 3;
       const int64_t p = o->off;
@@ -524,6 +528,25 @@ __device__ __forceinline__ void ring_particle(const TileArgs& a, const uint32_t*
       o->off = lane * np + p;
       o->d = x0 + h * ((double)ua + (double)ub);
     }
+  } else if (MODE == TILE_RK2_FWD_GRAD12) {
+    // values and gradients at x_n (written out, rows as TILE_INTERP12),
+    // values at x*
+    float on[12], os[12];
+    eval_ring<CT, true>(ring, g, qn, X0, Y0, lane, on);
+    const float onl = pick3(on, lane);
+    const Pt qs = locate_quad(ax, xnl + a.dt * (double)onl, X0, Y0, zz - 1, zz + kSlab, lerr);
+    if (!qs.in_ring) {
+      if (lane == 0) o->defer = d.p;
+      return;
+    }
+    eval_ring<CT, false>(ring, g, qs, X0, Y0, lane, os);
+    const float ua = lane == 0 ? on[0] : lane == 1 ? on[1] : on[2];
+    const float ub = lane == 0 ? os[0] : lane == 1 ? os[1] : os[2];
+    o->off = p;
+    o->d = xnl + 0.5 * a.dt * ((double)ua + (double)ub);
+    o->f0 = lane == 0 ? on[0] : lane == 1 ? on[3] : lane == 2 ? on[6] : on[9];
+    o->f1 = lane == 0 ? on[1] : lane == 1 ? on[4] : lane == 2 ? on[7] : on[10];
+    o->f2 = lane == 0 ? on[2] : lane == 1 ? on[5] : lane == 2 ? on[8] : on[11];
   } else if (MODE == TILE_RK2_FWD_SAVE) {
     float on[12], os[12];
     eval_ring<CT, true>(ring, g, qn, X0, Y0, lane, on);
@@ -887,6 +910,16 @@ __global__ __launch_bounds__(256) void gather_deferred(TileArgs a) {
           a.vel_out[c * np + p] =
               (float)inertial_velocity(a.ik, vn[c], (double)u0[c], (double)u1[c]);
       }
+    } else if (MODE == TILE_RK2_FWD_GRAD12) {
+      float on[12], os[12];
+      eval_global<CT, true>(coeff, g, qn, on);
+      double xs[3];
+      for (int c = 0; c < 3; ++c) xs[c] = xn[c] + a.dt * (double)on[c];
+      const Pt qs = locate_pt<0>(g, xs, 0, 0, 0, -1, a.err);
+      eval_global<CT, false>(coeff, g, qs, os);
+      for (int c = 0; c < 3; ++c)
+        a.x_out[c * np + p] = xn[c] + 0.5 * a.dt * ((double)on[c] + (double)os[c]);
+      for (int r = 0; r < 12; ++r) a.out[r * np + p] = on[r];
     } else if (MODE == TILE_RK2_FWD_SAVE) {
       float on[12], os[12];
       eval_global<CT, true>(coeff, g, qn, on);
@@ -1925,6 +1958,7 @@ static const char* gather_name(int mode) {
     case TILE_INTERP3: return "tile_interp";
     case TILE_INTERP12: return "tile_interp_grad";
     case TILE_RK2_FWD_SAVE: return "tile_rk2_fwd_save";
+    case TILE_RK2_FWD_GRAD12: return "tile_rk2_fwd_grad";
     default: return "tile_tv_stage2";
   }
 }
@@ -1973,6 +2007,7 @@ static pt_status launch_gather(const pt_grid* g, TileArgs a, pt_dtype dtype, int
       case TILE_INTERP3: PT_TG(CT, TILE_INTERP3); break; \
       case TILE_INTERP12: PT_TG(CT, TILE_INTERP12); break; \
       case TILE_RK2_FWD_SAVE: PT_TG(CT, TILE_RK2_FWD_SAVE); break; \
+      case TILE_RK2_FWD_GRAD12: PT_TG(CT, TILE_RK2_FWD_GRAD12); break; \
       default: PT_TG(CT, TILE_TV_STAGE2); break;          \
     }                                                     \
   } while (0)
@@ -2009,6 +2044,20 @@ pt_status tile_rk2_fwd_save(const pt_grid* g, const void* coeff, pt_dtype dtype,
   a.x_out = x_out;
   a.saved = saved;
   return launch_gather(g, a, dtype, TILE_RK2_FWD_SAVE, defer, items_ws, check, s);
+}
+
+// The same step writing also (u, v, w) and the nine velocity gradients at x
+// to out ([12][np] floats, rows as tile_interp with nout = 12).  x_out may
+// alias x.
+pt_status tile_rk2_fwd_grad(const pt_grid* g, const void* coeff, pt_dtype dtype,
+                            const int32_t* ls, int64_t np, double dt, const double* x,
+                            double* x_out, float* out, void* defer, void* items_ws, bool check,
+                            hipStream_t s) {
+  TileArgs a = tile_args(g, coeff, ls, np, dt, kGatherSeg);
+  a.x = x;
+  a.x_out = x_out;
+  a.out = out;
+  return launch_gather(g, a, dtype, TILE_RK2_FWD_GRAD12, defer, items_ws, check, s);
 }
 
 // Inertial / diffusive step on sorted particles x (table ls, checked on the

@@ -163,7 +163,8 @@ def test_step_out_arguments(b):
 
 
 def test_saved_step_arguments(b):
-    """pt_rk2_step_save / pt_rk2_step_bwd_saved: FP64 coefficients (no tiled
+    """pt_rk2_step_save / pt_rk2_step_grad / pt_rk2_step_bwd_saved: FP64
+    coefficients (no tiled
     form), saved overlapping a position array, null buffers, short
     workspaces and too many particles are refused before any launch; no
     particles is a no-op."""
@@ -184,6 +185,16 @@ def test_saved_step_arguments(b):
              None) == b.PT_ERR_WORKSPACE
     assert f(ctypes.byref(g), fake, 0, 1 << 30, 0.1, fake, fake, vp(1 << 45), fake, 1 << 62,
              None) == b.PT_ERR_UNSUPPORTED
+    assert f(ctypes.byref(g), fake, 0, 0, 0.1, None, None, None, None, 0, None) == b.PT_OK
+    f = L.pt_rk2_step_grad
+    assert f(ctypes.byref(g), fake, b.PT_F64, 10, 0.1, fake, other, vp(0x20000000), fake,
+             1 << 40, None) == b.PT_ERR_UNSUPPORTED
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, other, None, fake, 1 << 40,
+             None) == b.PT_ERR_NULL
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, other, near, fake, 1 << 40,
+             None) == b.PT_ERR_ARG
+    assert f(ctypes.byref(g), fake, 0, 10, 0.1, fake, other, vp(0x20000000), fake, 8,
+             None) == b.PT_ERR_WORKSPACE
     assert f(ctypes.byref(g), fake, 0, 0, 0.1, None, None, None, None, 0, None) == b.PT_OK
     h = L.pt_rk2_step_bwd_saved
     assert h(ctypes.byref(g), 10, 0.1, fake, None, fake, None, fake, 1 << 40, None) == b.PT_ERR_NULL

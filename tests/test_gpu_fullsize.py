@@ -26,8 +26,9 @@ full with the plain oracle.
   2048^3, 256M uniform particles (64-bit sort keys): sort, the 12-output
     gather on the sorted particles (FP32, and BF16-stored coefficients at the
     same points) and one sorted Heun step, sampled; the saved-gradient step
-    (the c5 benchmark's fused gather + step) against both on every particle
-    and against the oracle on samples; and one
+    and the step that returns the 12 outputs (the c5 benchmark's fused
+    gather + step) against both on every particle and against the oracle on
+    samples; and one
     device's 256-plane slab solve of the same field, sampled;
   256^3, 1M particles: L = sum |x(8)|^2 through TrackParticles (checkpoints
     every 2 steps) against the oracle's hand adjoint, all outputs, and
@@ -508,13 +509,30 @@ def test_c5_2048_sampled(pt):
     assert e_v < 1e-6 and e_g < F32_TOL
     got_s = saved[:12, inv[sample].long()].double().cpu().numpy()
     fin_s = x1[:, inv[sample].long()].cpu().numpy()
-    del ps, perm, out12, inv, saved, x1
+    del saved
+    # the step that returns the 12 outputs at x_n (the c5 benchmark's step)
+    o12 = torch.empty((12, np_), dtype=torch.float32, device=dev)
+    B.pt_rk2_step_grad(g, coeff, dt, ps, x1, o12,
+                       pt.workspace(B.PT_OP_RK2, g, np_, torch.float32, dev))
+    assert pt.last_device_error() == 0
+    e_v = max(max_abs(o12[r] - out12[r]) / max_abs(out12[r]) for r in range(3))
+    e_g = (max(max_abs(o12[r] - out12[r]) for r in range(3, 12))
+           / max(max_abs(out12[r]) for r in range(3, 12)))
+    log(f"c5: step-with-gradients outputs against the 12-output gather, every particle: "
+        f"values {e_v:.3e}, gradients {e_g:.3e}")
+    assert e_v < 1e-6 and e_g < F32_TOL
+    got_g = o12[:, inv[sample].long()].double().cpu().numpy()
+    fin_g = x1[:, inv[sample].long()].cpu().numpy()
+    del ps, perm, out12, inv, x1, o12
     torch.cuda.empty_cache()
     err = normwise(got, ref12)
     log(f"c5 f32: tiled 12-output gather error (128 particles) {err:.3e}")
     assert err < F32_TOL
     err = normwise(got_s, ref12)
     log(f"c5 f32: 12 outputs kept by the saved-gradient step (128 particles) {err:.3e}")
+    assert err < F32_TOL
+    err = normwise(got_g, ref12)
+    log(f"c5 f32: 12 outputs of the step with gradients (128 particles) {err:.3e}")
     assert err < F32_TOL
     log("c5: sorted 12-output gather ok")
     ids = torch.arange(np_, dtype=torch.int32, device=dev)
@@ -527,6 +545,9 @@ def test_c5_2048_sampled(pt):
     assert err < F32_TOL
     err = normwise(fin_s - pos0, ref - pos0)
     log(f"c5: saved-gradient step displacement error {err:.3e}")
+    assert err < F32_TOL
+    err = normwise(fin_g - pos0, ref - pos0)
+    log(f"c5: step-with-gradients displacement error {err:.3e}")
     assert err < F32_TOL
     del pos, ids, coeff
     torch.cuda.empty_cache()

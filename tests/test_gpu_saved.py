@@ -142,3 +142,35 @@ def test_saved_adjoint_without_coefficient_gradient(pt):
     lam_ref, _ = oracle.rk2_step_bwd(og, ref_coeff, pos_s, dt, lam, np.zeros_like(ref_coeff))
     assert normwise(host(gp), lam_ref) < F32_TOL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("shape,np_,clustered,cfl", CASES)
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_step_with_gradients_parity(pt, shape, np_, clustered, cfl, dtype):
+    """pt_rk2_step_grad: the step and the 12 outputs at x_n from one pass,
+    against the oracle, and against pt_interp_sorted (nout = 12) and
+    pt_rk2_step_out on the device."""
+    import torch
+    from paper_2005_13193_amd import _binding as B
+    g, og, coeff, ref_coeff, pos_s, dt = _case(pt, shape, np_, clustered, cfl, dtype)
+    ps = dev(pos_s)
+    out = torch.empty_like(ps)
+    o12 = torch.empty((12, np_), dtype=torch.float32, device="cuda")
+    B.pt_rk2_step_grad(g, coeff, dt, ps, out, o12, pt.workspace(B.PT_OP_RK2, g, np_, coeff.dtype))
+    assert pt.last_device_error() == 0
+    ref = oracle.rk2_step(og, ref_coeff, pos_s, dt)
+    assert normwise(host(out) - pos_s, ref - pos_s) < F32_TOL
+    at_n = oracle.interp(og, ref_coeff, pos_s, n_out=12)
+    got = host(o12)
+    assert normwise(got[:3], at_n[:3]) < F32_TOL
+    assert grad_normwise(got[3:], at_n[3:]) < F32_TOL
+    # the same values as the separate gather and step (particles whose
+    # predictor left the ring take the 12 outputs from the global-memory
+    # path, summed in another order: gradients to FP32 rounding of |S| / h)
+    i12 = host(pt.interp_sorted(g, coeff, ps, nout=12))
+    assert normwise(got[:3], i12[:3]) < 1e-6
+    assert grad_normwise(got[3:], i12[3:]) < F32_TOL
+    out2 = torch.empty_like(ps)
+    B.pt_rk2_step_out(g, coeff, dt, ps, out2, B.PT_SORTED,
+                      pt.workspace(B.PT_OP_RK2, g, np_, coeff.dtype))
+    assert normwise(host(out) - pos_s, host(out2) - pos_s) < 1e-6
