@@ -174,3 +174,34 @@ def test_step_with_gradients_parity(pt, shape, np_, clustered, cfl, dtype):
     B.pt_rk2_step_out(g, coeff, dt, ps, out2, B.PT_SORTED,
                       pt.workspace(B.PT_OP_RK2, g, np_, coeff.dtype))
     assert normwise(host(out) - pos_s, host(out2) - pos_s) < 1e-6
+
+
+def test_saved_path_with_positions_out_of_cell_order(pt):
+    """Positions not in cell order: the particle table fails its device check
+    and every particle and stencil goes through the global-memory paths, with
+    the same results (as for PT_SORTED with unsorted positions)."""
+    import torch
+    from paper_2005_13193_amd import _binding as B
+    g, og, coeff, ref_coeff, pos_s, dt = _case(pt, (48, 40, 36), 6000, True, 1.0, "f32")
+    rng = np.random.default_rng(4)
+    pos_u = np.ascontiguousarray(pos_s[:, rng.permutation(pos_s.shape[1])])
+    pu = dev(pos_u)
+    np_ = pu.shape[1]
+    out, saved = _save(pt, g, coeff, pu, dt)
+    ref = oracle.rk2_step(og, ref_coeff, pos_u, dt)
+    assert normwise(host(out) - pos_u, ref - pos_u) < F32_TOL
+    o12 = torch.empty((12, np_), dtype=torch.float32, device="cuda")
+    out2 = torch.empty_like(pu)
+    B.pt_rk2_step_grad(g, coeff, dt, pu, out2, o12, pt.workspace(B.PT_OP_RK2, g, np_))
+    assert normwise(host(out2) - pos_u, ref - pos_u) < F32_TOL
+    at_n = oracle.interp(og, ref_coeff, pos_u, n_out=12)
+    assert normwise(host(o12)[:3], at_n[:3]) < F32_TOL
+    assert grad_normwise(host(o12)[3:], at_n[3:]) < F32_TOL
+    lam = rng.standard_normal((3, np_))
+    gco = torch.zeros(g.padded_shape, dtype=torch.float32, device="cuda")
+    gp = _bwd_saved(pt, g, pu, saved, dt, lam, gco)
+    lam_ref, gc_ref = oracle.rk2_step_bwd(og, ref_coeff, pos_u, dt, lam,
+                                          np.zeros_like(ref_coeff))
+    assert normwise(host(gp), lam_ref) < F32_TOL
+    assert normwise(host(gco).reshape(3, -1), gc_ref.reshape(3, -1)) < F32_TOL
+    assert pt.last_device_error() == 0
