@@ -4,9 +4,14 @@ SplineCoeffs   field -> padded coefficients   (backward: pt_spline_coeffs_bwd)
 InterpUVW      (coeff, pos) -> (u,v,w)         (backward: pt_interp_uvw_bwd)
 TrackParticles (field, pos0) -> positions after K Heun steps, with the
                coefficients built inside; backward re-runs the forward from
-               position checkpoints and applies pt_rk2_step_bwd step by step,
+               position checkpoints and applies the step adjoint step by step,
                then pt_spline_coeffs_bwd once (the field is frozen over the K
-               steps, so the coefficient gradient simply accumulates).
+               steps, so the coefficient gradient simply accumulates).  With
+               the cell sort and FP32 / BF16 coefficients the re-run sorts
+               each step (pt_sort_particles) and keeps the velocity gradients
+               (pt_rk2_step_save), and the adjoint reads them
+               (pt_rk2_step_bwd_saved) instead of gathering them again;
+               otherwise pt_rk2_step_bwd gathers them.
 BF16 coefficient storage is treated as the identity in backward.
 """
 import torch
@@ -82,6 +87,33 @@ class TrackParticles(torch.autograd.Function):
         g = g_pos_out.to(torch.float64).contiguous().clone()
         g_coeff = torch.zeros(grid.padded_shape, dtype=torch.float32, device=dev)
         ws_f = workspace(_b.PT_OP_RK2, grid, np_, coeff.dtype, dev)
+        if int(sort) == _b.PT_SORT and coeff.dtype in (torch.float32, torch.bfloat16):
+            # each forward step sorted its input, then stepped in that order
+            ws_s = workspace(_b.PT_OP_SORT, grid, np_, coeff.dtype, dev)
+            ws_b = workspace(_b.PT_OP_RK2_BWD, grid, np_, torch.float32, dev)
+            for seg in range(len(ctx.ckpts) - 1, -1, -1):
+                k0 = seg * every
+                k1 = min(k0 + every, steps)
+                x = ctx.ckpts[seg]
+                recs = []
+                for _ in range(k0, k1):  # the segment's steps again, as the forward ran them
+                    ps = torch.empty_like(x)
+                    perm = torch.empty(np_, dtype=torch.int32, device=dev)
+                    _b.pt_sort_particles(grid, x, ps, perm, None, None, ws_s)
+                    xo = torch.empty_like(x)
+                    saved = torch.empty((21, np_), dtype=torch.float32, device=dev)
+                    _b.pt_rk2_step_save(grid, coeff, dt, ps, xo, saved, ws_f)
+                    recs.append((ps, perm, saved))
+                    x = xo
+                for ps, perm, saved in reversed(recs):
+                    # g: dL/d(step output) in the step's (sorted) order
+                    _b.pt_rk2_step_bwd_saved(grid, dt, ps, saved, g, g_coeff, ws_b)
+                    gi = torch.empty_like(g)
+                    gi[:, perm.long()] = g  # sorted slot i held input particle perm[i]
+                    g = gi
+            g_field = spline_coeffs_bwd(grid, g_coeff) if ctx.needs_input_grad[0] else None
+            g_pos0 = g if ctx.needs_input_grad[1] else None
+            return g_field, g_pos0, None, None, None, None, None, None
         ws_b = workspace(_b.PT_OP_RK2_BWD, grid, np_, coeff.dtype, dev)
         for seg in range(len(ctx.ckpts) - 1, -1, -1):
             k0 = seg * every
