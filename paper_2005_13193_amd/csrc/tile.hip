@@ -1892,6 +1892,56 @@ struct ItemSet {
   int64_t bound;
 };
 
+// Scatter items of each launch (colour) and XCD range, the segments that
+// next_item deals from, reordered by decreasing estimated cost, particles +
+// 32 x layers (a layer's flush and barriers cost about what 32 particles
+// cost): the workgroups of an XCD take the long items first and the short
+// ones fill in at the end, which shortens the wait for the last workgroup of
+// a launch.  The items of one launch are disjoint, so their order changes no
+// result.  Segments longer than kOrderMax keep the order they were built in.
+constexpr int kOrderMax = 3072;
+constexpr int kOrderBins = 32;
+__global__ __launch_bounds__(256) void order_items(int4* __restrict__ items,
+                                                   const int* __restrict__ range,
+                                                   const int32_t* __restrict__ ls, int nz,
+                                                   int cost_max) {
+  __shared__ int4 s_it[kOrderMax];
+  __shared__ unsigned char s_bin[kOrderMax];
+  __shared__ int s_cnt[kOrderBins];
+  const int c = blockIdx.x >> 3, x = blockIdx.x & 7;
+  const int begin = range[c], n = range[c + 1] - begin;
+  const int per = (n + 7) / 8;
+  const int lo = x * per, hi = min(n, lo + per), len = hi - lo;
+  if (len <= 1 || len > kOrderMax) return;  // uniform over the block
+  if (threadIdx.x < kOrderBins) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int4* seg = items + begin + lo;
+  for (int i = threadIdx.x; i < len; i += 256) {
+    const int4 it = seg[i];  // (column, half, z0, z1)
+    s_it[i] = it;
+    // particles of the half-column over layers z0 .. z1-1: entry 2 z + half
+    // of the column's table starts half `half` of layer z
+    const int32_t* L = ls + 2 * (int64_t)it.x * nz + it.y;
+    int64_t p = 0;
+    for (int z = it.z; z < it.w; ++z) p += L[2 * z + 1] - L[2 * z];
+    const int64_t cost = p + 32 * (int64_t)(it.w - it.z);
+    const int b = (int)min<int64_t>(kOrderBins - 1, cost * kOrderBins / cost_max);
+    s_bin[i] = (unsigned char)(kOrderBins - 1 - b);  // the costliest first
+    atomicAdd(&s_cnt[kOrderBins - 1 - b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int b = 0; b < kOrderBins; ++b) {
+      const int t = s_cnt[b];
+      s_cnt[b] = o;
+      o += t;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < len; i += 256) seg[atomicAdd(&s_cnt[s_bin[i]], 1)] = s_it[i];
+}
+
 __global__ void zero_ctr(int* p) {
   if (threadIdx.x < 64) p[threadIdx.x] = 0;
 }
@@ -1920,6 +1970,13 @@ static pt_status build_tile_items(const pt_grid* g, int64_t np, const int32_t* h
   hipLaunchKernelGGL(build_items<true>, dim3(blocks), dim3(256), 0, s, hs, nunits, g->nz, ncx,
                      cfg, offsets, items, bound);
   PT_LAUNCH_CHECK();
+  if (scatter) {
+    // the gather keeps its order: neighbouring columns of one XCD share halo
+    // lines in its L2 when they run together
+    hipLaunchKernelGGL(order_items, dim3(8 * ncolors), dim3(256), 0, s, items, range, hs, g->nz,
+                       kItemPmax + 32 * lmax);
+    PT_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(zero_ctr, dim3(1), dim3(64), 0, s, ctr);
   PT_LAUNCH_CHECK();
   out->items = items;
